@@ -1,0 +1,289 @@
+"""Pins for the FP64 alignment oracle (CPU only).
+
+Each test ties the oracle to something other than itself: a library SVD
+with the determinant test of Algorithm 1, brute force over every start index
+and a fine angle grid, the paper's FFT formulation of Eq. A-mtx (the fast
+method gives exactly the slow method's alignment errors, section 2
+experiments), closed forms and invariants.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import resample_ref as rr
+from synth import curves
+
+
+def random_curve(rng, n, K=8, A=0.15):
+    """A smooth random closed curve sampled at n uniform parameters (test-only)."""
+    t = np.arange(n) * (2 * np.pi / n)
+    k = np.arange(1, K + 1)
+    a = rng.normal(size=K) * (A / k)
+    phi = rng.uniform(0, 2 * np.pi, size=K)
+    r = 1.0 + (a[:, None] * np.cos(np.outer(k, t) + phi[:, None])).sum(0)
+    z = r * np.exp(1j * t)
+    return z - z.mean()
+
+
+def R_paper(theta):
+    """Rotation of section 2: R(theta) = [[cos, sin], [-sin, cos]]."""
+    c, s = math.cos(theta), math.sin(theta)
+    return np.array([[c, s], [-s, c]])
+
+
+def kabsch_svd(A):
+    """Algorithm 1 with a library SVD: R = U S~ V^T, S~ = diag(1, +-1)."""
+    U, S, Vt = np.linalg.svd(A)
+    d = np.linalg.det(U) * np.linalg.det(Vt.T)
+    St = np.diag([1.0, 1.0 if d > 0 else -1.0])
+    return U @ St @ Vt
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_closed_form_equals_algorithm1_svd(seed):
+    rng = np.random.default_rng(seed)
+    n = 48
+    z1 = random_curve(rng, n)
+    z2 = random_curve(rng, n) if seed % 2 else np.exp(0.7j) * np.roll(z1, 5) + 0.05 * rng.normal(size=n)
+    T, H = oracle.shift_scores(z1, z2)
+    for m in rng.integers(0, n, size=8):
+        A = oracle.a_matrix(z1, z2, m)
+        R = kabsch_svd(A)
+        assert abs(np.linalg.det(R) - 1.0) < 1e-12
+        # same optimal value of tr(R A^T)
+        assert abs(np.trace(R @ A.T) - T[m]) <= 1e-12 * max(1.0, abs(T[m]))
+        # same rotation: the oracle's angle reproduces the SVD rotation
+        assert np.allclose(R_paper(H[m]), R, atol=1e-10)
+        # singular values: tr max = s1 + sgn(det A) s2
+        s = np.linalg.svd(A, compute_uv=False)
+        assert abs(s[0] + np.sign(np.linalg.det(A)) * s[1] - T[m]) < 1e-12 * max(1.0, T[m])
+
+
+def test_reflection_case_keeps_a_rotation():
+    """det(U) det(V) < 0 branch of Algorithm 1: still a proper rotation."""
+    A = np.array([[0.3, 0.1], [0.2, -0.5]])     # det A < 0
+    R = kabsch_svd(A)
+    c, s = A[0, 0] + A[1, 1], A[0, 1] - A[1, 0]
+    th = math.atan2(s, c)
+    assert np.allclose(R, R_paper(th), atol=1e-12)
+    assert abs(np.trace(R @ A.T) - math.hypot(c, s)) < 1e-12
+
+
+def energy_numpy(z1, z2, m, theta):
+    """Eq. disc-energy written with complex numbers (test-side brute force)."""
+    n = len(z1)
+    w = np.exp(-1j * theta) * np.roll(z2, -m)      # R(theta) beta2^{l (+) m}
+    return float(np.sum(np.abs(z1 - w) ** 2) / n)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_brute_force_over_shifts_and_angle_grid(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = 16 + 4 * seed
+    z1 = random_curve(rng, n)
+    z2 = np.exp(1j * rng.uniform(0, 6.28)) * np.roll(random_curve(rng, n) * 0.3 + z1, 3)
+    grid = np.linspace(-np.pi, np.pi, 1 << 16, endpoint=False)
+    best = (np.inf, None, None)
+    for m in range(n):
+        w = np.roll(z2, -m)
+        # E(theta) = n1 + n2 - (2/n) Re(e^{-i theta} sum conj(z1) w), evaluated on the grid
+        d = np.sum(np.conj(z1) * w)
+        E = np.mean(np.abs(z1) ** 2) + np.mean(np.abs(w) ** 2) - 2.0 / n * np.real(np.exp(-1j * grid) * d)
+        k = int(np.argmin(E))
+        # golden-section refinement around the grid minimum on the direct energy
+        a, b = grid[k] - 2e-4, grid[k] + 2e-4
+        g = (math.sqrt(5) - 1) / 2
+        for _ in range(80):
+            c1, c2 = b - g * (b - a), a + g * (b - a)
+            if energy_numpy(z1, z2, m, c1) < energy_numpy(z1, z2, m, c2):
+                b = c2
+            else:
+                a = c1
+        th = 0.5 * (a + b)
+        e = energy_numpy(z1, z2, m, th)
+        if e < best[0]:
+            best = (e, m, th)
+    res = oracle.align_pair(z1, z2)
+    assert res["m"] == best[1]
+    assert abs(oracle.wrap_angle(res["theta_paper"] - best[2])) < 1e-7
+    assert abs(res["E"] - best[0]) <= 1e-12 + 1e-10 * best[0]
+
+
+@pytest.mark.parametrize("n", [17, 64, 100])
+def test_fft_formulation_of_a_matrix(n):
+    """Convolution-theorem form of Eq. A-mtx: with the reversed curve
+    beta~1^l = beta1^{(-l) mod n}, IDFT(DFT(beta~1k) . DFT(beta2j))[m] = A_kj(t_m)."""
+    rng = np.random.default_rng(n)
+    z1, z2 = random_curve(rng, n), random_curve(rng, n)
+    b1 = np.stack([z1.real, z1.imag])
+    b2 = np.stack([z2.real, z2.imag])
+    rev = (-np.arange(n)) % n
+    for k in range(2):
+        for j in range(2):
+            conv = np.fft.ifft(np.fft.fft(b1[k][rev]) * np.fft.fft(b2[j])).real
+            for m in range(n):
+                A = oracle.a_matrix(z1, z2, m)
+                assert abs(conv[m] - A[k, j]) < 1e-12
+
+
+def test_fast_method_reaches_the_same_alignment_error():
+    """Algorithm 2 in FP64 numpy (12 FFTs, then Kabsch by SVD per start index)
+    returns the same (t0, R) and the same error as the slow method."""
+    rng = np.random.default_rng(7)
+    for n in (64, 128, 256):
+        z1 = random_curve(rng, n)
+        z2 = np.exp(2.1j) * np.roll(z1, n // 4) + 0.01 * (rng.normal(size=n) + 1j * rng.normal(size=n))
+        b1 = np.stack([z1.real, z1.imag])
+        b2 = np.stack([z2.real, z2.imag])
+        rev = (-np.arange(n)) % n
+        A = np.empty((n, 2, 2))
+        for k in range(2):
+            for j in range(2):
+                A[:, k, j] = np.fft.ifft(np.fft.fft(b1[k][rev]) * np.fft.fft(b2[j])).real
+        tr = np.empty(n)
+        Rs = []
+        for m in range(n):
+            R = kabsch_svd(A[m])
+            Rs.append(R)
+            tr[m] = np.trace(R @ A[m].T)
+        m_fast = int(np.argmax(tr))
+        th_fast = math.atan2(Rs[m_fast][0, 1], Rs[m_fast][0, 0])
+        res = oracle.align_pair(z1, z2)
+        assert res["m"] == m_fast
+        assert abs(oracle.wrap_angle(res["theta_paper"] - th_fast)) < 1e-12
+        assert abs(oracle.energy(z1, z2, m_fast, th_fast) - res["E"]) < 1e-14
+
+
+@pytest.mark.parametrize("n,s0,theta0", [(64, 17, 1.1), (100, 3, -2.5), (256, 200, 0.3), (33, 1, 3.0)])
+def test_rotated_shifted_exact_copy(n, s0, theta0):
+    """z2[j] = e^{i theta0} z1[(j + s0) mod n]: start index m = n - s0, the
+    clockwise angle undoes theta0, zero energy; library convention (s0, -theta0)."""
+    rng = np.random.default_rng(n + s0)
+    z1 = random_curve(rng, n)
+    z2 = np.exp(1j * theta0) * np.roll(z1, -s0)
+    res = oracle.align_pair(z1, z2)
+    assert res["m"] == (n - s0) % n
+    assert abs(oracle.wrap_angle(res["theta_paper"] - theta0)) < 1e-12
+    assert res["E"] < 1e-28 + 1e-14 * res["n1"]
+    s, th = oracle.to_library_convention(res["m"], res["theta_paper"], n)
+    assert s == s0 and abs(oracle.wrap_angle(th + theta0)) < 1e-12
+
+
+def test_paper_validation_protocol():
+    """Template = reference with its start moved from 0 to 0.25 and rotated by
+    pi/3 (experiments of section 2).  Found: t0 = 0.75 and the clockwise pi/3
+    that undoes the rotation, zero energy."""
+    rng = np.random.default_rng(3)
+    for n in (64, 256, 1024):
+        z1 = random_curve(rng, n)
+        z2 = np.exp(1j * np.pi / 3) * np.roll(z1, -(n // 4))
+        res = oracle.align_pair(z1, z2)
+        assert res["m"] / n == 0.75
+        assert abs(res["theta_paper"] - np.pi / 3) < 1e-12
+        assert res["E"] < 1e-14 * res["n1"]
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_swap_symmetry(seed):
+    rng = np.random.default_rng(50 + seed)
+    n = 96
+    z1, z2 = random_curve(rng, n), random_curve(rng, n)
+    a, b = oracle.align_pair(z1, z2), oracle.align_pair(z2, z1)
+    assert b["m"] == (n - a["m"]) % n
+    assert abs(oracle.wrap_angle(a["theta_paper"] + b["theta_paper"])) < 1e-12
+    assert abs(a["E"] - b["E"]) < 1e-14
+
+
+def test_energy_expansion_and_bounds():
+    """E^h = ||b1||^2 + ||b2||^2 - 2 tr(RA^T)/n (rewrite of Eq. disc-energy0),
+    0 <= E <= n1 + n2, and the optimum is below the energy at random (m, theta)."""
+    rng = np.random.default_rng(11)
+    n = 80
+    z1, z2 = random_curve(rng, n), random_curve(rng, n) * 0.7
+    res = oracle.align_pair(z1, z2)
+    assert abs(res["E"] - (res["n1"] + res["n2"] - 2 * res["T"] / n)) < 1e-14
+    assert 0.0 <= res["E"] <= res["n1"] + res["n2"]
+    for _ in range(50):
+        m, th = int(rng.integers(0, n)), rng.uniform(-np.pi, np.pi)
+        assert oracle.energy(z1, z2, m, th) >= res["E"] - 1e-15
+
+
+def test_scale_invariance():
+    rng = np.random.default_rng(12)
+    n = 64
+    z1, z2 = random_curve(rng, n), random_curve(rng, n)
+    a = oracle.align_pair(z1, z2)
+    b = oracle.align_pair(3.0 * z1, 3.0 * z2)
+    assert a["m"] == b["m"]
+    assert abs(a["theta_paper"] - b["theta_paper"]) < 1e-12
+    assert abs(b["E"] - 9.0 * a["E"]) < 1e-12
+
+
+def test_circle_all_shifts_tie():
+    """For a circle every start index is optimal; the angle moves by 2 pi / n per index."""
+    n = 64
+    z = np.exp(2j * np.pi * np.arange(n) / n)
+    T, H = oracle.shift_scores(z, z)
+    assert np.ptp(T) < 1e-12
+    d = oracle.wrap_angle(np.diff(H))
+    assert np.allclose(d, 2 * np.pi / n, atol=1e-12)
+
+
+def test_k_fold_symmetry_gives_k_ties():
+    n, k = 120, 3
+    t = np.arange(n) * 2 * np.pi / n
+    z = (1 + 0.3 * np.cos(k * t)) * np.exp(1j * t)
+    T, _ = oracle.shift_scores(z, z)
+    top = np.sort(np.argsort(-T)[:k])
+    assert list(top) == [0, n // k, 2 * n // k]
+    assert np.ptp(T[top]) < 1e-12
+    rest = np.delete(T, top)
+    assert rest.max() < T[0] * (1 - 1e-4)
+
+
+def test_batch_matches_pairs():
+    rng = np.random.default_rng(5)
+    B, n = 6, 40
+    z1 = np.stack([random_curve(rng, n) for _ in range(B)]).astype(np.complex64)
+    z2 = np.stack([random_curve(rng, n) for _ in range(B)]).astype(np.complex64)
+    m, th, e, t, used = oracle.align_batch_f32(z1, z2, nthreads=2)
+    assert used >= 1
+    for p in range(B):
+        r = oracle.align_pair(z1[p].astype(np.complex128), z2[p].astype(np.complex128))
+        assert m[p] == r["m"] and th[p] == r["theta_paper"] and e[p] == r["E"]
+
+
+def test_resampling_needed_for_nonuniform_sampling():
+    """Analogue of the hippopede illustration: a copy of a curve sampled with
+    nodes crowded in one part aligns badly as raw nodes and well after
+    uniform arc-length resampling of both lists."""
+    n = 256
+    t1 = np.arange(n) * 2 * np.pi / n
+    u = np.arange(n) / n
+    t2 = 2 * np.pi * (u + 0.12 * np.sin(2 * np.pi * u) / (2 * np.pi) * 2)   # crowded nodes
+    shape = lambda t: (1 + 0.3 * np.cos(2 * t)) * np.exp(1j * t)        # noqa: E731
+    raw1 = shape(t1)
+    raw2 = np.exp(1j * np.pi / 3) * shape(t2 + 0.25 * 2 * np.pi)
+    to_xy = lambda z: np.stack([z.real, z.imag], 1)                      # noqa: E731
+    L1 = np.sum(np.abs(np.diff(np.append(raw1, raw1[0]))))
+    L2 = np.sum(np.abs(np.diff(np.append(raw2, raw2[0]))))
+    bad = oracle.align_pair((raw1 - raw1.mean()) / L1, (raw2 - raw2.mean()) / L2)
+    r1, _ = rr.resample(to_xy(raw1), n)
+    r2, _ = rr.resample(to_xy(raw2), n)
+    good = oracle.align_pair(r1, r2)
+    assert good["E"] < 1e-4 * good["n1"]
+    assert bad["E"] > 100 * good["E"]
+
+
+def test_generator_template_truth():
+    """single_pair's template is the raw curve rotated by theta0 and shifted by
+    s0 vertices; aligning the raw vertex lists (no resampling) recovers both."""
+    raw1, raw2, truth = curves.single_pair(4242, n_raw=200, sigma=0.0)
+    z1 = raw1[:, 0].astype(np.float64) + 1j * raw1[:, 1]
+    z2 = raw2[:, 0].astype(np.float64) + 1j * raw2[:, 1]
+    res = oracle.align_pair(z1 - z1.mean(), z2 - z2.mean())
+    s, th = oracle.to_library_convention(res["m"], res["theta_paper"], 200)
+    assert s == truth["s0"]
+    assert abs(oracle.wrap_angle(th + truth["theta0"])) < 1e-6
