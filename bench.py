@@ -1,0 +1,155 @@
+#!/usr/bin/env python3
+"""Throughput of the MI355X closed-curve alignment path.
+
+Default workload: 65,536 independent pairs of closed curves with n = 1024
+uniform arc-length nodes each, FP32, one call of align_batch per step (norms,
+two forward FFTs, spectrum product, correlation FFT, argmax, FP64 re-scoring,
+theta and e0 for every pair).  Inputs are seeded synthetic star curves; the
+raw polygons are resampled to uniform arc length on the GPU before timing
+(untimed) and stay resident in HBM.
+
+Prints ONE JSON line (rank 0).  Other workloads: --config {pair,batch,allpairs,
+ragged,bf16}; only the default line is the headline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+RESULT_BYTES = 24
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="batch",
+                    choices=["batch", "pair", "allpairs", "ragged", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="target wall time of the CPU oracle sample")
+    return ap.parse_args()
+
+
+def sources_digest(names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2501_17779_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel_key: str, digest: str, per_launch_units: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    e = d.get(kernel_key)
+    if not e or e.get("sources") != digest:
+        return None
+    return float(e["bytes_per_unit"]) * per_launch_units
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(stop) / steps, wall
+
+
+def cpu_baseline_batch(raw1, raw2, n, seconds):
+    """The FP64 oracle (slow method, OpenMP over pairs) on a bounded sample of
+    the workload's pairs; the oracle's cost does not depend on the node values,
+    so the sample uses the raw n-vertex node lists of the first pairs."""
+    import oracle
+    z1 = (raw1[..., 0] + 1j * raw1[..., 1]).astype(np.complex64)
+    z2 = (raw2[..., 0] + 1j * raw2[..., 1]).astype(np.complex64)
+    probe = min(64, len(z1))
+    t0 = time.perf_counter()
+    _, _, _, _, used = oracle.align_batch_f32(z1[:probe], z2[:probe])
+    dt = time.perf_counter() - t0
+    k = int(min(len(z1), max(probe, probe * seconds / max(dt, 1e-6))))
+    t0 = time.perf_counter()
+    _, _, _, _, used = oracle.align_batch_f32(z1[:k], z2[:k])
+    dt = time.perf_counter() - t0
+    return {"value": k / dt, "unit": "pairs/s", "cores": int(used), "kind": "oracle",
+            "sample": f"first {k} of the workload's pairs (n={n}), FP64 slow method, "
+                      f"{dt:.1f} s wall on {used} threads"}
+
+
+def bench_batch(args, torch, ca):
+    from synth import curves
+    B, n = 65536, 1024
+    r1, r2 = curves.batch_pairs(17780, B, n)
+    dev = torch.device("cuda:0")
+    raw = torch.from_numpy(np.concatenate([r1, r2]).reshape(-1, 2)).to(dev)
+    raw = torch.view_as_complex(raw).contiguous()
+    roff = torch.arange(0, 2 * B + 1, dtype=torch.int64, device=dev) * n
+    nodes, _, flags = ca.resample_arclength(raw, roff, roff)
+    z1 = nodes[: B * n].view(B, n)
+    z2 = nodes[B * n:].view(B, n)
+    out = ca.empty_results(B, dev)
+    torch.cuda.synchronize()
+    assert int((flags != 0).sum().item()) == 0
+    ms, wall = time_steps(lambda: ca.align_batch(z1, z2, out=out), args.steps, args.warmup, torch)
+    algo_bytes = B * (2 * n * 8 + RESULT_BYTES)
+    achieved = algo_bytes / (ms * 1e-3) / 1e9
+    digest = sources_digest(["align.hip", "fft_engines.hpp", "dft_small.hpp", "common.hpp"])
+    traffic = traffic_for("k_align_team_1024", digest, B)
+    line = {
+        "metric": "curve-pair alignments/sec at N=1024, FP32 vs split-BF16, err vs FP64 oracle",
+        "value": B / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch of 65536 curve pairs, n=1024 nodes, FP32, top-2 FP64 re-scoring",
+                   "pairs": B, "n": n, "rescore": "top2"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_batch(r1, r2, n, args.cpu_seconds)
+    return line
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus "
+              f"{args.gpus}); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2501_17779_amd as ca
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    ca.default_context(0)
+    fn = {"batch": bench_batch}[args.config]
+    line = fn(args, torch, ca)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,182 @@
+/*
+ * curvealign.h -- C ABI of the MI355X (gfx950) closed-curve alignment library.
+ *
+ * The library computes, for pairs of closed planar curves given as n uniform
+ * arc-length nodes each, the optimal starting point and rotation of
+ * Dogan, Bernal and Hagwood, "FFT-based alignment of 2d closed curves with
+ * application to elastic shape analysis", section 2 (Algorithm 2), and the
+ * mismatch energy of Eq. (disc-energy) at that optimum.  It also provides the
+ * uniform arc-length resampling of section 2 (Eq. arc-length-param followed
+ * by cubic-spline interpolation) that turns raw vertex lists into such nodes.
+ *
+ * Curves are complex signals z[k] = x_k + i y_k.  For a pair (z1, z2) with n
+ * nodes the library evaluates the circular cross-correlation
+ *     C(s) = sum_k z1[k] conj(z2[(k - s) mod n]),   s = 0..n-1,
+ * (the FFT route: C = IFFT(FFT(z1) . conj(FFT(z2)))) and returns
+ *     shift  = argmax_s |C(s)|            (smallest s among exact ties)
+ *     theta  = arg C(shift)               (counter-clockwise rotation applied to z2)
+ *     e0     = n1 + n2 - 2 |C(shift)| / n,  n_i = (1/n) sum_k |z_i[k]|^2.
+ * In the paper's notation (start index m, t0 = m/n, clockwise R(theta)) the
+ * same optimum reads m = (n - shift) mod n and theta_paper = -theta; e0 is
+ * E^h(t0, R) of Eq. (disc-energy) with h = 1/n.  |C(s)| is the value of
+ * tr(R A^T) maximised over R for A = A(t_m) of Eq. (A-mtx).
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers (hipMalloc'ed or torch CUDA
+ *     tensors) owned by the caller, unless stated otherwise.  The library
+ *     never frees or retains them.
+ *   - Complex arrays are interleaved: float pairs (complex64) for the FP32 and
+ *     split-BF16 precisions, double pairs (complex128) for FP64.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Every call is stream-ordered and asynchronous: it validates arguments on
+ *     the host, enqueues kernels and returns.  Results are ready when the
+ *     stream is synchronised.
+ *   - Errors: a negative status means nothing was enqueued (argument errors are
+ *     detected synchronously on the host) or, for CA_ERR_HIP, that a HIP call
+ *     failed (ca_last_error() has the text).  Data conditions never fail a
+ *     call: they set per-result flags (CA_FLAG_*).
+ *   - A context is not thread-safe; use one per host thread.  Calls that
+ *     share a context must be issued to the same stream or be serialised
+ *     by the caller (they share the context's workspace).
+ */
+#ifndef CURVEALIGN_H
+#define CURVEALIGN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ca_status_t;
+enum {
+    CA_OK = 0,
+    CA_ERR_INVALID_ARG = -1,   /* null pointer, negative count, bad option value  */
+    CA_ERR_UNSUPPORTED_N = -2, /* n outside the supported set (see align_batch)   */
+    CA_ERR_HIP = -3,           /* a HIP runtime call failed; see ca_last_error()  */
+    CA_ERR_OOM = -4,           /* workspace allocation failed                    */
+    CA_ERR_NO_DEVICE = -5,     /* no gfx950 device at the requested index        */
+    CA_ERR_INTERNAL = -6
+};
+
+/* Per-pair result: 24 bytes, 8-byte aligned. */
+typedef struct {
+    int32_t shift;    /* optimal correlation shift s* in [0, n)                     */
+    uint32_t flags;   /* CA_FLAG_* bits                                             */
+    float theta;      /* arg C(s*), radians in (-pi, pi]                            */
+    float err_est;    /* relative half-width of the FP32 |C| error bound at s*      */
+    double e0;        /* n1 + n2 - 2|C(s*)|/n with |C(s*)| and n_i in FP64          */
+} ca_result_t;
+
+enum {
+    CA_FLAG_NEAR_TIE = 1u << 0,     /* best and runner-up |C| within 1e-6 relative   */
+    CA_FLAG_RESCORED = 1u << 1,     /* more than one shift was re-scored in FP64     */
+    CA_FLAG_CAND_CAPPED = 1u << 2,  /* candidate window exceeded its cap (32)        */
+    CA_FLAG_DEGENERATE = 1u << 3,   /* a curve has zero norm; shift 0, theta 0,
+                                       e0 = n1 + n2                                  */
+    CA_FLAG_NONFINITE = 1u << 4,    /* NaN/Inf in the input; shift 0, theta 0, e0 NaN */
+    CA_FLAG_THETA_FP64 = 1u << 5,   /* theta taken from the FP64 C(s*)               */
+    CA_FLAG_UNSUPPORTED_N = 1u << 6 /* ragged pair with an unsupported n; not aligned */
+};
+
+enum { CA_PREC_FP32 = 0, CA_PREC_SPLIT_BF16 = 1, CA_PREC_FP64 = 2 };
+
+/* Which shifts are re-scored with an FP64 dot product.  The FP64 value of
+ * C at the chosen shift is always computed (it enters e0).
+ *   TOP2   (default): the FP32 best and runner-up, when their |C| gap is below
+ *          twice the FP32 error bound.
+ *   WINDOW: every shift whose FP32 |C| lies within twice the error bound of
+ *          the maximum, at most 32 (CA_FLAG_CAND_CAPPED beyond; then TOP2).   */
+enum { CA_RESCORE_TOP2 = 0, CA_RESCORE_WINDOW = 1 };
+
+enum { CA_RESAMPLE_SPLINE = 0, CA_RESAMPLE_LINEAR = 1 };
+
+typedef struct {
+    int32_t precision;   /* CA_PREC_*                                         */
+    int32_t rescore;     /* CA_RESCORE_*                                      */
+    int32_t theta_fp64;  /* nonzero: theta from the FP64 C(s*)                */
+    int32_t reserved;    /* must be 0                                         */
+} ca_options_t;          /* NULL options pointer = {FP32, TOP2, 0, 0}         */
+
+typedef struct ca_context* ca_context_t;
+
+/* Create a context on HIP device `device` (must be gfx950).  The context owns
+ * twiddle tables, DFT matrices and workspace, all released by ca_destroy. */
+ca_status_t ca_create(ca_context_t* ctx, int device);
+ca_status_t ca_destroy(ca_context_t ctx);
+const char* ca_status_string(ca_status_t status);
+/* Text of the last error raised on this thread (empty if none). */
+const char* ca_last_error(void);
+
+/* Largest n accepted by align_* (uniform and ragged), and the predicate for
+ * a single n: 2 <= n <= CA_MAX_N and n has no prime factor above 7. */
+#define CA_MAX_N 4096
+int32_t ca_n_supported(int32_t n);
+
+/*
+ * align_pair -- Algorithm 2 for one pair (section 2).
+ *   z1, z2 : n nodes each (complex64, or complex128 when precision = FP64)
+ *   out    : one ca_result_t in device memory
+ * Same semantics as align_batch with num_pairs = 1.
+ */
+ca_status_t align_pair(ca_context_t ctx, const void* z1, const void* z2, int32_t n,
+                       ca_result_t* out, const ca_options_t* opt, void* stream);
+
+/*
+ * align_batch -- Algorithm 2 for many independent pairs.
+ *   Uniform batch (offsets == NULL): pair p uses z1 + p*n and z2 + p*n
+ *     (n nodes each); n must satisfy ca_n_supported, else CA_ERR_UNSUPPORTED_N.
+ *   Ragged batch (offsets != NULL): offsets is a device array of num_pairs+1
+ *     int64 node offsets, nondecreasing, offsets[0] = 0; pair p uses nodes
+ *     [offsets[p], offsets[p+1]) of both z1 and z2; `n` is ignored.  A pair
+ *     whose size is not supported gets CA_FLAG_UNSUPPORTED_N and is skipped.
+ *   out: num_pairs results in device memory (pair order).
+ *   precision SPLIT_BF16 requires a uniform batch with n == 128.
+ * num_pairs == 0 is a no-op.
+ */
+ca_status_t align_batch(ca_context_t ctx, const void* z1, const void* z2,
+                        const int64_t* offsets, int32_t n, int64_t num_pairs,
+                        ca_result_t* out, const ca_options_t* opt, void* stream);
+
+/*
+ * align_all_pairs -- every unordered pair (i, j), i < j, of a gallery of m
+ * curves with n nodes each (complex64, curve-contiguous [m][n]).  Per-curve
+ * spectra and norms are computed once.  Results are packed in row-major
+ * upper-triangle order: pair (i, j) is at k = i*m - i*(i+1)/2 + (j - i - 1),
+ * m*(m-1)/2 results in total.  FP32 precision only; n in {64,...,1024}
+ * powers of two or any supported n.
+ */
+ca_status_t align_all_pairs(ca_context_t ctx, const void* curves, int32_t m, int32_t n,
+                            ca_result_t* out_upper, const ca_options_t* opt, void* stream);
+
+/*
+ * resample_arclength -- uniform arc-length resampling (section 2, Eq.
+ * arc-length-param and the cubic-spline step after it).
+ *   raw         : raw vertices, complex64, all curves back to back
+ *   raw_offsets : int64 [num_curves+1] vertex offsets (device)
+ *   out_offsets : int64 [num_curves+1] node offsets (device); curve c gets
+ *                 out_offsets[c+1] - out_offsets[c] nodes (>= 2)
+ *   out         : complex64 nodes, centred on their mean and scaled by the
+ *                 reciprocal of the raw perimeter (unit length)
+ *   norms_out   : optional FP64 (1/n) sum |z|^2 per curve (NULL to skip)
+ *   flags_out   : optional uint32 per curve; CA_FLAG_DEGENERATE when fewer than
+ *                 3 distinct vertices remain or the perimeter is zero (nodes
+ *                 are then 0); CA_FLAG_NONFINITE for NaN/Inf vertices
+ *   mode        : CA_RESAMPLE_SPLINE (periodic C2 cubic spline through the
+ *                 arc-length knots) or CA_RESAMPLE_LINEAR
+ * Input rules: vertices are counter-clockwise and not closed; trailing copies
+ * of the first vertex and runs of consecutive duplicates are dropped.
+ * Raw curves may have at most 65536 vertices (CA_ERR_INVALID_ARG is not
+ * detectable on the host for device offsets: longer curves get
+ * CA_FLAG_UNSUPPORTED_N and zero nodes).
+ */
+ca_status_t resample_arclength(ca_context_t ctx, const void* raw, const int64_t* raw_offsets,
+                               int64_t num_curves, const int64_t* out_offsets, void* out,
+                               double* norms_out, uint32_t* flags_out, int32_t mode,
+                               void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CURVEALIGN_H */

@@ -1,0 +1,267 @@
+"""Python binding of libcurvealign (MI355X / gfx950 closed-curve alignment).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in include/curvealign.h.  Tensors are torch
+CUDA (HIP) tensors used as device memory; calls are enqueued on the current
+torch stream unless a stream is given.
+
+Result records (24 bytes each) are returned as a uint8 CUDA tensor of shape
+[count, 24]; `unpack` turns them into named tensors or `to_numpy` into a
+numpy structured array with fields shift, flags, theta, err_est, e0.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcurvealign.so")
+
+RESULT_DTYPE = np.dtype([("shift", "<i4"), ("flags", "<u4"), ("theta", "<f4"),
+                         ("err_est", "<f4"), ("e0", "<f8")])
+
+OK = 0
+ERR_INVALID_ARG = -1
+ERR_UNSUPPORTED_N = -2
+ERR_HIP = -3
+ERR_OOM = -4
+ERR_NO_DEVICE = -5
+
+FLAG_NEAR_TIE = 1 << 0
+FLAG_RESCORED = 1 << 1
+FLAG_CAND_CAPPED = 1 << 2
+FLAG_DEGENERATE = 1 << 3
+FLAG_NONFINITE = 1 << 4
+FLAG_THETA_FP64 = 1 << 5
+FLAG_UNSUPPORTED_N = 1 << 6
+
+PRECISION = {"fp32": 0, "split_bf16": 1, "fp64": 2}
+RESCORE = {"top2": 0, "window": 1}
+RESAMPLE = {"spline": 0, "linear": 1}
+MAX_N = 4096
+
+EXPORTED = ("ca_create", "ca_destroy", "ca_status_string", "ca_last_error", "ca_n_supported",
+            "align_pair", "align_batch", "align_all_pairs", "resample_arclength")
+
+
+class CurveAlignError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"curvealign status {status}: {msg}")
+        self.status = status
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("rescore", ctypes.c_int32),
+                ("theta_fp64", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    """Load libcurvealign.so (no fallback: a missing library is an error)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(f"{LIB_PATH} is missing; build it with "
+                                  "`python -c 'import __graft_entry__ as g; g.build()'`")
+            L = ctypes.CDLL(LIB_PATH)
+            vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+            L.ca_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+            L.ca_destroy.argtypes = [vp]
+            L.ca_status_string.argtypes = [i32]
+            L.ca_status_string.restype = ctypes.c_char_p
+            L.ca_last_error.argtypes = []
+            L.ca_last_error.restype = ctypes.c_char_p
+            L.ca_n_supported.argtypes = [i32]
+            L.ca_n_supported.restype = i32
+            L.align_pair.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+            L.align_batch.argtypes = [vp, vp, vp, vp, i32, i64, vp, vp, vp]
+            L.align_all_pairs.argtypes = [vp, vp, i32, i32, vp, vp, vp]
+            L.resample_arclength.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, i32, vp]
+            for name in ("ca_create", "ca_destroy", "align_pair", "align_batch",
+                         "align_all_pairs", "resample_arclength"):
+                getattr(L, name).restype = i32
+            _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != OK:
+        L = lib()
+        raise CurveAlignError(status, f"{L.ca_status_string(status).decode()}: "
+                                      f"{L.ca_last_error().decode()}")
+
+
+def n_supported(n: int) -> bool:
+    return bool(lib().ca_n_supported(int(n)))
+
+
+class Context:
+    """Owns the library context (plans, twiddle tables, workspace) on one device."""
+
+    def __init__(self, device: int = 0):
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        _check(lib().ca_create(ctypes.byref(h), self.device))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ca_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_contexts: dict[int, Context] = {}
+
+
+def default_context(device: int | None = None) -> Context:
+    import torch
+    dev = torch.cuda.current_device() if device is None else int(device)
+    if dev not in _contexts:
+        _contexts[dev] = Context(dev)
+    return _contexts[dev]
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _options(precision: str, rescore: str, theta_fp64: bool) -> _Options:
+    if precision not in PRECISION:
+        raise ValueError(f"precision must be one of {sorted(PRECISION)}")
+    if rescore not in RESCORE:
+        raise ValueError(f"rescore must be one of {sorted(RESCORE)}")
+    return _Options(PRECISION[precision], RESCORE[rescore], 1 if theta_fp64 else 0, 0)
+
+
+def _require(t, what, dtypes, ndim=None):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{what} must live on a GPU device")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{what} must have dtype in {dtypes}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if ndim is not None and t.dim() != ndim:
+        raise ValueError(f"{what} must have {ndim} dims")
+
+
+def empty_results(count: int, device):
+    import torch
+    return torch.empty((int(count), 24), dtype=torch.uint8, device=device)
+
+
+def unpack(res):
+    """Named views of a [count, 24] uint8 result tensor (no copies)."""
+    import torch
+    w32 = res.view(torch.int32).view(-1, 6)
+    return {"shift": w32[:, 0], "flags": w32[:, 1],
+            "theta": res.view(torch.float32).view(-1, 6)[:, 2],
+            "err_est": res.view(torch.float32).view(-1, 6)[:, 3],
+            "e0": res.view(torch.float64).view(-1, 3)[:, 2]}
+
+
+def to_numpy(res) -> np.ndarray:
+    return res.cpu().numpy().view(RESULT_DTYPE).reshape(-1)
+
+
+def align_pair(z1, z2, *, precision="fp32", rescore="top2", theta_fp64=False, out=None,
+               stream=None, ctx=None):
+    """Optimal start shift, rotation and e0 for one pair of n-node curves."""
+    import torch
+    dt = (torch.complex128,) if precision == "fp64" else (torch.complex64,)
+    _require(z1, "z1", dt, 1)
+    _require(z2, "z2", dt, 1)
+    if z1.shape != z2.shape:
+        raise ValueError("z1 and z2 must have the same length")
+    ctx = ctx or default_context(z1.device.index)
+    out = empty_results(1, z1.device) if out is None else out
+    opt = _options(precision, rescore, theta_fp64)
+    _check(lib().align_pair(ctx.handle, z1.data_ptr(), z2.data_ptr(), z1.shape[0],
+                            out.data_ptr(), ctypes.byref(opt), _stream_ptr(stream)))
+    return out
+
+
+def align_batch(z1, z2, offsets=None, *, precision="fp32", rescore="top2", theta_fp64=False,
+                out=None, stream=None, ctx=None):
+    """Uniform batch: z1, z2 of shape [B, n].  Ragged batch: z1, z2 flat [total]
+    with int64 `offsets` [B+1] (device tensor)."""
+    import torch
+    dt = (torch.complex128,) if precision == "fp64" else (torch.complex64,)
+    _require(z1, "z1", dt)
+    _require(z2, "z2", dt)
+    if z1.shape != z2.shape:
+        raise ValueError("z1 and z2 must have the same shape")
+    if offsets is None:
+        if z1.dim() != 2:
+            raise ValueError("uniform batches are [B, n]")
+        B, n = z1.shape
+        off_ptr = None
+    else:
+        _require(offsets, "offsets", (torch.int64,), 1)
+        B, n = offsets.shape[0] - 1, 0
+        off_ptr = offsets.data_ptr()
+    ctx = ctx or default_context(z1.device.index)
+    out = empty_results(B, z1.device) if out is None else out
+    opt = _options(precision, rescore, theta_fp64)
+    _check(lib().align_batch(ctx.handle, z1.data_ptr(), z2.data_ptr(), off_ptr, n, B,
+                             out.data_ptr(), ctypes.byref(opt), _stream_ptr(stream)))
+    return out
+
+
+def align_all_pairs(curves, *, rescore="top2", theta_fp64=False, out=None, stream=None, ctx=None):
+    """All i<j pairs of a gallery [m, n]; results in row-major upper-triangle order."""
+    import torch
+    _require(curves, "curves", (torch.complex64,), 2)
+    m, n = curves.shape
+    ctx = ctx or default_context(curves.device.index)
+    out = empty_results(m * (m - 1) // 2, curves.device) if out is None else out
+    opt = _options("fp32", rescore, theta_fp64)
+    _check(lib().align_all_pairs(ctx.handle, curves.data_ptr(), m, n, out.data_ptr(),
+                                 ctypes.byref(opt), _stream_ptr(stream)))
+    return out
+
+
+def resample_arclength(raw, raw_offsets, out_offsets, *, mode="spline", with_norms=True,
+                       with_flags=True, out=None, stream=None, ctx=None):
+    """Raw polygons (complex64 flat, int64 offsets [C+1]) -> uniform arc-length
+    nodes (complex64 flat, laid out by out_offsets).  Returns (nodes, norms, flags)."""
+    import torch
+    _require(raw, "raw", (torch.complex64,), 1)
+    _require(raw_offsets, "raw_offsets", (torch.int64,), 1)
+    _require(out_offsets, "out_offsets", (torch.int64,), 1)
+    if mode not in RESAMPLE:
+        raise ValueError(f"mode must be one of {sorted(RESAMPLE)}")
+    C = raw_offsets.shape[0] - 1
+    if out_offsets.shape[0] != C + 1:
+        raise ValueError("raw_offsets and out_offsets must have the same length")
+    total = int(out_offsets[-1].item()) if out is None else out.shape[0]
+    ctx = ctx or default_context(raw.device.index)
+    out = torch.empty(total, dtype=torch.complex64, device=raw.device) if out is None else out
+    norms = torch.empty(C, dtype=torch.float64, device=raw.device) if with_norms else None
+    flags = torch.empty(C, dtype=torch.int32, device=raw.device) if with_flags else None
+    _check(lib().resample_arclength(ctx.handle, raw.data_ptr(), raw_offsets.data_ptr(), C,
+                                    out_offsets.data_ptr(), out.data_ptr(),
+                                    norms.data_ptr() if norms is not None else None,
+                                    flags.data_ptr() if flags is not None else None,
+                                    RESAMPLE[mode], _stream_ptr(stream)))
+    return out, norms, flags

@@ -1,0 +1,502 @@
+// Alignment kernels: Algorithm 2 of section 2 as
+//   FFT(z1), FFT(z2) -> P = conj(Z1) Z2 -> D = FFT(P) = n conj(C)
+//   -> argmax |D|^2 -> FP64 re-scoring of the candidate shifts -> theta, e0.
+// (Forward-transforming conj(Z1) Z2 gives n conj(C(s)) with
+//  C(s) = sum_k z1[k] conj(z2[k - s]); |C| and arg C follow without a
+//  separate inverse transform.)
+#include <math.h>
+
+#include "fft_engines.hpp"
+#include "launch.hpp"
+
+namespace ca {
+
+// ------------------------------------------------------------ shared epilogue
+// Selection state of the FP64 re-scoring: best |C64|^2 (smallest shift on
+// equal values), its C64, and the second best value.
+struct Pick {
+    double best = -1.0, second = -1.0, re = 0.0, im = 0.0;
+    int shift = -1, count = 0;
+    __device__ __forceinline__ void offer(int c, double r, double i) {
+        const double m = r * r + i * i;
+        if (m > best || (m == best && c < shift)) {
+            second = best; best = m; shift = c; re = r; im = i;
+        } else if (m > second) {
+            second = m;
+        }
+        ++count;
+    }
+};
+
+__device__ __forceinline__ float wrap_pi(float a) {
+    const float pi = 3.14159265358979323846f;
+    return (a <= -pi) ? pi : a;
+}
+__device__ __forceinline__ double wrap_pi(double a) {
+    const double pi = 3.14159265358979323846;
+    return (a <= -pi) ? pi : a;
+}
+
+__device__ __forceinline__ void finish(ca_result_t& res, const Pick& pk, int n, double n1, double n2,
+                                       double d1, double d2, double epsD, bool capped,
+                                       float theta_path, int theta64) {
+    uint32_t flags = 0;
+    const double c64 = sqrt(pk.best);
+    if (pk.count > 1) flags |= CA_FLAG_RESCORED;
+    if (capped) flags |= CA_FLAG_CAND_CAPPED;
+    if (pk.count > 1 && pk.second >= 0.0) {
+        if (c64 - sqrt(pk.second) < kNearTie * c64) flags |= CA_FLAG_NEAR_TIE;
+    } else if (d1 - d2 < kNearTie * d1) {
+        flags |= CA_FLAG_NEAR_TIE;
+    }
+    float th = theta_path;
+    if (theta64) {
+        th = (float)wrap_pi(atan2(pk.im, pk.re));
+        flags |= CA_FLAG_THETA_FP64;
+    }
+    res.shift = pk.shift;
+    res.flags = flags;
+    res.theta = th;
+    res.err_est = (float)(2.0 * epsD / d1);
+    res.e0 = n1 + n2 - 2.0 * c64 / (double)n;
+}
+
+__device__ __forceinline__ bool special_case(ca_result_t& res, double n1, double n2, double bv) {
+    res.shift = 0;
+    res.theta = 0.0f;
+    res.err_est = 0.0f;
+    if (!(isfinite(n1) && isfinite(n2) && isfinite(bv))) {
+        res.flags = CA_FLAG_NONFINITE;
+        res.e0 = __builtin_nan("");
+        return true;
+    }
+    if (!(n1 > 0.0) || !(n2 > 0.0) || !(bv > 0.0)) {
+        res.flags = CA_FLAG_DEGENERATE;
+        res.e0 = n1 + n2;
+        return true;
+    }
+    return false;
+}
+
+// --------------------------------------------------------------- team engine
+// Epilogue of one pair held by a team: d[q] = D[t + T q] (D = n conj C),
+// a0[q] = z1[t + T q] (FP32 nodes of curve 1), zb = LDS copy of curve 2's
+// nodes at padded positions.  Returns the finished result (every lane).
+template <int N, int T>
+__device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const cf (&a0)[N / T],
+                                                     const cf* zb, int t, double n1, double n2,
+                                                     int rescore, int theta64) {
+    constexpr int R = N / T;
+    float m2[R];
+    float bv = -1.0f;
+    int bi = 0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        m2[q] = norm2(d[q]);
+        if (m2[q] > bv) { bv = m2[q]; bi = t + T * q; }
+    }
+    team_argmax<T>(bv, bi);
+    float cv = -1.0f;
+    int ci = 0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int idx = t + T * q;
+        if (idx != bi && m2[q] > cv) { cv = m2[q]; ci = idx; }
+    }
+    team_argmax<T>(cv, ci);
+
+    ca_result_t res;
+    if (special_case(res, n1, n2, (double)bv)) return res;
+    const double d1 = sqrt((double)bv), d2 = sqrt(fmax((double)cv, 0.0));
+    const double epsD = kErrScale * num<float>::u * (double)ilog2_ceil(N) * N * N * sqrt(n1 * n2);
+    Pick pk;
+    auto rescore_one = [&](int c) {
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const cf zz = zb[lpad((t + T * q - c) & (N - 1))];
+            const double ax = a0[q].x, ay = a0[q].y, bx = zz.x, by = zz.y;
+            re = fma(ax, bx, fma(ay, by, re));
+            im = fma(ay, bx, fma(-ax, by, im));
+        }
+        re = team_sum<T>(re);
+        im = team_sum<T>(im);
+        pk.offer(c, re, im);
+    };
+    bool capped = false;
+    if (rescore == CA_RESCORE_WINDOW) {
+        const double thr = d1 - 2.0 * epsD;
+        const float thr2 = thr > 0.0 ? (float)(thr * thr) : 0.0f;
+        int cnt = 0;
+#pragma unroll
+        for (int q = 0; q < R; ++q) cnt += (m2[q] >= thr2) ? 1 : 0;
+        cnt = team_sum<T>(cnt);
+        if (thr > 0.0 && cnt <= kCandCap) {
+            const int base = (threadIdx.x & 63) - t;
+            const uint64_t tmask = (T == 64) ? ~0ull : (((1ull << T) - 1ull) << base);
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                uint64_t msk = __ballot(m2[q] >= thr2) & tmask;
+                while (msk) {
+                    const int l = __ffsll((unsigned long long)msk) - 1;
+                    msk &= msk - 1;
+                    rescore_one(l - base + T * q);
+                }
+            }
+        } else {
+            capped = true;
+        }
+    }
+    if (rescore != CA_RESCORE_WINDOW || capped || pk.count == 0) {
+        rescore_one(bi);
+        if (d1 - d2 < 2.0 * epsD) rescore_one(ci);
+    }
+    // the path's own C at the chosen shift: arg C = atan2(-Im D, Re D)
+    const int qs = pk.shift / T, ls = pk.shift % T;
+    cf sel = d[0];
+#pragma unroll
+    for (int q = 1; q < R; ++q)
+        if (q == qs) sel = d[q];
+    sel.x = __shfl(sel.x, ls, T);
+    sel.y = __shfl(sel.y, ls, T);
+    const float thp = wrap_pi(atan2f(-sel.y, sel.x));
+    finish(res, pk, N, n1, n2, d1, d2, epsD, capped, thp, theta64);
+    return res;
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void k_align_team(const cf* __restrict__ z1, const cf* __restrict__ z2,
+                                                    int64_t num_pairs, ca_result_t* __restrict__ out,
+                                                    const cf* __restrict__ tw, int rescore, int theta64) {
+    constexpr int T = TeamCfg<N>::T;
+    constexpr int R = N / T;
+    constexpr int TEAMS = 256 / T;
+    constexpr int PADN = N + N / 16;
+    __shared__ cf lds_all[TEAMS * PADN];
+    const int team = threadIdx.x / T;
+    const int t = threadIdx.x % T;
+    const int64_t pair = (int64_t)blockIdx.x * TEAMS + team;
+    if (pair >= num_pairs) return;   // a team leaves as a whole
+    cf* lds = lds_all + team * PADN;
+    const cf* pa = z1 + pair * N;
+    const cf* pb = z2 + pair * N;
+
+    cf v[R], w[R], a0[R], b0[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) { v[q] = pa[t + T * q]; w[q] = pb[t + T * q]; }
+    double q1 = 0.0, q2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        a0[q] = v[q]; b0[q] = w[q];
+        const double ax = v[q].x, ay = v[q].y, bx = w[q].x, by = w[q].y;
+        q1 = fma(ax, ax, fma(ay, ay, q1));
+        q2 = fma(bx, bx, fma(by, by, q2));
+    }
+    team_fft2<N, T>(v, w, lds, tw, t);
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = cjmul(v[q], w[q]);
+    team_fft<N, T>(v, lds, tw, t);
+    const double n1 = team_sum<T>(q1) / N;
+    const double n2 = team_sum<T>(q2) / N;
+    // z2 nodes for the shifted FP64 dot products
+#pragma unroll
+    for (int q = 0; q < R; ++q) lds[lpad(t + T * q)] = b0[q];
+    wave_lds_sync();
+    const ca_result_t res = team_epilogue<N, T>(v, a0, lds, t, n1, n2, rescore, theta64);
+    if (t == 0) out[pair] = res;
+}
+
+// ------------------------------------------------------------------ all pairs
+// Per-curve spectra Z_i = FFT(z_i) in natural order and n_i = (1/n) sum |z_i|^2.
+template <int N>
+__global__ __launch_bounds__(256) void k_spectra(const cf* __restrict__ curves, int m, cf* __restrict__ spec,
+                                                 double* __restrict__ norms, const cf* __restrict__ tw) {
+    constexpr int T = TeamCfg<N>::T;
+    constexpr int R = N / T;
+    constexpr int TEAMS = 256 / T;
+    constexpr int PADN = N + N / 16;
+    __shared__ cf lds_all[TEAMS * PADN];
+    const int team = threadIdx.x / T;
+    const int t = threadIdx.x % T;
+    const int64_t i = (int64_t)blockIdx.x * TEAMS + team;
+    if (i >= m) return;
+    cf* lds = lds_all + team * PADN;
+    const cf* z = curves + i * N;
+    cf v[R];
+    double q2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        v[q] = z[t + T * q];
+        q2 = fma((double)v[q].x, (double)v[q].x, fma((double)v[q].y, (double)v[q].y, q2));
+    }
+    team_fft<N, T>(v, lds, tw, t);
+#pragma unroll
+    for (int q = 0; q < R; ++q) spec[i * N + t + T * q] = v[q];
+    q2 = team_sum<T>(q2);
+    if (t == 0) norms[i] = q2 / N;
+}
+
+// Upper-triangle tiles: blockIdx.y picks TEAMS rows i, blockIdx.x a block of
+// JB columns j.  Each row's conj spectrum and nodes stay in registers; every
+// column's spectrum and nodes are staged once in LDS and shared by the rows.
+template <int N, int JB>
+__global__ __launch_bounds__(256) void k_allpairs(const cf* __restrict__ curves, const cf* __restrict__ spec,
+                                                  const double* __restrict__ norms, int m,
+                                                  ca_result_t* __restrict__ out, const cf* __restrict__ tw,
+                                                  int rescore, int theta64) {
+    constexpr int T = TeamCfg<N>::T;
+    constexpr int R = N / T;
+    constexpr int TEAMS = 256 / T;
+    constexpr int PADN = N + N / 16;
+    __shared__ cf sZ[N];
+    __shared__ cf sz[PADN];
+    __shared__ cf xbuf[TEAMS * PADN];
+    const int i0 = blockIdx.y * TEAMS;
+    const int j0 = blockIdx.x * JB;
+    if (j0 + JB - 1 <= i0) return;     // no j > i in this tile
+    const int team = threadIdx.x / T;
+    const int t = threadIdx.x % T;
+    const int i = i0 + team;
+    const bool row_ok = i < m;
+    cf* lds = xbuf + team * PADN;
+    cf Zi[R], zi[R];
+    double ni = 0.0;
+    if (row_ok) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            Zi[q] = spec[(int64_t)i * N + t + T * q];
+            zi[q] = curves[(int64_t)i * N + t + T * q];
+        }
+        ni = norms[i];
+    }
+    const int jend = min(j0 + JB, m);
+    for (int j = j0; j < jend; ++j) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < N; k += 256) {
+            sZ[k] = spec[(int64_t)j * N + k];
+            sz[lpad(k)] = curves[(int64_t)j * N + k];
+        }
+        __syncthreads();
+        if (row_ok && j > i) {
+            cf v[R];
+#pragma unroll
+            for (int q = 0; q < R; ++q) v[q] = cjmul(Zi[q], sZ[t + T * q]);
+            team_fft<N, T>(v, lds, tw, t);
+            const ca_result_t res = team_epilogue<N, T>(v, zi, sz, t, ni, norms[j], rescore, theta64);
+            if (t == 0) {
+                const int64_t k = (int64_t)i * m - (int64_t)i * (i + 1) / 2 + (j - i - 1);
+                out[k] = res;
+            }
+        }
+    }
+}
+
+bool allpairs_supported(int n) { return n == 64 || n == 128 || n == 256 || n == 512 || n == 1024; }
+
+template <int N>
+static hipError_t launch_spectra_n(const void* curves, int m, void* spec, double* norms, const void* tw,
+                                   hipStream_t s) {
+    constexpr int TEAMS = 256 / TeamCfg<N>::T;
+    hipLaunchKernelGGL(k_spectra<N>, dim3((unsigned)((m + TEAMS - 1) / TEAMS)), dim3(256), 0, s,
+                       (const cf*)curves, m, (cf*)spec, norms, (const cf*)tw);
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_allpairs_n(const void* curves, const void* spec, const double* norms, int m,
+                                    ca_result_t* out, const void* tw, int rescore, int theta64,
+                                    hipStream_t s) {
+    constexpr int TEAMS = 256 / TeamCfg<N>::T;
+    constexpr int JB = 64;
+    dim3 grid((unsigned)((m + JB - 1) / JB), (unsigned)((m + TEAMS - 1) / TEAMS));
+    hipLaunchKernelGGL((k_allpairs<N, JB>), grid, dim3(256), 0, s, (const cf*)curves, (const cf*)spec,
+                       norms, m, out, (const cf*)tw, rescore, theta64);
+    return hipGetLastError();
+}
+
+hipError_t launch_spectra(const void* curves, int m, int n, void* spec, double* norms, const void* tw,
+                          hipStream_t s) {
+    switch (n) {
+        case 64: return launch_spectra_n<64>(curves, m, spec, norms, tw, s);
+        case 128: return launch_spectra_n<128>(curves, m, spec, norms, tw, s);
+        case 256: return launch_spectra_n<256>(curves, m, spec, norms, tw, s);
+        case 512: return launch_spectra_n<512>(curves, m, spec, norms, tw, s);
+        case 1024: return launch_spectra_n<1024>(curves, m, spec, norms, tw, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_allpairs(const void* curves, const void* spec, const double* norms, int m, int n,
+                           ca_result_t* out, const void* tw, int rescore, int theta64, hipStream_t s) {
+    switch (n) {
+        case 64: return launch_allpairs_n<64>(curves, spec, norms, m, out, tw, rescore, theta64, s);
+        case 128: return launch_allpairs_n<128>(curves, spec, norms, m, out, tw, rescore, theta64, s);
+        case 256: return launch_allpairs_n<256>(curves, spec, norms, m, out, tw, rescore, theta64, s);
+        case 512: return launch_allpairs_n<512>(curves, spec, norms, m, out, tw, rescore, theta64, s);
+        case 1024: return launch_allpairs_n<1024>(curves, spec, norms, m, out, tw, rescore, theta64, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+bool team_supported(int n) { return n == 64 || n == 128 || n == 256 || n == 512 || n == 1024; }
+
+template <int N>
+static hipError_t launch_team_n(const void* z1, const void* z2, int64_t np, ca_result_t* out,
+                                const void* tw, int rescore, int theta64, hipStream_t s) {
+    constexpr int TEAMS = 256 / TeamCfg<N>::T;
+    const int64_t blocks = (np + TEAMS - 1) / TEAMS;
+    hipLaunchKernelGGL(k_align_team<N>, dim3((unsigned)blocks), dim3(256), 0, s, (const cf*)z1,
+                       (const cf*)z2, np, out, (const cf*)tw, rescore, theta64);
+    return hipGetLastError();
+}
+
+hipError_t launch_align_team(const void* z1, const void* z2, int n, int64_t np, ca_result_t* out,
+                             const void* tw, int rescore, int theta64, hipStream_t s) {
+    switch (n) {
+        case 64: return launch_team_n<64>(z1, z2, np, out, tw, rescore, theta64, s);
+        case 128: return launch_team_n<128>(z1, z2, np, out, tw, rescore, theta64, s);
+        case 256: return launch_team_n<256>(z1, z2, np, out, tw, rescore, theta64, s);
+        case 512: return launch_team_n<512>(z1, z2, np, out, tw, rescore, theta64, s);
+        case 1024: return launch_team_n<1024>(z1, z2, np, out, tw, rescore, theta64, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// -------------------------------------------------------------- block engine
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1, const cpx<T>* __restrict__ z2,
+                                                  const int64_t* __restrict__ offsets, int n_uniform,
+                                                  int64_t num_pairs, ca_result_t* __restrict__ out,
+                                                  const Plan* __restrict__ plans,
+                                                  const cpx<T>* __restrict__ arena, int rescore, int theta64) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    __shared__ double red[2 * (NT / 64)];
+    __shared__ int clist[kCandCap + 1];
+    const int64_t pair = blockIdx.x;
+    if (pair >= num_pairs) return;
+    int64_t off;
+    int n;
+    if (offsets) {
+        off = offsets[pair];
+        const int64_t len = offsets[pair + 1] - off;
+        n = (len >= 2 && len <= kMaxN) ? (int)len : 0;
+    } else {
+        off = pair * (int64_t)n_uniform;
+        n = n_uniform;
+    }
+    if (n == 0 || plans[n].n != n) {
+        if (threadIdx.x == 0) {
+            ca_result_t r;
+            r.shift = 0; r.flags = CA_FLAG_UNSUPPORTED_N; r.theta = 0.0f; r.err_est = 0.0f;
+            r.e0 = __builtin_nan("");
+            out[pair] = r;
+        }
+        return;
+    }
+    const Plan& p = plans[n];
+    const cpx<T>* tw = arena + p.tw_off;
+    cpx<T>* A = reinterpret_cast<cpx<T>*>(smem);
+    cpx<T>* B = A + n;
+    const cpx<T>* pa = z1 + off;
+    const cpx<T>* pb = z2 + off;
+
+    double q1 = 0.0, q2 = 0.0;
+    for (int k = threadIdx.x; k < n; k += NT) {
+        const cpx<T> a = pa[k], b = pb[k];
+        A[k] = a;
+        B[k] = b;
+        q1 = fma((double)a.x, (double)a.x, fma((double)a.y, (double)a.y, q1));
+        q2 = fma((double)b.x, (double)b.x, fma((double)b.y, (double)b.y, q2));
+    }
+    const double n1 = block_sum<NT>(q1, red) / n;   // block_sum synchronises
+    const double n2 = block_sum<NT>(q2, red) / n;
+    blk_fft<NT>(A, p, tw);
+    blk_fft<NT>(B, p, tw);
+    for (int k = threadIdx.x; k < n; k += NT) A[k] = cjmul(A[k], B[k]);
+    __syncthreads();
+    blk_fft<NT>(A, p, tw);
+    for (int k = threadIdx.x; k < n; k += NT) B[k] = pb[k];   // z2 again, for re-scoring
+
+    T bv = T(-1);
+    int bi = 0;
+    for (int k = threadIdx.x; k < n; k += NT) {
+        const T m = norm2(A[k]);
+        if (m > bv) { bv = m; bi = k; }
+    }
+    block_argmax<NT>(bv, bi, red);
+    T cv = T(-1);
+    int ci = 0;
+    for (int k = threadIdx.x; k < n; k += NT) {
+        const T m = norm2(A[k]);
+        if (k != bi && m > cv) { cv = m; ci = k; }
+    }
+    block_argmax<NT>(cv, ci, red);
+
+    ca_result_t res;
+    if (!special_case(res, n1, n2, (double)bv)) {
+        const double d1 = sqrt((double)bv), d2 = sqrt(fmax((double)cv, 0.0));
+        double lg = 0.0;
+        for (int m = 1; m < n; m <<= 1) lg += 1.0;
+        const double epsD = kErrScale * num<T>::u * lg * (double)n * (double)n * sqrt(n1 * n2);
+        Pick pk;
+        auto rescore_one = [&](int c) {
+            double re = 0.0, im = 0.0;
+            for (int k = threadIdx.x; k < n; k += NT) {
+                int idx = k - c;
+                if (idx < 0) idx += n;
+                const cpx<T> a = pa[k], b = B[idx];
+                const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
+                re = fma(ax, bx, fma(ay, by, re));
+                im = fma(ay, bx, fma(-ax, by, im));
+            }
+            re = block_sum<NT>(re, red);
+            im = block_sum<NT>(im, red);
+            pk.offer(c, re, im);
+        };
+        bool capped = false;
+        if (rescore == CA_RESCORE_WINDOW) {
+            const double thr = d1 - 2.0 * epsD;
+            const double thr2 = thr > 0.0 ? thr * thr : 0.0;
+            if (threadIdx.x == 0) clist[0] = 0;
+            __syncthreads();
+            for (int k = threadIdx.x; k < n; k += NT) {
+                if ((double)norm2(A[k]) >= thr2) {
+                    const int pos = atomicAdd(&clist[0], 1);
+                    if (pos < kCandCap) clist[1 + pos] = k;
+                }
+            }
+            __syncthreads();
+            const int cnt = clist[0];
+            if (thr > 0.0 && cnt <= kCandCap) {
+                for (int c = 0; c < cnt; ++c) rescore_one(clist[1 + c]);
+            } else {
+                capped = true;
+            }
+        }
+        if (rescore != CA_RESCORE_WINDOW || capped || pk.count == 0) {
+            rescore_one(bi);
+            if (d1 - d2 < 2.0 * epsD) rescore_one(ci);
+        }
+        const cpx<T> sel = A[pk.shift];
+        const float thp = (float)wrap_pi(atan2((double)-sel.y, (double)sel.x));
+        finish(res, pk, n, n1, n2, d1, d2, epsD, capped, thp, theta64);
+    }
+    if (threadIdx.x == 0) out[pair] = res;
+}
+
+size_t blk_dynamic_lds(int n_max, size_t elem) { return 2 * (size_t)n_max * elem; }
+
+template <typename T>
+static hipError_t launch_blk(const BlkArgs& a, hipStream_t s) {
+    constexpr int NT = 256;
+    const size_t lds = blk_dynamic_lds(a.n_max, sizeof(cpx<T>));
+    hipLaunchKernelGGL((k_align_blk<T, NT>), dim3((unsigned)a.num_pairs), dim3(NT), lds, s,
+                       (const cpx<T>*)a.z1, (const cpx<T>*)a.z2, a.offsets, a.n_uniform, a.num_pairs,
+                       a.out, a.plans, (const cpx<T>*)a.tw_arena, a.rescore, a.theta64);
+    return hipGetLastError();
+}
+
+hipError_t launch_align_blk_f32(const BlkArgs& a, hipStream_t s) { return launch_blk<float>(a, s); }
+hipError_t launch_align_blk_f64(const BlkArgs& a, hipStream_t s) { return launch_blk<double>(a, s); }
+
+}  // namespace ca

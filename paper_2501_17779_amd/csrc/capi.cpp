@@ -1,0 +1,360 @@
+// C ABI of the library (declared in include/curvealign.h): contexts, plan and
+// twiddle tables, argument validation and kernel dispatch.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/curvealign.h"
+#include "fft_engines.hpp"
+#include "launch.hpp"
+
+namespace ca {
+int64_t resample_slot_bytes();
+int resample_max_raw();
+}
+
+using ca::Plan;
+
+namespace {
+
+thread_local std::string g_err;
+
+ca_status_t fail(ca_status_t st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+ca_status_t hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return CA_ERR_HIP;
+}
+
+bool smooth7(int n) {
+    if (n < 2 || n > CA_MAX_N) return false;
+    for (int p : {2, 3, 5, 7})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+// Radix schedule of the block engine: eights, then a four or two, then the
+// odd primes.
+void make_plan(int n, Plan& p) {
+    memset(&p, 0, sizeof(p));
+    p.n = n;
+    int m = n, k = 0;
+    while (m % 8 == 0) { p.radix[k++] = 8; m /= 8; }
+    if (m % 4 == 0) { p.radix[k++] = 4; m /= 4; }
+    if (m % 2 == 0) { p.radix[k++] = 2; m /= 2; }
+    for (int r : {3, 5, 7})
+        while (m % r == 0) { p.radix[k++] = r; m /= r; }
+    p.npass = k;
+}
+
+// w_n^m = exp(-2 pi i m / n), computed in long double and rounded once.
+void twiddles(int n, std::vector<double>& re, std::vector<double>& im) {
+    re.resize(n);
+    im.resize(n);
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    for (int m = 0; m < n; ++m) {
+        const long double a = two_pi * (long double)m / (long double)n;
+        long double c = cosl(a), s = -sinl(a);
+        if (fabsl(c) < 1e-18L) c = 0.0L;
+        if (fabsl(s) < 1e-18L) s = 0.0L;
+        re[m] = (double)c;
+        im[m] = (double)s;
+    }
+}
+
+}  // namespace
+
+struct ca_context {
+    int device = 0;
+    int num_cus = 0;
+    size_t lds_per_block = 0;
+    std::mutex mu;
+    // block-engine plans for every n in [0, CA_MAX_N] and the twiddle arenas
+    Plan* d_plans = nullptr;
+    std::vector<Plan> h_plans;
+    void* d_tw32 = nullptr;   // float2 arena
+    void* d_tw64 = nullptr;   // double2 arena
+    // resampler scratch
+    void* d_rs = nullptr;
+    int64_t rs_slots = 0;
+    // all-pairs spectra workspace
+    void* d_spec = nullptr;
+    size_t spec_bytes = 0;
+    double* d_norms = nullptr;
+    size_t norms_count = 0;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+ca_status_t ensure_tables(ca_context* c, bool need64) {
+    if (!c->d_plans) {
+        c->h_plans.assign(CA_MAX_N + 1, Plan{});
+        std::vector<float> arena32;
+        int64_t off = 0;
+        std::vector<double> re, im;
+        for (int n = 2; n <= CA_MAX_N; ++n) {
+            if (!smooth7(n)) continue;
+            make_plan(n, c->h_plans[n]);
+            c->h_plans[n].tw_off = off;
+            twiddles(n, re, im);
+            for (int m = 0; m < n; ++m) {
+                arena32.push_back((float)re[m]);
+                arena32.push_back((float)im[m]);
+            }
+            off += n;
+        }
+        hipError_t e;
+        if ((e = hipMalloc(&c->d_plans, sizeof(Plan) * (CA_MAX_N + 1))) != hipSuccess)
+            return fail(CA_ERR_OOM, "plan table allocation failed");
+        if ((e = hipMemcpy(c->d_plans, c->h_plans.data(), sizeof(Plan) * (CA_MAX_N + 1),
+                           hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "plan upload");
+        if ((e = hipMalloc(&c->d_tw32, arena32.size() * sizeof(float))) != hipSuccess)
+            return fail(CA_ERR_OOM, "twiddle arena allocation failed");
+        if ((e = hipMemcpy(c->d_tw32, arena32.data(), arena32.size() * sizeof(float),
+                           hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "twiddle upload");
+    }
+    if (need64 && !c->d_tw64) {
+        std::vector<double> arena64, re, im;
+        for (int n = 2; n <= CA_MAX_N; ++n) {
+            if (!smooth7(n)) continue;
+            twiddles(n, re, im);
+            for (int m = 0; m < n; ++m) {
+                arena64.push_back(re[m]);
+                arena64.push_back(im[m]);
+            }
+        }
+        hipError_t e;
+        if ((e = hipMalloc(&c->d_tw64, arena64.size() * sizeof(double))) != hipSuccess)
+            return fail(CA_ERR_OOM, "FP64 twiddle arena allocation failed");
+        if ((e = hipMemcpy(c->d_tw64, arena64.data(), arena64.size() * sizeof(double),
+                           hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "FP64 twiddle upload");
+    }
+    return CA_OK;
+}
+
+const void* tw32_for(ca_context* c, int n) {
+    return (const char*)c->d_tw32 + c->h_plans[n].tw_off * 2 * sizeof(float);
+}
+
+ca_status_t parse_opts(const ca_options_t* opt, ca_options_t& o) {
+    o = ca_options_t{CA_PREC_FP32, CA_RESCORE_TOP2, 0, 0};
+    if (!opt) return CA_OK;
+    o = *opt;
+    if (o.precision != CA_PREC_FP32 && o.precision != CA_PREC_SPLIT_BF16 && o.precision != CA_PREC_FP64)
+        return fail(CA_ERR_INVALID_ARG, "options.precision must be CA_PREC_FP32, _SPLIT_BF16 or _FP64");
+    if (o.rescore != CA_RESCORE_TOP2 && o.rescore != CA_RESCORE_WINDOW)
+        return fail(CA_ERR_INVALID_ARG, "options.rescore must be CA_RESCORE_TOP2 or _WINDOW");
+    if (o.reserved != 0) return fail(CA_ERR_INVALID_ARG, "options.reserved must be 0");
+    return CA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ca_status_string(ca_status_t s) {
+    switch (s) {
+        case CA_OK: return "ok";
+        case CA_ERR_INVALID_ARG: return "invalid argument";
+        case CA_ERR_UNSUPPORTED_N: return "unsupported curve size";
+        case CA_ERR_HIP: return "HIP runtime error";
+        case CA_ERR_OOM: return "out of device memory";
+        case CA_ERR_NO_DEVICE: return "no gfx950 device";
+        case CA_ERR_INTERNAL: return "internal error";
+        default: return "unknown status";
+    }
+}
+
+const char* ca_last_error(void) { return g_err.c_str(); }
+
+int32_t ca_n_supported(int32_t n) { return smooth7(n) ? 1 : 0; }
+
+ca_status_t ca_create(ca_context_t* ctx, int device) {
+    if (!ctx) return fail(CA_ERR_INVALID_ARG, "ctx is NULL");
+    *ctx = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+        return fail(CA_ERR_NO_DEVICE, "no HIP device visible");
+    if (device < 0 || device >= count) return fail(CA_ERR_NO_DEVICE, "device index out of range");
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(CA_ERR_NO_DEVICE, std::string("device is ") + prop.gcnArchName + ", gfx950 required");
+    ca_context* c = new ca_context();
+    c->device = device;
+    c->num_cus = prop.multiProcessorCount;
+    c->lds_per_block = prop.sharedMemPerBlock;
+    DeviceGuard g(device);
+    ca_status_t st = ensure_tables(c, false);
+    if (st != CA_OK) {
+        ca_destroy(c);
+        return st;
+    }
+    *ctx = c;
+    return CA_OK;
+}
+
+ca_status_t ca_destroy(ca_context_t c) {
+    if (!c) return CA_OK;
+    {
+        DeviceGuard g(c->device);
+        (void)hipDeviceSynchronize();
+        if (c->d_plans) (void)hipFree(c->d_plans);
+        if (c->d_tw32) (void)hipFree(c->d_tw32);
+        if (c->d_tw64) (void)hipFree(c->d_tw64);
+        if (c->d_rs) (void)hipFree(c->d_rs);
+        if (c->d_spec) (void)hipFree(c->d_spec);
+        if (c->d_norms) (void)hipFree(c->d_norms);
+    }
+    delete c;
+    return CA_OK;
+}
+
+ca_status_t align_batch(ca_context_t c, const void* z1, const void* z2, const int64_t* offsets,
+                        int32_t n, int64_t num_pairs, ca_result_t* out, const ca_options_t* opt,
+                        void* stream) {
+    if (!c) return fail(CA_ERR_INVALID_ARG, "context is NULL");
+    if (num_pairs < 0) return fail(CA_ERR_INVALID_ARG, "num_pairs < 0");
+    ca_options_t o;
+    ca_status_t st = parse_opts(opt, o);
+    if (st != CA_OK) return st;
+    if (num_pairs == 0) return CA_OK;
+    if (!z1 || !z2 || !out) return fail(CA_ERR_INVALID_ARG, "z1, z2 and out must be non-NULL");
+    if (num_pairs > 0x7fffffffLL) return fail(CA_ERR_INVALID_ARG, "num_pairs exceeds 2^31 - 1");
+    if (!offsets && !smooth7(n))
+        return fail(CA_ERR_UNSUPPORTED_N, "n must be in [2, 4096] with prime factors 2, 3, 5, 7");
+    if (o.precision == CA_PREC_SPLIT_BF16)
+        return fail(CA_ERR_UNSUPPORTED_N, "split-BF16 precision is not available for this n");
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    st = ensure_tables(c, o.precision == CA_PREC_FP64);
+    if (st != CA_OK) return st;
+    hipError_t e;
+    if (o.precision == CA_PREC_FP32 && !offsets && ca::team_supported(n)) {
+        e = ca::launch_align_team(z1, z2, n, num_pairs, out, tw32_for(c, n), o.rescore, o.theta_fp64, s);
+    } else {
+        ca::BlkArgs a;
+        a.z1 = z1;
+        a.z2 = z2;
+        a.offsets = offsets;
+        a.n_uniform = offsets ? 0 : n;
+        a.n_max = offsets ? CA_MAX_N : n;
+        a.num_pairs = num_pairs;
+        a.out = out;
+        a.plans = c->d_plans;
+        a.rescore = o.rescore;
+        a.theta64 = o.theta_fp64;
+        const size_t elem = o.precision == CA_PREC_FP64 ? 16 : 8;
+        if (ca::blk_dynamic_lds(a.n_max, elem) + 1024 > c->lds_per_block)
+            return fail(CA_ERR_UNSUPPORTED_N, "curve size needs more LDS than one workgroup has");
+        if (o.precision == CA_PREC_FP64) {
+            a.tw_arena = c->d_tw64;
+            e = ca::launch_align_blk_f64(a, s);
+        } else {
+            a.tw_arena = c->d_tw32;
+            e = ca::launch_align_blk_f32(a, s);
+        }
+    }
+    if (e != hipSuccess) return hip_fail(e, "align kernel launch");
+    return CA_OK;
+}
+
+ca_status_t align_pair(ca_context_t c, const void* z1, const void* z2, int32_t n, ca_result_t* out,
+                       const ca_options_t* opt, void* stream) {
+    return align_batch(c, z1, z2, nullptr, n, 1, out, opt, stream);
+}
+
+ca_status_t align_all_pairs(ca_context_t c, const void* curves, int32_t m, int32_t n,
+                            ca_result_t* out_upper, const ca_options_t* opt, void* stream) {
+    if (!c) return fail(CA_ERR_INVALID_ARG, "context is NULL");
+    ca_options_t o;
+    ca_status_t st = parse_opts(opt, o);
+    if (st != CA_OK) return st;
+    if (m < 0) return fail(CA_ERR_INVALID_ARG, "m < 0");
+    if (m < 2) return CA_OK;
+    if (!curves || !out_upper) return fail(CA_ERR_INVALID_ARG, "curves and out_upper must be non-NULL");
+    if (o.precision != CA_PREC_FP32) return fail(CA_ERR_INVALID_ARG, "align_all_pairs is FP32 only");
+    if (!smooth7(n)) return fail(CA_ERR_UNSUPPORTED_N, "unsupported n");
+    const int64_t npairs = (int64_t)m * (m - 1) / 2;
+    if (npairs > 0x7fffffffLL) return fail(CA_ERR_INVALID_ARG, "m*(m-1)/2 exceeds 2^31 - 1");
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    st = ensure_tables(c, false);
+    if (st != CA_OK) return st;
+    hipError_t e;
+    if (ca::allpairs_supported(n)) {
+        const size_t need = (size_t)m * n * 2 * sizeof(float);
+        if (need > c->spec_bytes) {
+            if (c->d_spec) (void)hipFree(c->d_spec);
+            c->d_spec = nullptr;
+            c->spec_bytes = 0;
+            if (hipMalloc(&c->d_spec, need) != hipSuccess) return fail(CA_ERR_OOM, "spectra workspace");
+            c->spec_bytes = need;
+        }
+        if ((size_t)m > c->norms_count) {
+            if (c->d_norms) (void)hipFree(c->d_norms);
+            c->d_norms = nullptr;
+            c->norms_count = 0;
+            if (hipMalloc(&c->d_norms, (size_t)m * sizeof(double)) != hipSuccess)
+                return fail(CA_ERR_OOM, "norms workspace");
+            c->norms_count = m;
+        }
+        e = ca::launch_spectra(curves, m, n, c->d_spec, c->d_norms, tw32_for(c, n), s);
+        if (e != hipSuccess) return hip_fail(e, "spectra kernel launch");
+        e = ca::launch_allpairs(curves, c->d_spec, c->d_norms, m, n, out_upper, tw32_for(c, n),
+                                o.rescore, o.theta_fp64, s);
+        if (e != hipSuccess) return hip_fail(e, "all-pairs kernel launch");
+        return CA_OK;
+    }
+    return fail(CA_ERR_UNSUPPORTED_N, "align_all_pairs supports n in {64, 128, 256, 512, 1024}");
+}
+
+ca_status_t resample_arclength(ca_context_t c, const void* raw, const int64_t* raw_offsets,
+                               int64_t num_curves, const int64_t* out_offsets, void* out,
+                               double* norms_out, uint32_t* flags_out, int32_t mode, void* stream) {
+    if (!c) return fail(CA_ERR_INVALID_ARG, "context is NULL");
+    if (num_curves < 0) return fail(CA_ERR_INVALID_ARG, "num_curves < 0");
+    if (mode != CA_RESAMPLE_SPLINE && mode != CA_RESAMPLE_LINEAR)
+        return fail(CA_ERR_INVALID_ARG, "mode must be CA_RESAMPLE_SPLINE or CA_RESAMPLE_LINEAR");
+    if (num_curves == 0) return CA_OK;
+    if (!raw || !raw_offsets || !out_offsets || !out)
+        return fail(CA_ERR_INVALID_ARG, "raw, raw_offsets, out_offsets and out must be non-NULL");
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    if (!c->d_rs) {
+        const int64_t slots = 2 * (int64_t)c->num_cus;
+        if (hipMalloc(&c->d_rs, (size_t)(slots * ca::resample_slot_bytes())) != hipSuccess)
+            return fail(CA_ERR_OOM, "resampler scratch");
+        c->rs_slots = slots;
+    }
+    hipError_t e = ca::launch_resample(raw, raw_offsets, num_curves, out_offsets, out, norms_out,
+                                       flags_out, mode, c->d_rs, ca::resample_slot_bytes(),
+                                       c->rs_slots, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "resample kernel launch");
+    return CA_OK;
+}
+
+}  // extern "C"

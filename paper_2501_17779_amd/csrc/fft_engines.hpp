@@ -1,0 +1,232 @@
+// Two FFT engines for the correlation of section 2 (the DFT steps of
+// Algorithm 2).  Both are Stockham auto-sort, decimation in time:
+//
+//   pass p with radix R and stride Ns (product of the earlier radices):
+//     for butterfly j in [0, N/R), k = j mod Ns:
+//       b[r] = x[j + r N/R] * w_{Ns R}^{r k},  r = 0..R-1
+//       b    = DFT_R(b)
+//       y[(j - k) R + k + r Ns] = b[r]
+//
+// which leaves the output in natural order.
+//
+// * Block engine (any n with factors 2, 3, 5, 7; n <= 4096): one pair per
+//   workgroup, the signal lives in LDS, every pass reads, synchronises and
+//   writes in place.  Twiddles w_n^m come from a per-n table.
+// * Team engine (powers of two, FP32): a team of T lanes (T <= 64, inside one
+//   wave) owns one signal, lane t holding x[t + T q] for q = 0..R-1 in
+//   registers (R = n / T).  With butterflies j = t + u T every pass reads
+//   exactly those elements, so each pass is: butterflies on registers, a
+//   scatter of the outputs to a per-team LDS buffer, and a gather of
+//   x[t + T q] back into registers; the last pass needs no exchange and
+//   leaves lane t holding X[t + T q] again.  The LDS buffer is padded with one
+//   element per 16 so the stride-R scatter of the first pass is free of bank
+//   conflicts.
+#pragma once
+
+#include "dft_small.hpp"
+
+namespace ca {
+
+// ------------------------------------------------------------------ block engine
+struct Plan {
+    int32_t n;
+    int32_t npass;
+    int32_t radix[16];
+    int64_t tw_off;      // offset of the w_n^m table in the twiddle arena
+};
+
+template <int R, int NT, typename T>
+__device__ __forceinline__ void blk_pass(cpx<T>* buf, int n, int ns, const cpx<T>* __restrict__ tw) {
+    constexpr int UM = (kMaxN / R + NT - 1) / NT;
+    const int nb = n / R;
+    const int tstride = n / (ns * R);
+    cpx<T> v[UM][R];
+#pragma unroll
+    for (int u = 0; u < UM; ++u) {
+        const int j = threadIdx.x + u * NT;
+        if (j < nb) {
+            const int k = j % ns;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[u][r] = buf[j + r * nb];
+            if (ns > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[u][r] = mul(v[u][r], tw[r * k * tstride]);
+            }
+            dft<R>(v[u]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < UM; ++u) {
+        const int j = threadIdx.x + u * NT;
+        if (j < nb) {
+            const int k = j % ns;
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[base + r * ns] = v[u][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <int NT, typename T>
+__device__ void blk_fft(cpx<T>* buf, const Plan& p, const cpx<T>* __restrict__ tw) {
+    int ns = 1;
+    for (int i = 0; i < p.npass; ++i) {
+        const int r = p.radix[i];
+        switch (r) {
+            case 2: blk_pass<2, NT>(buf, p.n, ns, tw); break;
+            case 3: blk_pass<3, NT>(buf, p.n, ns, tw); break;
+            case 4: blk_pass<4, NT>(buf, p.n, ns, tw); break;
+            case 5: blk_pass<5, NT>(buf, p.n, ns, tw); break;
+            case 7: blk_pass<7, NT>(buf, p.n, ns, tw); break;
+            default: blk_pass<8, NT>(buf, p.n, ns, tw); break;
+        }
+        ns *= r;
+    }
+}
+
+// ------------------------------------------------------------------- team engine
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+
+template <int N, int T, int RP, int NS, bool LAST>
+__device__ __forceinline__ void team_pass(cf (&v)[N / T], cf* lds, const cf* __restrict__ tw, int t) {
+    constexpr int R = N / T;
+    constexpr int U = R / RP;
+    static_assert(R % RP == 0, "radix must divide the per-lane count");
+    constexpr int TS = N / (NS * RP);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = t + u * T;
+        const int k = j % NS;
+        cf b[RP];
+#pragma unroll
+        for (int r = 0; r < RP; ++r) b[r] = v[u + r * U];
+        if constexpr (NS > 1) {
+#pragma unroll
+            for (int r = 1; r < RP; ++r) b[r] = mul(b[r], tw[r * k * TS]);
+        }
+        dft<RP>(b);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int r = 0; r < RP; ++r) v[u + r * U] = b[r];
+        } else {
+            const int base = (j - k) * RP + k;
+#pragma unroll
+            for (int r = 0; r < RP; ++r) lds[lpad(base + r * NS)] = b[r];
+        }
+    }
+    if constexpr (!LAST) {
+        wave_lds_sync();
+#pragma unroll
+        for (int q = 0; q < R; ++q) v[q] = lds[lpad(t + T * q)];
+        wave_lds_sync();
+    }
+}
+
+// Same pass on two signals with one twiddle fetch.
+template <int N, int T, int RP, int NS, bool LAST>
+__device__ __forceinline__ void team_pass2(cf (&v)[N / T], cf (&w)[N / T], cf* lds,
+                                           const cf* __restrict__ tw, int t) {
+    constexpr int R = N / T;
+    constexpr int U = R / RP;
+    constexpr int TS = N / (NS * RP);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = t + u * T;
+        const int k = j % NS;
+        cf b[RP], c[RP];
+#pragma unroll
+        for (int r = 0; r < RP; ++r) { b[r] = v[u + r * U]; c[r] = w[u + r * U]; }
+        if constexpr (NS > 1) {
+#pragma unroll
+            for (int r = 1; r < RP; ++r) {
+                const cf f = tw[r * k * TS];
+                b[r] = mul(b[r], f);
+                c[r] = mul(c[r], f);
+            }
+        }
+        dft<RP>(b);
+        dft<RP>(c);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int r = 0; r < RP; ++r) { v[u + r * U] = b[r]; w[u + r * U] = c[r]; }
+        } else {
+            const int base = (j - k) * RP + k;
+#pragma unroll
+            for (int r = 0; r < RP; ++r) lds[lpad(base + r * NS)] = b[r];
+            wave_lds_sync();
+#pragma unroll
+            for (int q = 0; q < R; ++q) v[q] = lds[lpad(t + T * q)];
+            wave_lds_sync();
+#pragma unroll
+            for (int r = 0; r < RP; ++r) lds[lpad(base + r * NS)] = c[r];
+        }
+    }
+    if constexpr (!LAST) {
+        static_assert(LAST || U == 1, "two-signal exchange assumes one butterfly per lane");
+        wave_lds_sync();
+#pragma unroll
+        for (int q = 0; q < R; ++q) w[q] = lds[lpad(t + T * q)];
+        wave_lds_sync();
+    }
+}
+
+// Radix schedules of the team engine (product = N, each radix divides N/T).
+template <int N> struct TeamCfg;
+template <> struct TeamCfg<64> { static constexpr int T = 8; };     // 8 x 8
+template <> struct TeamCfg<128> { static constexpr int T = 8; };    // 16 x 8
+template <> struct TeamCfg<256> { static constexpr int T = 16; };   // 16 x 16
+template <> struct TeamCfg<512> { static constexpr int T = 32; };   // 16 x 16 x 2
+template <> struct TeamCfg<1024> { static constexpr int T = 64; };  // 16 x 16 x 4
+
+template <int N, int T>
+__device__ __forceinline__ void team_fft(cf (&v)[N / T], cf* lds, const cf* __restrict__ tw, int t) {
+    if constexpr (N == 64) {
+        team_pass<64, T, 8, 1, false>(v, lds, tw, t);
+        team_pass<64, T, 8, 8, true>(v, lds, tw, t);
+    } else if constexpr (N == 128) {
+        team_pass<128, T, 16, 1, false>(v, lds, tw, t);
+        team_pass<128, T, 8, 16, true>(v, lds, tw, t);
+    } else if constexpr (N == 256) {
+        team_pass<256, T, 16, 1, false>(v, lds, tw, t);
+        team_pass<256, T, 16, 16, true>(v, lds, tw, t);
+    } else if constexpr (N == 512) {
+        team_pass<512, T, 16, 1, false>(v, lds, tw, t);
+        team_pass<512, T, 16, 16, false>(v, lds, tw, t);
+        team_pass<512, T, 2, 256, true>(v, lds, tw, t);
+    } else {
+        static_assert(N == 1024, "team engine sizes: 64..1024");
+        team_pass<1024, T, 16, 1, false>(v, lds, tw, t);
+        team_pass<1024, T, 16, 16, false>(v, lds, tw, t);
+        team_pass<1024, T, 4, 256, true>(v, lds, tw, t);
+    }
+}
+
+// Forward transforms of two signals.  Passes whose radix equals N/T (one
+// butterfly per lane) share their twiddle loads between the two signals.
+template <int N, int T>
+__device__ __forceinline__ void team_fft2(cf (&v)[N / T], cf (&w)[N / T], cf* lds,
+                                          const cf* __restrict__ tw, int t) {
+    if constexpr (N == 64) {
+        team_pass<64, T, 8, 1, false>(v, lds, tw, t);
+        team_pass<64, T, 8, 1, false>(w, lds, tw, t);
+        team_pass2<64, T, 8, 8, true>(v, w, lds, tw, t);
+    } else if constexpr (N == 128) {
+        team_pass2<128, T, 16, 1, false>(v, w, lds, tw, t);
+        team_pass2<128, T, 8, 16, true>(v, w, lds, tw, t);
+    } else if constexpr (N == 256) {
+        team_pass2<256, T, 16, 1, false>(v, w, lds, tw, t);
+        team_pass2<256, T, 16, 16, true>(v, w, lds, tw, t);
+    } else if constexpr (N == 512) {
+        team_pass2<512, T, 16, 1, false>(v, w, lds, tw, t);
+        team_pass2<512, T, 16, 16, false>(v, w, lds, tw, t);
+        team_pass2<512, T, 2, 256, true>(v, w, lds, tw, t);
+    } else {
+        team_pass2<1024, T, 16, 1, false>(v, w, lds, tw, t);
+        team_pass2<1024, T, 16, 16, false>(v, w, lds, tw, t);
+        team_pass2<1024, T, 4, 256, true>(v, w, lds, tw, t);
+    }
+}
+
+}  // namespace ca

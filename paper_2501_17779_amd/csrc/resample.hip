@@ -1,0 +1,346 @@
+// Uniform arc-length resampling of closed polygons (section 2: Eq.
+// arc-length-param, then cubic-spline interpolation evaluated at the uniform
+// parameters t_n = n/N), followed by scaling to unit length and centering on
+// the node mean.  One workgroup per curve, persistent over the batch; each
+// workgroup owns a slot of global scratch for the cleaned vertex list and the
+// per-knot quantities.
+//
+// Spline: the periodic C2 cubic through (s_j, Q_j) has second derivatives
+// M_j solving the cyclic tridiagonal system
+//   h_{j-1} M_{j-1} + 2 (h_{j-1} + h_j) M_j + h_j M_{j+1} = 6 (D_j - D_{j-1}),
+//   D_j = (Q_{j+1} - Q_j) / h_j.
+// After Jacobi scaling its eigenvalues lie in [1/2, 3/2], so the inverse
+// decays at least like ((sqrt 3 - 1)/(sqrt 3 + 1))^d = 0.268^d with distance d.
+// Each chunk of kRsC consecutive knots is therefore solved on the periodic
+// extension truncated kRsW knots to either side (forward elimination from the
+// left end, backward elimination from the right end, meeting at the chunk's
+// right edge, then back substitution): the truncation changes M by at most
+// ~0.268^kRsW relative, far below FP32 rounding for kRsW = 12.
+#include <math.h>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace ca {
+
+constexpr int kRsNT = 256;
+constexpr int kRsW = 12;
+constexpr int kRsC = 16;
+constexpr int kRsMCap = 32768;   // raw vertices per curve
+
+struct RsSlot {
+    cf* Q;        // cleaned vertices            [cap]
+    double* s;    // knot parameters s_j in [0,1) [cap + 1]
+    float* h;     // normalised chord lengths     [cap]
+    cf* rhs;      // 6 (D_j - D_{j-1})            [cap]
+    cf* M;        // spline second derivatives    [cap]
+};
+
+__host__ __device__ inline int64_t rs_slot_bytes() {
+    return (int64_t)kRsMCap * (8 + 8 + 4 + 8 + 8) + 8 + 256;
+}
+
+__device__ __forceinline__ RsSlot rs_slot(unsigned char* base) {
+    RsSlot s;
+    s.s = reinterpret_cast<double*>(base);
+    s.Q = reinterpret_cast<cf*>(s.s + kRsMCap + 1);
+    s.rhs = s.Q + kRsMCap;
+    s.M = s.rhs + kRsMCap;
+    s.h = reinterpret_cast<float*>(s.M + kRsMCap);
+    return s;
+}
+
+__device__ __forceinline__ int wrapk(int i, int K) {
+    i %= K;
+    return i < 0 ? i + K : i;
+}
+
+// Block-wide reductions/scans on 256 threads (4 waves).
+__device__ __forceinline__ double rs_sum(double v, double* sh) {
+    v = team_sum<64>(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return sh[0] + sh[1] + sh[2] + sh[3];
+}
+__device__ __forceinline__ int rs_max(int v, int* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return max(max(sh[0], sh[1]), max(sh[2], sh[3]));
+}
+// Exclusive scan of doubles over the block; returns this thread's prefix and
+// the block total.
+__device__ __forceinline__ double rs_exscan(double v, double* sh, double& total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    __syncthreads();
+    if (lane == 63) sh[w] = incl;
+    __syncthreads();
+    double off = 0.0;
+    for (int k = 0; k < w; ++k) off += sh[k];
+    total = sh[0] + sh[1] + sh[2] + sh[3];
+    return off + incl - v;
+}
+
+// Local solve for knots [a0, a0 + kRsC) (indices mod K).
+__device__ void rs_local_solve(const RsSlot& S, int K, int a0) {
+    float al[kRsC];
+    cf de[kRsC];
+    // forward elimination from a0 - W (natural truncation M = 0 outside)
+    float hprev = S.h[wrapk(a0 - kRsW - 1, K)];
+    float alpha = 0.0f, cprev = 0.0f;
+    cf delta = {0.0f, 0.0f};
+#pragma unroll
+    for (int i = 0; i < kRsW + kRsC; ++i) {
+        const int j = wrapk(a0 - kRsW + i, K);
+        const float hj = S.h[j];
+        const cf d = S.rhs[j];
+        const float b = 2.0f * (hprev + hj);
+        if (i == 0) {
+            alpha = b;
+            delta = d;
+        } else {
+            const float f = hprev / alpha;     // a_j / alpha_{j-1}, a_j = h_{j-1}
+            alpha = b - f * cprev;             // c_{j-1} = h_{j-1}
+            delta = {d.x - f * delta.x, d.y - f * delta.y};
+        }
+        cprev = hj;
+        hprev = hj;
+        if (i >= kRsW) { al[i - kRsW] = alpha; de[i - kRsW] = delta; }
+    }
+    // backward elimination from e + W - 1 down to e = a0 + C
+    const int e = a0 + kRsC;
+    float hnext = S.h[wrapk(e + kRsW - 1, K)];   // h_{last}
+    float beta = 0.0f, anext = 0.0f;
+    cf eps = {0.0f, 0.0f};
+#pragma unroll
+    for (int i = kRsW - 1; i >= 0; --i) {
+        const int j = wrapk(e + i, K);
+        const float hj = S.h[j];
+        const float hjm = S.h[wrapk(e + i - 1, K)];
+        const cf d = S.rhs[j];
+        const float b = 2.0f * (hjm + hj);
+        if (i == kRsW - 1) {
+            beta = b;
+            eps = d;
+        } else {
+            const float g = hj / beta;          // c_j / beta_{j+1}, c_j = h_j
+            beta = b - g * anext;               // a_{j+1} = h_j
+            eps = {d.x - g * eps.x, d.y - g * eps.y};
+        }
+        anext = hjm;   // a_j = h_{j-1}, used by the next (smaller) j
+        (void)hnext;
+    }
+    // meet at e: a_e M_{e-1} + beta_e M_e = eps_e, alpha_{e-1} M_{e-1} + c_{e-1} M_e = delta_{e-1}
+    const float ae = S.h[wrapk(e - 1, K)];       // a_e = h_{e-1} = c_{e-1}
+    const float ce1 = ae;
+    const float aL = al[kRsC - 1];
+    const cf dL = de[kRsC - 1];
+    const float den = beta - ae * ce1 / aL;
+    cf Me = {(eps.x - ae * dL.x / aL) / den, (eps.y - ae * dL.y / aL) / den};
+    cf Mnext = Me;
+#pragma unroll
+    for (int i = kRsC - 1; i >= 0; --i) {
+        const int j = a0 + i;
+        const float cj = S.h[wrapk(j, K)];
+        const cf Mi = {(de[i].x - cj * Mnext.x) / al[i], (de[i].y - cj * Mnext.y) / al[i]};
+        if (j < K) S.M[j] = Mi;
+        Mnext = Mi;
+    }
+}
+
+__global__ __launch_bounds__(kRsNT) void k_resample(const cf* __restrict__ raw, const int64_t* __restrict__ raw_off,
+                                                    int64_t num_curves, const int64_t* __restrict__ out_off,
+                                                    cf* __restrict__ out, double* __restrict__ norms,
+                                                    uint32_t* __restrict__ flags, int mode,
+                                                    unsigned char* __restrict__ scratch, int64_t slot_bytes) {
+    __shared__ double shd[4];
+    __shared__ int shi[4];
+    const RsSlot S = rs_slot(scratch + (int64_t)blockIdx.x * slot_bytes);
+    const int tid = threadIdx.x;
+    for (int64_t c = blockIdx.x; c < num_curves; c += gridDim.x) {
+        const int64_t r0 = raw_off[c];
+        const int64_t mraw = raw_off[c + 1] - r0;
+        const int64_t o0 = out_off[c];
+        const int N = (int)(out_off[c + 1] - o0);
+        cf* o = out + o0;
+        uint32_t fl = 0;
+        if (mraw < 1 || mraw > kRsMCap) fl = CA_FLAG_UNSUPPORTED_N;
+        const cf* P = raw + r0;
+        int M = (int)(fl ? 0 : mraw);
+
+        // non-finite check and trailing copies of the first vertex
+        int last = 0, bad = 0;
+        const cf P0 = M > 0 ? P[0] : cf{0.0f, 0.0f};
+        for (int j = tid; j < M; j += kRsNT) {
+            const cf p = P[j];
+            if (!(isfinite(p.x) && isfinite(p.y))) bad = 1;
+            if (p.x != P0.x || p.y != P0.y) last = max(last, j);
+        }
+        if (rs_max(bad, shi)) fl |= CA_FLAG_NONFINITE;
+        const int mt = rs_max(last, shi) + 1;
+
+        // compaction: keep j iff j == 0 or P_j != P_{j-1}
+        int K = 0;
+        if (!fl) {
+            for (int base = 0; base < mt; base += kRsNT) {
+                const int j = base + tid;
+                bool keep = false;
+                cf p = {0.0f, 0.0f};
+                if (j < mt) {
+                    p = P[j];
+                    if (j == 0) keep = true;
+                    else { const cf pp = P[j - 1]; keep = (p.x != pp.x || p.y != pp.y); }
+                }
+                const uint64_t msk = __ballot(keep);
+                const int lane = tid & 63;
+                const int pre = __popcll(msk & ((1ull << lane) - 1ull));
+                __syncthreads();
+                if (lane == 0) shi[tid >> 6] = __popcll(msk);
+                __syncthreads();
+                int woff = 0;
+                for (int k = 0; k < (tid >> 6); ++k) woff += shi[k];
+                if (keep) S.Q[K + woff + pre] = p;
+                K += shi[0] + shi[1] + shi[2] + shi[3];
+            }
+        }
+        if (!fl && K < 3) fl = CA_FLAG_DEGENERATE;
+        __syncthreads();
+
+        // chord lengths and their FP64 exclusive scan: L_j = sum_{i<j} |Q_{i+1} - Q_i|
+        double L = 0.0;
+        if (!fl) {
+            double carry = 0.0;
+            for (int base = 0; base < K; base += kRsNT) {
+                const int j = base + tid;
+                double hj = 0.0;
+                if (j < K) {
+                    const cf a = S.Q[j], b = S.Q[j + 1 < K ? j + 1 : 0];
+                    const float dx = b.x - a.x, dy = b.y - a.y;
+                    const float hf = sqrtf(dx * dx + dy * dy);
+                    hj = hf;
+                    S.h[j] = hf;
+                }
+                double tot;
+                const double pre = rs_exscan(hj, shd, tot);
+                if (j < K) S.s[j] = carry + pre;
+                carry += tot;
+            }
+            L = carry;
+            if (!(L > 0.0)) fl = CA_FLAG_DEGENERATE;
+        }
+        __syncthreads();
+        const double invL = fl ? 0.0 : 1.0 / L;
+        if (!fl) {
+            for (int j = tid; j < K; j += kRsNT) {
+                S.s[j] *= invL;
+                S.h[j] = (float)((double)S.h[j] * invL);
+            }
+            if (tid == 0) S.s[K] = 1.0;
+        }
+        __syncthreads();
+        if (!fl && mode == CA_RESAMPLE_SPLINE) {
+            // right-hand sides 6 (D_j - D_{j-1})
+            for (int j = tid; j < K; j += kRsNT) {
+                const int jm = j > 0 ? j - 1 : K - 1, jp = j + 1 < K ? j + 1 : 0;
+                const cf qm = S.Q[jm], q = S.Q[j], qp = S.Q[jp];
+                const float hm = S.h[jm], hj = S.h[j];
+                const float Dx = (qp.x - q.x) / hj, Dy = (qp.y - q.y) / hj;
+                const float Dmx = (q.x - qm.x) / hm, Dmy = (q.y - qm.y) / hm;
+                S.rhs[j] = {6.0f * (Dx - Dmx), 6.0f * (Dy - Dmy)};
+            }
+            __syncthreads();
+            const int nchunks = (K + kRsC - 1) / kRsC;
+            for (int g = tid; g < nchunks; g += kRsNT) rs_local_solve(S, K, g * kRsC);
+            __syncthreads();
+        }
+
+        // evaluation at t_n = n/N: thread owns knots [a, b) and the nodes in [s_a N, s_b N)
+        double sx = 0.0, sy = 0.0;
+        if (!fl) {
+            const int per = (K + kRsNT - 1) / kRsNT;
+            const int a = tid * per;
+            const int b = min(a + per, K);
+            const float il = (float)invL;
+            if (a < b) {
+                const double dN = (double)N;
+                const int nlo = (int)ceil(S.s[a] * dN);
+                const int nhi = (b == K) ? N : (int)ceil(S.s[b] * dN);
+                int j = a;
+                for (int nn = nlo; nn < nhi; ++nn) {
+                    while (j + 1 < b && S.s[j + 1] * dN <= (double)nn) ++j;
+                    const int jp = j + 1 < K ? j + 1 : 0;
+                    const float hj = S.h[j];
+                    const float bb = (float)((double)nn / dN - S.s[j]);
+                    const float aa = hj - bb;
+                    const cf qj = S.Q[j], qp = S.Q[jp];
+                    cf z;
+                    if (mode == CA_RESAMPLE_SPLINE) {
+                        const cf mj = S.M[j], mp = S.M[jp];
+                        const float ih = 1.0f / hj;
+                        const float ca = aa * aa * aa * ih * (1.0f / 6.0f);
+                        const float cb = bb * bb * bb * ih * (1.0f / 6.0f);
+                        const float h6 = hj * hj * (1.0f / 6.0f);
+                        const float ua = aa * ih, ub = bb * ih;
+                        z.x = mj.x * ca + mp.x * cb + (qj.x - mj.x * h6) * ua + (qp.x - mp.x * h6) * ub;
+                        z.y = mj.y * ca + mp.y * cb + (qj.y - mj.y * h6) * ua + (qp.y - mp.y * h6) * ub;
+                    } else {
+                        const float ub = bb / hj, ua = 1.0f - ub;
+                        z.x = qj.x * ua + qp.x * ub;
+                        z.y = qj.y * ua + qp.y * ub;
+                    }
+                    z.x *= il;
+                    z.y *= il;
+                    o[nn] = z;
+                    sx += z.x;
+                    sy += z.y;
+                }
+            }
+        }
+        sx = rs_sum(sx, shd);
+        sy = rs_sum(sy, shd);
+        const float mx = (float)(sx / N), my = (float)(sy / N);
+        double q2 = 0.0;
+        for (int nn = tid; nn < N; nn += kRsNT) {
+            cf z;
+            if (fl) {
+                z = {0.0f, 0.0f};
+            } else {
+                z = o[nn];
+                z.x -= mx;
+                z.y -= my;
+            }
+            o[nn] = z;
+            q2 = fma((double)z.x, (double)z.x, fma((double)z.y, (double)z.y, q2));
+        }
+        q2 = rs_sum(q2, shd);
+        if (tid == 0) {
+            if (norms) norms[c] = q2 / N;
+            if (flags) flags[c] = fl;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_resample(const void* raw, const int64_t* raw_off, int64_t num_curves,
+                           const int64_t* out_off, void* out, double* norms, uint32_t* flags, int mode,
+                           void* scratch, int64_t slot_bytes, int64_t slots, hipStream_t s) {
+    const int64_t grid = num_curves < slots ? num_curves : slots;
+    hipLaunchKernelGGL(k_resample, dim3((unsigned)grid), dim3(kRsNT), 0, s, (const cf*)raw, raw_off,
+                       num_curves, out_off, (cf*)out, norms, flags, mode, (unsigned char*)scratch,
+                       slot_bytes);
+    return hipGetLastError();
+}
+
+int64_t resample_slot_bytes() { return rs_slot_bytes(); }
+int resample_max_raw() { return kRsMCap; }
+
+}  // namespace ca

@@ -1,0 +1,196 @@
+"""GPU parity of the alignment entry points against the FP64 oracle.
+
+Every case calls the HIP library through its C ABI (via the ctypes binding)
+on seeded inputs that the oracle resampled, and checks each pair with the
+acceptance rule in acceptance.py.
+"""
+import numpy as np
+import pytest
+
+import acceptance as acc
+import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ca():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2501_17779_amd as m
+    m.default_context(0)
+    return m
+
+
+def note(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def run_batch(ca, z1, z2, **kw):
+    note(f"align_batch B={z1.shape[0]} n={z1.shape[1]} {kw}")
+    res = ca.align_batch(gpu(z1), gpu(z2), **kw)
+    torch.cuda.synchronize()
+    return ca.to_numpy(res)
+
+
+@pytest.mark.parametrize("n", [64, 128, 256, 512, 1024])
+@pytest.mark.parametrize("rescore", ["top2", "window"])
+def test_team_engine_parity(ca, n, rescore):
+    B = 203 if n <= 256 else 77            # several teams/waves and a ragged tail
+    z1, z2 = inputs.batch(11 + n, B, n)
+    res = run_batch(ca, z1, z2, rescore=rescore)
+    st = acc.check_batch(res, z1, z2)
+    note(f"n={n} {rescore}: {st}")
+    assert np.all((res["flags"] & (ca.FLAG_DEGENERATE | ca.FLAG_NONFINITE)) == 0)
+    if rescore == "window":
+        # the FP64 window leaves a shift mismatch only at exact ties
+        assert st["shift_mismatch"] == 0
+
+
+@pytest.mark.parametrize("n", [2, 3, 12, 300, 315, 1000, 2048, 2187, 4096])
+def test_block_engine_parity(ca, n):
+    B = 24 if n >= 2048 else 40
+    if n < 16:
+        rng = np.random.default_rng(n)
+        z1 = (rng.normal(size=(B, n)) + 1j * rng.normal(size=(B, n))).astype(np.complex64)
+        z2 = (rng.normal(size=(B, n)) + 1j * rng.normal(size=(B, n))).astype(np.complex64)
+    else:
+        z1, z2 = inputs.batch(500 + n, B, n)
+    for rescore in ("top2", "window"):
+        res = run_batch(ca, z1, z2, rescore=rescore)
+        st = acc.check_batch(res, z1, z2)
+        note(f"n={n} {rescore}: {st}")
+
+
+def test_fp64_single_pair(ca):
+    """The one-pair workload in FP64 (n = 256)."""
+    z1, z2, truth = inputs.single(17779, 256)
+    note("align_pair fp64 n=256")
+    res = ca.align_pair(gpu(z1), gpu(z2), precision="fp64")
+    torch.cuda.synchronize()
+    r = ca.to_numpy(res)[0]
+    acc.check_pair(r, z1, z2, theta_tol=1e-10, e_rtol=1e-10)
+    # the template is the same curve restarted s0 vertices later and rotated by theta0
+    assert abs(int(r["shift"]) - truth["s0"]) <= 2
+    assert abs(float(acc.oracle.wrap_angle(float(r["theta"]) + truth["theta0"]))) < 0.05
+
+
+def test_fp64_batch_block_sizes(ca):
+    for n in (128, 360, 1024):
+        z1, z2 = inputs.batch(900 + n, 16, n)
+        note(f"align_batch fp64 n={n}")
+        res = ca.to_numpy(ca.align_batch(gpu(z1.astype(np.complex128)), gpu(z2.astype(np.complex128)),
+                                         precision="fp64"))
+        acc.check_batch(res, z1.astype(np.complex128), z2.astype(np.complex128),
+                        theta_tol=1e-10, e_rtol=1e-10)
+
+
+def test_ragged_batch(ca):
+    d = inputs.ragged(31, 48)
+    note(f"ragged align_batch B=48 n in [{d['n'].min()}, {d['n'].max()}]")
+    res = ca.to_numpy(ca.align_batch(gpu(d["z1"]), gpu(d["z2"]), offsets=gpu(d["off"])))
+    torch.cuda.synchronize()
+    off = d["off"]
+    for b in range(48):
+        acc.check_pair(res[b], d["z1"][off[b]:off[b + 1]], d["z2"][off[b]:off[b + 1]])
+
+
+def test_ragged_unsupported_sizes_are_flagged(ca):
+    rng = np.random.default_rng(3)
+    sizes = [64, 11, 1, 5000, 128]        # 11: prime > 7; 1: too small; 5000: too large
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    z1 = (rng.normal(size=off[-1]) + 1j * rng.normal(size=off[-1])).astype(np.complex64)
+    z2 = (rng.normal(size=off[-1]) + 1j * rng.normal(size=off[-1])).astype(np.complex64)
+    note("ragged unsupported sizes")
+    res = ca.to_numpy(ca.align_batch(gpu(z1), gpu(z2), offsets=gpu(off)))
+    bad = (res["flags"] & ca.FLAG_UNSUPPORTED_N) != 0
+    assert list(bad) == [False, True, True, True, False]
+    for b in (0, 4):
+        acc.check_pair(res[b], z1[off[b]:off[b + 1]], z2[off[b]:off[b + 1]])
+
+
+@pytest.mark.parametrize("n", [64, 256, 1000, 1024])
+def test_exact_copy_and_paper_protocol(ca, n):
+    """Template = reference restarted at t = 0.25 and rotated by pi/3."""
+    z1 = inputs.batch(7, 1, n)[0][0].astype(np.complex128)
+    z2 = np.exp(1j * np.pi / 3) * np.roll(z1, -(n // 4))
+    a = np.stack([z1, z1]).astype(np.complex64)
+    b = np.stack([z2, z1]).astype(np.complex64)
+    res = run_batch(ca, a, b)
+    assert res["shift"][0] == n // 4 and res["shift"][1] == 0
+    assert abs(res["theta"][0] + np.pi / 3) < 1e-5 and abs(res["theta"][1]) < 1e-6
+    acc.check_batch(res, a, b)
+
+
+def test_swap_symmetry(ca):
+    z1, z2 = inputs.batch(44, 64, 512)
+    r12 = run_batch(ca, z1, z2)
+    r21 = run_batch(ca, z2, z1)
+    ok = (r12["flags"] & ca.FLAG_NEAR_TIE) == 0
+    assert np.all(r21["shift"][ok] == (512 - r12["shift"][ok]) % 512)
+    assert np.max(np.abs(acc.oracle.wrap_angle(r12["theta"][ok] + r21["theta"][ok]))) < 2e-5
+    assert np.allclose(r12["e0"], r21["e0"], rtol=1e-9, atol=1e-14)
+
+
+def test_degenerate_and_nonfinite(ca):
+    z1, z2 = inputs.batch(45, 4, 256)
+    z1 = z1.copy()
+    z2 = z2.copy()
+    z1[1] = 0
+    z2[2, 17] = np.nan
+    res = run_batch(ca, z1, z2)
+    assert res["flags"][1] & ca.FLAG_DEGENERATE and res["shift"][1] == 0
+    assert res["e0"][1] == pytest.approx(acc.oracle.sqnorm(z2[1]), rel=1e-12)
+    assert res["flags"][2] & ca.FLAG_NONFINITE and np.isnan(res["e0"][2])
+    acc.check_pair(res[0], z1[0], z2[0])
+    acc.check_pair(res[3], z1[3], z2[3])
+
+
+def test_invalid_arguments(ca):
+    z = gpu(np.zeros((2, 11), np.complex64))
+    with pytest.raises(ca.CurveAlignError) as e:
+        ca.align_batch(z, z)
+    assert e.value.status == ca.ERR_UNSUPPORTED_N
+    z = gpu(np.zeros((0, 64), np.complex64))
+    out = ca.align_batch(z, z)        # empty batch: no-op
+    assert out.shape == (0, 24)
+    z = gpu(np.zeros((2, 128), np.complex64))
+    with pytest.raises(ValueError):
+        ca.align_batch(z, z, precision="fp16")
+
+
+def test_theta_from_fp64(ca):
+    z1, z2 = inputs.batch(46, 64, 1024)
+    res = run_batch(ca, z1, z2, theta_fp64=True)
+    assert np.all(res["flags"] & ca.FLAG_THETA_FP64)
+    acc.check_batch(res, z1, z2, theta_tol=1e-6)
+
+
+def test_determinism(ca):
+    z1, z2 = inputs.batch(47, 256, 1024)
+    a = run_batch(ca, z1, z2)
+    b = run_batch(ca, z1, z2)
+    assert a.tobytes() == b.tobytes()
+
+
+def test_full_size_batch_sampled():
+    """65,536 pairs at n = 1024 in the benchmark's launch configuration;
+    sampled pairs checked against the oracle one by one."""
+    import paper_2501_17779_amd as ca
+    from synth import curves
+    B, n = 65536, 1024
+    r1, r2 = curves.batch_pairs(17780, B, n)
+    z1 = (r1[..., 0] + 1j * r1[..., 1]).astype(np.complex64)
+    z2 = (r2[..., 0] + 1j * r2[..., 1]).astype(np.complex64)
+    res = run_batch(ca, z1, z2)
+    idx = np.random.default_rng(0).choice(B, 48, replace=False)
+    st = acc.check_batch(res[idx], z1[idx], z2[idx])
+    note(f"full size sampled: {st}")
+    assert np.all((res["flags"] & (ca.FLAG_DEGENERATE | ca.FLAG_NONFINITE)) == 0)

@@ -1,0 +1,114 @@
+"""GPU parity of resample_arclength against the FP64 oracle resampler."""
+import numpy as np
+import pytest
+
+from oracle import resample_ref as rr
+from synth import curves
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# Node tolerance: FP32 chord lengths, spline solve and evaluation on curves of
+# unit length; the positions carry a few FP32 ulps of the raw coordinates
+# (|raw| ~ 1, perimeter ~ 6.5), i.e. ~1e-7 after scaling by 1/L.
+TOL_POS = 2e-6
+
+
+@pytest.fixture(scope="module")
+def ca():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2501_17779_amd as m
+    m.default_context(0)
+    return m
+
+
+def note(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def run(ca, polys, ns, mode):
+    raw = np.concatenate([p[:, 0] + 1j * p[:, 1] for p in polys]).astype(np.complex64)
+    roff = np.zeros(len(polys) + 1, np.int64)
+    roff[1:] = np.cumsum([len(p) for p in polys])
+    ooff = np.zeros(len(polys) + 1, np.int64)
+    ooff[1:] = np.cumsum(ns)
+    note(f"resample {len(polys)} curves mode={mode}")
+    out, norms, flags = ca.resample_arclength(torch.from_numpy(raw).cuda(), torch.from_numpy(roff).cuda(),
+                                              torch.from_numpy(ooff).cuda(), mode=mode)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), ooff, norms.cpu().numpy(), flags.cpu().numpy()
+
+
+@pytest.mark.parametrize("mode", ["spline", "linear"])
+def test_resample_parity(ca, mode):
+    d = curves.ragged_pairs(77, 40, 64, 4096)
+    polys = [d["raw1"][d["off1"][b]:d["off1"][b + 1]] for b in range(40)]
+    polys += [d["raw2"][d["off2"][b]:d["off2"][b + 1]] for b in range(40)]
+    ns = np.concatenate([d["n"], d["n"]])
+    out, ooff, norms, flags = run(ca, polys, ns, mode)
+    m = rr.SPLINE if mode == "spline" else rr.LINEAR
+    worst = 0.0
+    for c, p in enumerate(polys):
+        z, info = rr.resample(p.astype(np.float64), int(ns[c]), m)
+        g = out[ooff[c]:ooff[c + 1]]
+        err = np.max(np.abs(g - z))
+        worst = max(worst, err)
+        assert err <= TOL_POS, f"curve {c}: node error {err:.3g}"
+        assert abs(norms[c] - np.mean(np.abs(g.astype(np.complex128)) ** 2)) < 1e-12
+        assert flags[c] == 0
+    note(f"resample {mode}: worst node error {worst:.3g}")
+
+
+def test_resample_small_and_worked_example(ca):
+    sq = np.array([[0, 0], [1, 0], [1, 1], [0, 1]], np.float32)
+    tri = np.array([[0, 0], [3, 0], [3, 4]], np.float32)
+    polys = [sq, sq, tri, sq * 7 + 2]
+    ns = [8, 8, 30, 16]
+    for mode in ("spline", "linear"):
+        out, ooff, norms, flags = run(ca, polys, ns, mode)
+        m = rr.SPLINE if mode == "spline" else rr.LINEAR
+        for c, p in enumerate(polys):
+            z, _ = rr.resample(p.astype(np.float64), ns[c], m)
+            assert np.max(np.abs(out[ooff[c]:ooff[c + 1]] - z)) < 1e-6
+
+
+def test_resample_cleaning_and_degenerate(ca):
+    rng = np.random.default_rng(5)
+    ang = np.sort(rng.uniform(0, 2 * np.pi, 50))
+    P = np.stack([np.cos(ang), np.sin(ang)], 1).astype(np.float32)
+    dup = np.vstack([P[:10], P[9:10], P[9:10], P[10:], P[:1], P[:1]])
+    line = np.array([[0, 0], [1, 1], [1, 1], [0, 0]], np.float32)       # 2 distinct points
+    point = np.array([[2, 2]] * 6, np.float32)
+    nanp = P.copy()
+    nanp[3, 0] = np.nan
+    polys = [P, dup, line, point, nanp]
+    ns = [64, 64, 16, 16, 16]
+    out, ooff, norms, flags = run(ca, polys, ns, "spline")
+    assert np.max(np.abs(out[0:64] - out[64:128])) < 1e-6
+    assert flags[0] == 0 and flags[1] == 0
+    assert flags[2] & 8 and flags[3] & 8 and flags[4] & 16
+    assert np.all(out[128:] == 0)
+
+
+def test_resample_full_size_sampled(ca):
+    """The ragged workload's resampling launch (100,000 pairs, 200,000 curves)
+    with sampled curves checked against the oracle."""
+    B = 100000
+    d = curves.ragged_pairs(17782, B)
+    raw = np.concatenate([d["raw1"], d["raw2"]])
+    raw_c = (raw[:, 0] + 1j * raw[:, 1]).astype(np.complex64)
+    roff = np.concatenate([d["off1"], d["off2"][1:] + d["off1"][-1]])
+    ns = np.concatenate([d["n"], d["n"]]).astype(np.int64)
+    ooff = np.zeros(2 * B + 1, np.int64)
+    ooff[1:] = np.cumsum(ns)
+    note("resample full size")
+    out, _, flags = ca.resample_arclength(torch.from_numpy(raw_c).cuda(), torch.from_numpy(roff).cuda(),
+                                          torch.from_numpy(ooff).cuda())
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    assert int((flags != 0).sum().item()) == 0
+    for c in np.random.default_rng(2).choice(2 * B, 40, replace=False):
+        z, _ = rr.resample(raw[roff[c]:roff[c + 1]].astype(np.float64), int(ns[c]))
+        assert np.max(np.abs(out[ooff[c]:ooff[c + 1]] - z)) <= TOL_POS
