@@ -59,13 +59,16 @@ enum {
     CA_ERR_INTERNAL = -6
 };
 
-/* Per-pair result: 24 bytes, 8-byte aligned. */
+/* Per-pair result: 32 bytes, 8-byte aligned. */
 typedef struct {
-    int32_t shift;    /* optimal correlation shift s* in [0, n)                     */
-    uint32_t flags;   /* CA_FLAG_* bits                                             */
-    float theta;      /* arg C(s*), radians in (-pi, pi]                            */
-    float err_est;    /* relative half-width of the FP32 |C| error bound at s*      */
-    double e0;        /* n1 + n2 - 2|C(s*)|/n with |C(s*)| and n_i in FP64          */
+    int32_t shift;    /* optimal correlation shift s* in [0, n)                      */
+    uint32_t flags;   /* CA_FLAG_* bits                                              */
+    double theta;     /* arg C(s*), radians in (-pi, pi], from the path's own C
+                         (FP32, FP64 or split-BF16) unless theta_fp64 is set          */
+    double e0;        /* n1 + n2 - 2|C(s*)|/n with |C(s*)| and n_i in FP64           */
+    float err_est;    /* relative half-width of the path's |C| error bound at s*     */
+    float gap;        /* (|C|best - |C|runner-up) / |C|best, FP64 values when more
+                         than one shift was re-scored, else the path's own values     */
 } ca_result_t;
 
 enum {

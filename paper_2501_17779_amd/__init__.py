@@ -5,9 +5,9 @@ kernels behind the C ABI declared in include/curvealign.h.  Tensors are torch
 CUDA (HIP) tensors used as device memory; calls are enqueued on the current
 torch stream unless a stream is given.
 
-Result records (24 bytes each) are returned as a uint8 CUDA tensor of shape
-[count, 24]; `unpack` turns them into named tensors or `to_numpy` into a
-numpy structured array with fields shift, flags, theta, err_est, e0.
+Result records (32 bytes each) are returned as a uint8 CUDA tensor of shape
+[count, 32]; `unpack` turns them into named tensors or `to_numpy` into a
+numpy structured array with fields shift, flags, theta, e0, err_est, gap.
 """
 from __future__ import annotations
 
@@ -20,8 +20,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcurvealign.so")
 
-RESULT_DTYPE = np.dtype([("shift", "<i4"), ("flags", "<u4"), ("theta", "<f4"),
-                         ("err_est", "<f4"), ("e0", "<f8")])
+RESULT_DTYPE = np.dtype([("shift", "<i4"), ("flags", "<u4"), ("theta", "<f8"),
+                         ("e0", "<f8"), ("err_est", "<f4"), ("gap", "<f4")])
+RESULT_BYTES = RESULT_DTYPE.itemsize
 
 OK = 0
 ERR_INVALID_ARG = -1
@@ -167,17 +168,17 @@ def _require(t, what, dtypes, ndim=None):
 
 def empty_results(count: int, device):
     import torch
-    return torch.empty((int(count), 24), dtype=torch.uint8, device=device)
+    return torch.empty((int(count), RESULT_BYTES), dtype=torch.uint8, device=device)
 
 
 def unpack(res):
-    """Named views of a [count, 24] uint8 result tensor (no copies)."""
+    """Named views of a [count, 32] uint8 result tensor (no copies)."""
     import torch
-    w32 = res.view(torch.int32).view(-1, 6)
-    return {"shift": w32[:, 0], "flags": w32[:, 1],
-            "theta": res.view(torch.float32).view(-1, 6)[:, 2],
-            "err_est": res.view(torch.float32).view(-1, 6)[:, 3],
-            "e0": res.view(torch.float64).view(-1, 3)[:, 2]}
+    w32 = res.view(torch.int32).view(-1, 8)
+    f32 = res.view(torch.float32).view(-1, 8)
+    f64 = res.view(torch.float64).view(-1, 4)
+    return {"shift": w32[:, 0], "flags": w32[:, 1], "theta": f64[:, 1], "e0": f64[:, 2],
+            "err_est": f32[:, 6], "gap": f32[:, 7]}
 
 
 def to_numpy(res) -> np.ndarray:

@@ -39,32 +39,33 @@ __device__ __forceinline__ double wrap_pi(double a) {
 
 __device__ __forceinline__ void finish(ca_result_t& res, const Pick& pk, int n, double n1, double n2,
                                        double d1, double d2, double epsD, bool capped,
-                                       float theta_path, int theta64) {
+                                       double theta_path, int theta64) {
     uint32_t flags = 0;
     const double c64 = sqrt(pk.best);
     if (pk.count > 1) flags |= CA_FLAG_RESCORED;
     if (capped) flags |= CA_FLAG_CAND_CAPPED;
-    if (pk.count > 1 && pk.second >= 0.0) {
-        if (c64 - sqrt(pk.second) < kNearTie * c64) flags |= CA_FLAG_NEAR_TIE;
-    } else if (d1 - d2 < kNearTie * d1) {
-        flags |= CA_FLAG_NEAR_TIE;
-    }
-    float th = theta_path;
+    double gap;
+    if (pk.count > 1 && pk.second >= 0.0) gap = (c64 - sqrt(pk.second)) / c64;
+    else gap = (d1 - d2) / d1;
+    if (gap < kNearTie) flags |= CA_FLAG_NEAR_TIE;
+    double th = theta_path;
     if (theta64) {
-        th = (float)wrap_pi(atan2(pk.im, pk.re));
+        th = wrap_pi(atan2(pk.im, pk.re));
         flags |= CA_FLAG_THETA_FP64;
     }
     res.shift = pk.shift;
     res.flags = flags;
     res.theta = th;
     res.err_est = (float)(2.0 * epsD / d1);
+    res.gap = (float)gap;
     res.e0 = n1 + n2 - 2.0 * c64 / (double)n;
 }
 
 __device__ __forceinline__ bool special_case(ca_result_t& res, double n1, double n2, double bv) {
     res.shift = 0;
-    res.theta = 0.0f;
+    res.theta = 0.0;
     res.err_est = 0.0f;
+    res.gap = 0.0f;
     if (!(isfinite(n1) && isfinite(n2) && isfinite(bv))) {
         res.flags = CA_FLAG_NONFINITE;
         res.e0 = __builtin_nan("");
@@ -159,7 +160,7 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
         if (q == qs) sel = d[q];
     sel.x = __shfl(sel.x, ls, T);
     sel.y = __shfl(sel.y, ls, T);
-    const float thp = wrap_pi(atan2f(-sel.y, sel.x));
+    const double thp = (double)wrap_pi(atan2f(-sel.y, sel.x));
     finish(res, pk, N, n1, n2, d1, d2, epsD, capped, thp, theta64);
     return res;
 }
@@ -387,7 +388,7 @@ __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1,
     if (n == 0 || plans[n].n != n) {
         if (threadIdx.x == 0) {
             ca_result_t r;
-            r.shift = 0; r.flags = CA_FLAG_UNSUPPORTED_N; r.theta = 0.0f; r.err_est = 0.0f;
+            r.shift = 0; r.flags = CA_FLAG_UNSUPPORTED_N; r.theta = 0.0; r.err_est = 0.0f; r.gap = 0.0f;
             r.e0 = __builtin_nan("");
             out[pair] = r;
         }
@@ -478,7 +479,7 @@ __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1,
             if (d1 - d2 < 2.0 * epsD) rescore_one(ci);
         }
         const cpx<T> sel = A[pk.shift];
-        const float thp = (float)wrap_pi(atan2((double)-sel.y, (double)sel.x));
+        const double thp = wrap_pi(atan2(-(double)sel.y, (double)sel.x));
         finish(res, pk, n, n1, n2, d1, d2, epsD, capped, thp, theta64);
     }
     if (threadIdx.x == 0) out[pair] = res;

@@ -43,7 +43,7 @@ template <> struct num<float> { static constexpr double u = 5.9604644775390625e-
 template <> struct num<double> { static constexpr double u = 1.1102230246251565e-16; };  // 2^-53
 
 // Result record, identical layout to ca_result_t.
-static_assert(sizeof(ca_result_t) == 24, "ca_result_t must be 24 bytes");
+static_assert(sizeof(ca_result_t) == 32, "ca_result_t must be 32 bytes");
 
 // Ordering of the LDS accesses of one wave: the fences stop the compiler from
 // moving LDS reads above LDS writes (and back); a wave's LDS operations are

@@ -206,3 +206,135 @@ def ragged_pairs(seed: int, B: int, nmin: int = 64, nmax: int = 4096,
     off2[1:] = np.cumsum(m2s)
     return {"raw1": np.concatenate(r1), "raw2": np.concatenate(r2),
             "off1": off1, "off2": off2, "n": n}
+
+
+# ----------------------------------------------------------------------------
+# The same curve families drawn with torch on a device (fast at full size).
+# Streams differ from the numpy versions above but are seeded the same way
+# (one torch.Generator per call).
+
+def _t_coeffs(gen, B, K, A, device, grid_pts=4096):
+    import torch
+    K = torch.as_tensor(K, device=device).expand(B)
+    k = torch.arange(1, KMAX + 1, device=device, dtype=torch.float64)
+    out = torch.zeros(B, KMAX, dtype=torch.complex128, device=device)
+    todo = torch.arange(B, device=device)
+    tg = torch.linspace(0, TWO_PI, grid_pts + 1, device=device, dtype=torch.float64)[:-1]
+    grid = torch.exp(1j * torch.outer(k, tg))                # (KMAX, G)
+    while todo.numel():
+        a = torch.randn(todo.numel(), KMAX, generator=gen, device=device, dtype=torch.float64) * (A / k)
+        phi = torch.rand(todo.numel(), KMAX, generator=gen, device=device, dtype=torch.float64) * TWO_PI
+        a = torch.where(k[None, :] > K[todo][:, None], torch.zeros_like(a), a)
+        cc = a * torch.exp(1j * phi)
+        r = 1.0 + (cc @ grid).real
+        ok = r.min(dim=1).values > 0.05
+        out[todo[ok]] = cc[ok]
+        todo = todo[~ok]
+    return out
+
+
+def _t_star(c, t, seg=None):
+    """z(t) with per-row coefficients c (R, KMAX); t is (R, M), or flat with
+    segment ids `seg` mapping each parameter to its coefficient row."""
+    import torch
+    w = torch.exp(1j * t)
+    acc = torch.zeros_like(w)
+    for k in range(KMAX, 0, -1):
+        ck = c[:, k - 1]
+        acc = (acc + (ck[seg] if seg is not None else ck[:, None])) * w
+    return (1.0 + acc.real) * w
+
+
+def _t_xy32(z):
+    import torch
+    return torch.stack([z.real, z.imag], dim=-1).to(torch.float32)
+
+
+def batch_pairs_torch(seed: int, B: int, n_raw: int, device, kmin: int = 8, kmax: int = 16,
+                      A: float = 0.1, sigma_max: float = 1e-2, jitter: float = 0.4,
+                      chunk: int = 8192):
+    """Device version of batch_pairs: float32 tensors (B, n_raw, 2)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    raw1 = torch.empty(B, n_raw, 2, dtype=torch.float32, device=device)
+    raw2 = torch.empty_like(raw1)
+    j = torch.arange(n_raw, device=device, dtype=torch.float64)
+    for lo in range(0, B, chunk):
+        b = min(B, lo + chunk) - lo
+        K = torch.randint(kmin, kmax + 1, (b,), generator=gen, device=device)
+        c = _t_coeffs(gen, b, K, A, device)
+        raw1[lo:lo + b] = _t_xy32(_t_star(c, (j * (TWO_PI / n_raw)).expand(b, n_raw)))
+        theta0 = torch.rand(b, 1, generator=gen, device=device, dtype=torch.float64) * TWO_PI
+        tau = torch.rand(b, 1, generator=gen, device=device, dtype=torch.float64) * TWO_PI
+        sigma = torch.rand(b, 1, generator=gen, device=device, dtype=torch.float64) * sigma_max
+        u = (torch.rand(b, n_raw, generator=gen, device=device, dtype=torch.float64) * 2 - 1) * jitter
+        t2 = (j[None, :] + u) * (TWO_PI / n_raw) + tau
+        z2 = torch.exp(1j * theta0) * _t_star(c, t2)
+        nz = torch.randn(b, n_raw, 2, generator=gen, device=device, dtype=torch.float64)
+        z2 = z2 + sigma * (nz[..., 0] + 1j * nz[..., 1])
+        raw2[lo:lo + b] = _t_xy32(z2)
+    return raw1, raw2
+
+
+def gallery_torch(seed: int, M: int, n_raw: int, device, K: int = 16, A: float = 0.2):
+    """Device version of gallery: float32 tensor (M, n_raw, 2)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    c = _t_coeffs(gen, M, K, A, device)
+    j = torch.arange(n_raw, device=device, dtype=torch.float64)
+    return _t_xy32(_t_star(c, (j * (TWO_PI / n_raw)).expand(M, n_raw)))
+
+
+def ragged_pairs_torch(seed: int, B: int, device, nmin: int = 64, nmax: int = 4096,
+                       ratio=(1.2, 5.0), A: float = 0.1, sigma_max: float = 1e-2,
+                       jitter: float = 0.4, chunk: int = 8192):
+    """Device version of ragged_pairs.  Returns dict of device tensors:
+    raw1, raw2 complex64 flat; off1, off2 int64 (B+1); n int32 (B)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    cand = torch.as_tensor(smooth7(nmin, nmax), device=device)
+    logc = torch.log(cand.double())
+    draw = torch.rand(B, generator=gen, device=device, dtype=torch.float64)
+    draw = math.log(nmin) + draw * (math.log(nmax) - math.log(nmin))
+    N = cand[(logc[None, :] - draw[:, None]).abs().argmin(dim=1)]
+    out = {"n": N.to(torch.int32)}
+    for which in (1, 2):
+        rr = torch.rand(B, generator=gen, device=device, dtype=torch.float64)
+        Mc = torch.clamp(torch.round((ratio[0] + rr * (ratio[1] - ratio[0])) * N.double()), min=8).long()
+        off = torch.zeros(B + 1, dtype=torch.int64, device=device)
+        off[1:] = torch.cumsum(Mc, 0)
+        out[f"off{which}"] = off
+        out[f"_m{which}"] = Mc
+    raws = {1: torch.empty(int(out["off1"][-1]), dtype=torch.complex64, device=device),
+            2: torch.empty(int(out["off2"][-1]), dtype=torch.complex64, device=device)}
+    for lo in range(0, B, chunk):
+        b = min(B, lo + chunk) - lo
+        K = torch.randint(8, 17, (b,), generator=gen, device=device)
+        c = _t_coeffs(gen, b, K, A, device)
+        theta0 = torch.rand(b, generator=gen, device=device, dtype=torch.float64) * TWO_PI
+        tau = torch.rand(b, generator=gen, device=device, dtype=torch.float64) * TWO_PI
+        sigma = torch.rand(b, generator=gen, device=device, dtype=torch.float64) * sigma_max
+        for which in (1, 2):
+            off = out[f"off{which}"]
+            Mc = out[f"_m{which}"][lo:lo + b]
+            p0, p1 = int(off[lo]), int(off[lo + b])
+            seg = torch.repeat_interleave(torch.arange(b, device=device), Mc)
+            jj = torch.arange(p1 - p0, device=device) - (off[lo:lo + b] - p0)[seg]
+            alpha = torch.rand(b, generator=gen, device=device, dtype=torch.float64) * 0.5
+            psi = torch.rand(b, generator=gen, device=device, dtype=torch.float64) * TWO_PI
+            u = (torch.rand(p1 - p0, generator=gen, device=device, dtype=torch.float64) * 2 - 1) * jitter
+            t = (jj.double() + u) * (TWO_PI / Mc.double()[seg])
+            t = t + alpha[seg] * torch.sin(t - psi[seg])
+            if which == 1:
+                z = _t_star(c, t, seg)
+            else:
+                z = torch.exp(1j * theta0[seg]) * _t_star(c, t + tau[seg], seg)
+                nz = torch.randn(p1 - p0, 2, generator=gen, device=device, dtype=torch.float64)
+                z = z + sigma[seg] * (nz[:, 0] + 1j * nz[:, 1])
+            raws[which][p0:p1] = z.to(torch.complex64)
+    out["raw1"], out["raw2"] = raws[1], raws[2]
+    del out["_m1"], out["_m2"]
+    return out

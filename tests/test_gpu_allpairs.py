@@ -57,10 +57,10 @@ def test_all_pairs_full_size_sampled(ca):
     configuration; sampled pairs checked one by one against the oracle."""
     from synth import curves
     M, n = 4096, 512
-    raw = curves.gallery(17781, M, n)
-    g = (raw[..., 0] + 1j * raw[..., 1]).astype(np.complex64)
+    gt = torch.view_as_complex(curves.gallery_torch(17781, M, n, "cuda")).contiguous()
+    g = gt.cpu().numpy()
     note("align_all_pairs full size")
-    out = ca.align_all_pairs(torch.from_numpy(g).cuda())
+    out = ca.align_all_pairs(gt)
     torch.cuda.synchronize()
     rng = np.random.default_rng(1)
     rows = []
