@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="batch",
-                    choices=["batch", "pair", "allpairs", "ragged", "bf16"])
+                    choices=["batch", "pair", "allpairs", "ragged", "bf16", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target wall time of the CPU oracle sample")
@@ -135,6 +135,20 @@ def bench_batch(args, torch, ca):
     return line
 
 
+def bench_copy(args, torch, ca):
+    """A plain device-to-device copy of 1 GiB: the reference reading for the
+    rocprofv3 FETCH_SIZE / WRITE_SIZE counters (bytes moved are known)."""
+    nbytes = 1 << 30
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    ms, _ = time_steps(lambda: dst.copy_(src), args.steps, args.warmup, torch)
+    gbs = 2 * nbytes / (ms * 1e-3) / 1e9
+    return {"metric": "device copy bandwidth", "value": gbs, "unit": "GB/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "copy of 1 GiB (read 1 GiB + write 1 GiB)", "bytes": nbytes}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -147,7 +161,7 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     ca.default_context(0)
-    fn = {"batch": bench_batch}[args.config]
+    fn = {"batch": bench_batch, "copy": bench_copy}[args.config]
     line = fn(args, torch, ca)
     print(json.dumps(line), flush=True)
 
