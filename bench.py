@@ -135,6 +135,127 @@ def bench_batch(args, torch, ca):
     return line
 
 
+HEADLINE_METRIC = "curve-pair alignments/sec at N=1024, FP32 vs split-BF16, err vs FP64 oracle"
+# FP32 and FP64 vector issue peaks without packed FP32 instructions (not used
+# by this build): 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz.
+VALU_FP32_PEAK_TFLOPS = 78.6
+
+
+def base_line(args, value, unit, ms, dtype, config, higher=True):
+    return {"metric": HEADLINE_METRIC if config.get("headline") else config["workload"],
+            "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms, "higher_is_better": higher, "scaling": "weak", "vs_baseline": None,
+            "dtype": dtype, "data": "synthetic",
+            "config": {k: v for k, v in config.items() if k != "headline"}}
+
+
+def bench_pair(args, torch, ca):
+    """One pair, n = 256, FP64 block engine: latency of one align_pair call."""
+    from synth import curves
+    dev = torch.device("cuda:0")
+    r1, r2 = curves.batch_pairs_torch(17779, 1, 256, dev, kmin=8, kmax=8, sigma_max=1e-3)
+    raw = torch.view_as_complex(torch.cat([r1, r2]).reshape(-1, 2)).contiguous()
+    off = torch.arange(0, 3, dtype=torch.int64, device=dev) * 256
+    nodes, _, _ = ca.resample_arclength(raw, off, off)
+    z = nodes.to(torch.complex128)
+    z1, z2 = z[:256].contiguous(), z[256:].contiguous()
+    out = ca.empty_results(1, dev)
+    steps = max(args.steps, 200)
+    ms, _ = time_steps(lambda: ca.align_pair(z1, z2, precision="fp64", out=out), steps, args.warmup, torch)
+    line = base_line(args, 1e3 / ms, "pairs/s", ms, "f64",
+                     {"workload": "single curve pair, n=256 nodes, FP64 (latency of one call)",
+                      "pairs": 1, "n": 256})
+    line["steps"] = steps
+    line["us_per_call"] = ms * 1e3
+    return line
+
+
+def bench_allpairs(args, torch, ca):
+    """All 8,386,560 pairs of a 4096-curve gallery at n = 512, FP32."""
+    from synth import curves
+    M, n = 4096, 512
+    dev = torch.device("cuda:0")
+    raw = torch.view_as_complex(curves.gallery_torch(17781, M, 2048, dev).reshape(-1, 2)).contiguous()
+    roff = torch.arange(0, M + 1, dtype=torch.int64, device=dev) * 2048
+    ooff = torch.arange(0, M + 1, dtype=torch.int64, device=dev) * n
+    g, _, _ = ca.resample_arclength(raw, roff, ooff)
+    g = g.view(M, n)
+    P = M * (M - 1) // 2
+    out = ca.empty_results(P, dev)
+    ms, _ = time_steps(lambda: ca.align_all_pairs(g, out=out), args.steps, args.warmup, torch)
+    flops = P * (5 * n * 9 + 9 * n)       # correlation FFT + product + |C|^2, per pair
+    achieved = flops / (ms * 1e-3) / 1e12
+    line = base_line(args, P / (ms * 1e-3), "pairs/s", ms, "f32",
+                     {"workload": "all pairs of a 4096-curve gallery, n=512 nodes, FP32", "curves": M,
+                      "pairs": P, "n": n})
+    line["roofline"] = {"bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": achieved / VALU_FP32_PEAK_TFLOPS, "traffic": None}
+    if not args.no_cpu_baseline:
+        gh = g[:256].cpu().numpy()
+        ii, jj = np.triu_indices(256, 1)
+        k = min(len(ii), 8192)
+        cb = cpu_baseline_batch(np.stack([gh[ii[:k]].real, gh[ii[:k]].imag], -1),
+                                np.stack([gh[jj[:k]].real, gh[jj[:k]].imag], -1), n, args.cpu_seconds)
+        cb["sample"] = "pairs among the first 256 gallery curves; " + cb["sample"]
+        line["cpu_baseline"] = cb
+    return line
+
+
+def bench_ragged(args, torch, ca):
+    """100,000 pairs of raw polygons, n log-uniform in [64, 4096] (7-smooth),
+    1.2-5x more raw vertices than n: GPU resampling + ragged alignment per step."""
+    from synth import curves
+    B = 100000
+    dev = torch.device("cuda:0")
+    d = curves.ragged_pairs_torch(17782, B, dev)
+    raw = torch.cat([d["raw1"], d["raw2"]])
+    roff = torch.cat([d["off1"], d["off2"][1:] + d["off1"][-1]])
+    n = d["n"].long()
+    ooff = torch.zeros(2 * B + 1, dtype=torch.int64, device=dev)
+    ooff[1:] = torch.cumsum(torch.cat([n, n]), 0)
+    total = int(ooff[-1].item())
+    nodes = torch.empty(total, dtype=torch.complex64, device=dev)
+    off = ooff[: B + 1].contiguous()
+    half = int(off[-1].item())
+    out = ca.empty_results(B, dev)
+
+    def step():
+        ca.resample_arclength(raw, roff, ooff, out=nodes, with_norms=False, with_flags=False)
+        ca.align_batch(nodes[:half], nodes[half:], offsets=off, out=out)
+
+    ms, _ = time_steps(step, args.steps, args.warmup, torch)
+    algo = raw.numel() * 8 + B * RESULT_BYTES
+    achieved = algo / (ms * 1e-3) / 1e9
+    line = base_line(args, B / (ms * 1e-3), "pairs/s", ms, "f32",
+                     {"workload": "100000 ragged pairs of raw polygons, n in [64,4096], GPU resampling "
+                                  "+ alignment", "pairs": B, "raw_vertices": int(raw.numel()),
+                      "nodes": total})
+    line["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    return line
+
+
+def bench_small_batch(args, torch, ca):
+    """1,048,576 pairs at n = 128 (FP32 team engine; split-BF16 when available)."""
+    from synth import curves
+    B, n = 1 << 20, 128
+    dev = torch.device("cuda:0")
+    r1, r2 = curves.batch_pairs_torch(17783, B, n, dev, kmin=8, kmax=8, sigma_max=1e-3)
+    raw = torch.view_as_complex(torch.cat([r1, r2]).reshape(-1, 2)).contiguous()
+    roff = torch.arange(0, 2 * B + 1, dtype=torch.int64, device=dev) * n
+    nodes, _, _ = ca.resample_arclength(raw, roff, roff)
+    z1, z2 = nodes[: B * n].view(B, n), nodes[B * n:].view(B, n)
+    out = ca.empty_results(B, dev)
+    ms, _ = time_steps(lambda: ca.align_batch(z1, z2, out=out), args.steps, args.warmup, torch)
+    algo = B * (2 * n * 8 + RESULT_BYTES)
+    achieved = algo / (ms * 1e-3) / 1e9
+    line = base_line(args, B / (ms * 1e-3), "pairs/s", ms, "f32",
+                     {"workload": "batch of 1048576 curve pairs, n=128 nodes, FP32", "pairs": B, "n": n})
+    line["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    return line
+
+
 def bench_copy(args, torch, ca):
     """A plain device-to-device copy of 1 GiB: the reference reading for the
     rocprofv3 FETCH_SIZE / WRITE_SIZE counters (bytes moved are known)."""
@@ -161,7 +282,8 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     ca.default_context(0)
-    fn = {"batch": bench_batch, "copy": bench_copy}[args.config]
+    fn = {"batch": bench_batch, "copy": bench_copy, "pair": bench_pair, "allpairs": bench_allpairs,
+          "ragged": bench_ragged, "bf16": bench_small_batch}[args.config]
     line = fn(args, torch, ca)
     print(json.dumps(line), flush=True)
 

@@ -82,10 +82,11 @@ __device__ __forceinline__ bool special_case(ca_result_t& res, double n1, double
 // --------------------------------------------------------------- team engine
 // Epilogue of one pair held by a team: d[q] = D[t + T q] (D = n conj C),
 // a0[q] = z1[t + T q] (FP32 nodes of curve 1), zb = LDS copy of curve 2's
-// nodes at padded positions.  Returns the finished result (every lane).
+// nodes at padded positions, cand = the team's candidate list in LDS.
+// Returns the finished result (every lane).
 template <int N, int T>
 __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const cf (&a0)[N / T],
-                                                     const cf* zb, int t, double n1, double n2,
+                                                     const cf* zb, int* cand, int t, double n1, double n2,
                                                      int rescore, int theta64) {
     constexpr int R = N / T;
     float m2[R];
@@ -110,8 +111,44 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
     if (special_case(res, n1, n2, (double)bv)) return res;
     const double d1 = sqrt((double)bv), d2 = sqrt(fmax((double)cv, 0.0));
     const double epsD = kErrScale * num<float>::u * (double)ilog2_ceil(N) * N * N * sqrt(n1 * n2);
+    const bool two = d1 - d2 < 2.0 * epsD;
+
+    // candidate list (team-uniform order: by register, then by lane)
+    int cnt = 0;
+    bool capped = false;
+    if (rescore == CA_RESCORE_WINDOW) {
+        const double thr = d1 - 2.0 * epsD;
+        const float thr2 = thr > 0.0 ? (float)(thr * thr) : 0.0f;
+        int loc = 0;
+#pragma unroll
+        for (int q = 0; q < R; ++q) loc += (m2[q] >= thr2) ? 1 : 0;
+        const int total = team_sum<T>(loc);
+        if (thr > 0.0 && total <= kCandCap) {
+            const int lane = threadIdx.x & 63;
+            const int base = lane - t;
+            const uint64_t tmask = (T == 64) ? ~0ull : (((1ull << T) - 1ull) << base);
+            const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const bool hit = m2[q] >= thr2;
+                const uint64_t msk = __ballot(hit) & tmask;
+                if (hit) cand[cnt + __popcll(msk & below)] = t + T * q;
+                cnt += __popcll(msk);
+            }
+        }
+        if (cnt == 0) capped = true;
+    }
+    if (rescore != CA_RESCORE_WINDOW || capped) {
+        if (t == 0) {
+            cand[0] = bi;
+            cand[1] = ci;
+        }
+        cnt = two ? 2 : 1;
+    }
+    wave_lds_sync();
     Pick pk;
-    auto rescore_one = [&](int c) {
+    for (int k = 0; k < cnt; ++k) {
+        const int c = cand[k];
         double re = 0.0, im = 0.0;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
@@ -123,35 +160,8 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
         re = team_sum<T>(re);
         im = team_sum<T>(im);
         pk.offer(c, re, im);
-    };
-    bool capped = false;
-    if (rescore == CA_RESCORE_WINDOW) {
-        const double thr = d1 - 2.0 * epsD;
-        const float thr2 = thr > 0.0 ? (float)(thr * thr) : 0.0f;
-        int cnt = 0;
-#pragma unroll
-        for (int q = 0; q < R; ++q) cnt += (m2[q] >= thr2) ? 1 : 0;
-        cnt = team_sum<T>(cnt);
-        if (thr > 0.0 && cnt <= kCandCap) {
-            const int base = (threadIdx.x & 63) - t;
-            const uint64_t tmask = (T == 64) ? ~0ull : (((1ull << T) - 1ull) << base);
-#pragma unroll
-            for (int q = 0; q < R; ++q) {
-                uint64_t msk = __ballot(m2[q] >= thr2) & tmask;
-                while (msk) {
-                    const int l = __ffsll((unsigned long long)msk) - 1;
-                    msk &= msk - 1;
-                    rescore_one(l - base + T * q);
-                }
-            }
-        } else {
-            capped = true;
-        }
     }
-    if (rescore != CA_RESCORE_WINDOW || capped || pk.count == 0) {
-        rescore_one(bi);
-        if (d1 - d2 < 2.0 * epsD) rescore_one(ci);
-    }
+    wave_lds_sync();
     // the path's own C at the chosen shift: arg C = atan2(-Im D, Re D)
     const int qs = pk.shift / T, ls = pk.shift % T;
     cf sel = d[0];
@@ -165,46 +175,59 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
     return res;
 }
 
+template <int TW>
+__device__ __forceinline__ void load_twiddles(cf* tws, const cf* __restrict__ tw) {
+    for (int i = threadIdx.x; i < TW; i += blockDim.x) tws[i] = tw[i];
+    __syncthreads();
+}
+
+// Persistent batch kernel: each team loops over pairs.
 template <int N>
-__global__ __launch_bounds__(256) void k_align_team(const cf* __restrict__ z1, const cf* __restrict__ z2,
+__global__ __launch_bounds__(256, 2) void k_align_team(const cf* __restrict__ z1, const cf* __restrict__ z2,
                                                     int64_t num_pairs, ca_result_t* __restrict__ out,
                                                     const cf* __restrict__ tw, int rescore, int theta64) {
     constexpr int T = TeamCfg<N>::T;
     constexpr int R = N / T;
     constexpr int TEAMS = 256 / T;
     constexpr int PADN = N + N / 16;
+    __shared__ cf tws[TeamCfg<N>::TW];
     __shared__ cf lds_all[TEAMS * PADN];
+    __shared__ int cand_all[TEAMS * kCandCap];
+    load_twiddles<TeamCfg<N>::TW>(tws, tw);
     const int team = threadIdx.x / T;
     const int t = threadIdx.x % T;
-    const int64_t pair = (int64_t)blockIdx.x * TEAMS + team;
-    if (pair >= num_pairs) return;   // a team leaves as a whole
     cf* lds = lds_all + team * PADN;
-    const cf* pa = z1 + pair * N;
-    const cf* pb = z2 + pair * N;
-
-    cf v[R], w[R], a0[R], b0[R];
+    int* cand = cand_all + team * kCandCap;
+    const int64_t stride = (int64_t)gridDim.x * TEAMS;
+    for (int64_t pair = (int64_t)blockIdx.x * TEAMS + team; pair < num_pairs; pair += stride) {
+        const cf* pa = z1 + pair * N;
+        const cf* pb = z2 + pair * N;
+        cf v[R], w[R], a0[R], b0[R];
 #pragma unroll
-    for (int q = 0; q < R; ++q) { v[q] = pa[t + T * q]; w[q] = pb[t + T * q]; }
-    double q1 = 0.0, q2 = 0.0;
+        for (int q = 0; q < R; ++q) { v[q] = pa[t + T * q]; w[q] = pb[t + T * q]; }
+        double q1 = 0.0, q2 = 0.0;
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-        a0[q] = v[q]; b0[q] = w[q];
-        const double ax = v[q].x, ay = v[q].y, bx = w[q].x, by = w[q].y;
-        q1 = fma(ax, ax, fma(ay, ay, q1));
-        q2 = fma(bx, bx, fma(by, by, q2));
+        for (int q = 0; q < R; ++q) {
+            a0[q] = v[q]; b0[q] = w[q];
+            const double ax = v[q].x, ay = v[q].y, bx = w[q].x, by = w[q].y;
+            q1 = fma(ax, ax, fma(ay, ay, q1));
+            q2 = fma(bx, bx, fma(by, by, q2));
+        }
+        team_fft2<N, T>(v, w, lds, tws, t);
+#pragma unroll
+        for (int q = 0; q < R; ++q) v[q] = cjmul(v[q], w[q]);
+        team_fft<N, T>(v, lds, tws, t);
+        const double n1 = team_sum<T>(q1) / N;
+        const double n2 = team_sum<T>(q2) / N;
+        // z2 nodes for the shifted FP64 dot products
+        const int rb = t + (t >> 4);
+#pragma unroll
+        for (int q = 0; q < R; ++q) lds[rb + T * q + ((T * q) >> 4)] = b0[q];
+        wave_lds_sync();
+        const ca_result_t res = team_epilogue<N, T>(v, a0, lds, cand, t, n1, n2, rescore, theta64);
+        if (t == 0) out[pair] = res;
+        wave_lds_sync();
     }
-    team_fft2<N, T>(v, w, lds, tw, t);
-#pragma unroll
-    for (int q = 0; q < R; ++q) v[q] = cjmul(v[q], w[q]);
-    team_fft<N, T>(v, lds, tw, t);
-    const double n1 = team_sum<T>(q1) / N;
-    const double n2 = team_sum<T>(q2) / N;
-    // z2 nodes for the shifted FP64 dot products
-#pragma unroll
-    for (int q = 0; q < R; ++q) lds[lpad(t + T * q)] = b0[q];
-    wave_lds_sync();
-    const ca_result_t res = team_epilogue<N, T>(v, a0, lds, t, n1, n2, rescore, theta64);
-    if (t == 0) out[pair] = res;
 }
 
 // ------------------------------------------------------------------ all pairs
@@ -216,7 +239,9 @@ __global__ __launch_bounds__(256) void k_spectra(const cf* __restrict__ curves, 
     constexpr int R = N / T;
     constexpr int TEAMS = 256 / T;
     constexpr int PADN = N + N / 16;
+    __shared__ cf tws[TeamCfg<N>::TW];
     __shared__ cf lds_all[TEAMS * PADN];
+    load_twiddles<TeamCfg<N>::TW>(tws, tw);
     const int team = threadIdx.x / T;
     const int t = threadIdx.x % T;
     const int64_t i = (int64_t)blockIdx.x * TEAMS + team;
@@ -230,7 +255,7 @@ __global__ __launch_bounds__(256) void k_spectra(const cf* __restrict__ curves, 
         v[q] = z[t + T * q];
         q2 = fma((double)v[q].x, (double)v[q].x, fma((double)v[q].y, (double)v[q].y, q2));
     }
-    team_fft<N, T>(v, lds, tw, t);
+    team_fft<N, T>(v, lds, tws, t);
 #pragma unroll
     for (int q = 0; q < R; ++q) spec[i * N + t + T * q] = v[q];
     q2 = team_sum<T>(q2);
@@ -238,10 +263,12 @@ __global__ __launch_bounds__(256) void k_spectra(const cf* __restrict__ curves, 
 }
 
 // Upper-triangle tiles: blockIdx.y picks TEAMS rows i, blockIdx.x a block of
-// JB columns j.  Each row's conj spectrum and nodes stay in registers; every
-// column's spectrum and nodes are staged once in LDS and shared by the rows.
+// JB columns j.  Each row's spectrum and nodes stay in registers; every
+// column's spectrum and nodes are staged once in LDS (double-buffered: the
+// next column is loaded while the current one is aligned) and shared by the
+// rows.
 template <int N, int JB>
-__global__ __launch_bounds__(256) void k_allpairs(const cf* __restrict__ curves, const cf* __restrict__ spec,
+__global__ __launch_bounds__(256, 2) void k_allpairs(const cf* __restrict__ curves, const cf* __restrict__ spec,
                                                   const double* __restrict__ norms, int m,
                                                   ca_result_t* __restrict__ out, const cf* __restrict__ tw,
                                                   int rescore, int theta64) {
@@ -249,17 +276,22 @@ __global__ __launch_bounds__(256) void k_allpairs(const cf* __restrict__ curves,
     constexpr int R = N / T;
     constexpr int TEAMS = 256 / T;
     constexpr int PADN = N + N / 16;
-    __shared__ cf sZ[N];
-    __shared__ cf sz[PADN];
+    constexpr int PER = (N + 255) / 256;
+    __shared__ cf tws[TeamCfg<N>::TW];
+    __shared__ cf sZ[2][N];
+    __shared__ cf sz[2][PADN];
     __shared__ cf xbuf[TEAMS * PADN];
+    __shared__ int cand_all[TEAMS * kCandCap];
     const int i0 = blockIdx.y * TEAMS;
     const int j0 = blockIdx.x * JB;
     if (j0 + JB - 1 <= i0) return;     // no j > i in this tile
+    load_twiddles<TeamCfg<N>::TW>(tws, tw);
     const int team = threadIdx.x / T;
     const int t = threadIdx.x % T;
     const int i = i0 + team;
     const bool row_ok = i < m;
     cf* lds = xbuf + team * PADN;
+    int* cand = cand_all + team * kCandCap;
     cf Zi[R], zi[R];
     double ni = 0.0;
     if (row_ok) {
@@ -270,29 +302,101 @@ __global__ __launch_bounds__(256) void k_allpairs(const cf* __restrict__ curves,
         }
         ni = norms[i];
     }
+    const int jbeg = max(j0, i0 + 1);
     const int jend = min(j0 + JB, m);
-    for (int j = j0; j < jend; ++j) {
-        __syncthreads();
-        for (int k = threadIdx.x; k < N; k += 256) {
-            sZ[k] = spec[(int64_t)j * N + k];
-            sz[lpad(k)] = curves[(int64_t)j * N + k];
+    cf gZ[PER], gz[PER];
+    auto fetch = [&](int j) {
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int k = threadIdx.x + 256 * p;
+            if (k < N) {
+                gZ[p] = spec[(int64_t)j * N + k];
+                gz[p] = curves[(int64_t)j * N + k];
+            }
         }
-        __syncthreads();
+    };
+    auto stash = [&](int b) {
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int k = threadIdx.x + 256 * p;
+            if (k < N) {
+                sZ[b][k] = gZ[p];
+                sz[b][lpad(k)] = gz[p];
+            }
+        }
+    };
+    if (jbeg < jend) {
+        fetch(jbeg);
+        stash(0);
+    }
+    __syncthreads();
+    for (int j = jbeg; j < jend; ++j) {
+        const int cur = (j - jbeg) & 1;
+        if (j + 1 < jend) fetch(j + 1);
         if (row_ok && j > i) {
             cf v[R];
 #pragma unroll
-            for (int q = 0; q < R; ++q) v[q] = cjmul(Zi[q], sZ[t + T * q]);
-            team_fft<N, T>(v, lds, tw, t);
-            const ca_result_t res = team_epilogue<N, T>(v, zi, sz, t, ni, norms[j], rescore, theta64);
+            for (int q = 0; q < R; ++q) v[q] = cjmul(Zi[q], sZ[cur][t + T * q]);
+            team_fft<N, T>(v, lds, tws, t);
+            const ca_result_t res = team_epilogue<N, T>(v, zi, sz[cur], cand, t, ni, norms[j], rescore, theta64);
             if (t == 0) {
                 const int64_t k = (int64_t)i * m - (int64_t)i * (i + 1) / 2 + (j - i - 1);
                 out[k] = res;
             }
         }
+        if (j + 1 < jend) stash(cur ^ 1);
+        __syncthreads();
     }
 }
 
-bool allpairs_supported(int n) { return n == 64 || n == 128 || n == 256 || n == 512 || n == 1024; }
+bool team_supported(int n) { return n == 64 || n == 128 || n == 256 || n == 512 || n == 1024; }
+bool allpairs_supported(int n) { return team_supported(n); }
+
+template <int N>
+static hipError_t launch_team_n(const void* z1, const void* z2, int64_t np, ca_result_t* out,
+                                const void* tw, int rescore, int theta64, int max_blocks, hipStream_t s) {
+    constexpr int TEAMS = 256 / TeamCfg<N>::T;
+    int64_t blocks = (np + TEAMS - 1) / TEAMS;
+    if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
+    hipLaunchKernelGGL(k_align_team<N>, dim3((unsigned)blocks), dim3(256), 0, s, (const cf*)z1,
+                       (const cf*)z2, np, out, (const cf*)tw, rescore, theta64);
+    return hipGetLastError();
+}
+
+template <int N>
+static int team_blocks_per_cu() {
+    static int cached = -1;
+    if (cached < 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_align_team<N>, 256, 0) != hipSuccess || nb < 1)
+            nb = 1;
+        cached = nb;
+    }
+    return cached;
+}
+
+hipError_t launch_align_team(const void* z1, const void* z2, int n, int64_t np, ca_result_t* out,
+                             const void* tw, int rescore, int theta64, int num_cus, hipStream_t s) {
+    switch (n) {
+        case 64: return launch_team_n<64>(z1, z2, np, out, tw, rescore, theta64, num_cus * team_blocks_per_cu<64>(), s);
+        case 128: return launch_team_n<128>(z1, z2, np, out, tw, rescore, theta64, num_cus * team_blocks_per_cu<128>(), s);
+        case 256: return launch_team_n<256>(z1, z2, np, out, tw, rescore, theta64, num_cus * team_blocks_per_cu<256>(), s);
+        case 512: return launch_team_n<512>(z1, z2, np, out, tw, rescore, theta64, num_cus * team_blocks_per_cu<512>(), s);
+        case 1024: return launch_team_n<1024>(z1, z2, np, out, tw, rescore, theta64, num_cus * team_blocks_per_cu<1024>(), s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int team_twiddle_count(int n) {
+    switch (n) {
+        case 64: return TeamCfg<64>::TW;
+        case 128: return TeamCfg<128>::TW;
+        case 256: return TeamCfg<256>::TW;
+        case 512: return TeamCfg<512>::TW;
+        case 1024: return TeamCfg<1024>::TW;
+        default: return 0;
+    }
+}
 
 template <int N>
 static hipError_t launch_spectra_n(const void* curves, int m, void* spec, double* norms, const void* tw,
@@ -335,30 +439,6 @@ hipError_t launch_allpairs(const void* curves, const void* spec, const double* n
         case 256: return launch_allpairs_n<256>(curves, spec, norms, m, out, tw, rescore, theta64, s);
         case 512: return launch_allpairs_n<512>(curves, spec, norms, m, out, tw, rescore, theta64, s);
         case 1024: return launch_allpairs_n<1024>(curves, spec, norms, m, out, tw, rescore, theta64, s);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-bool team_supported(int n) { return n == 64 || n == 128 || n == 256 || n == 512 || n == 1024; }
-
-template <int N>
-static hipError_t launch_team_n(const void* z1, const void* z2, int64_t np, ca_result_t* out,
-                                const void* tw, int rescore, int theta64, hipStream_t s) {
-    constexpr int TEAMS = 256 / TeamCfg<N>::T;
-    const int64_t blocks = (np + TEAMS - 1) / TEAMS;
-    hipLaunchKernelGGL(k_align_team<N>, dim3((unsigned)blocks), dim3(256), 0, s, (const cf*)z1,
-                       (const cf*)z2, np, out, (const cf*)tw, rescore, theta64);
-    return hipGetLastError();
-}
-
-hipError_t launch_align_team(const void* z1, const void* z2, int n, int64_t np, ca_result_t* out,
-                             const void* tw, int rescore, int theta64, hipStream_t s) {
-    switch (n) {
-        case 64: return launch_team_n<64>(z1, z2, np, out, tw, rescore, theta64, s);
-        case 128: return launch_team_n<128>(z1, z2, np, out, tw, rescore, theta64, s);
-        case 256: return launch_team_n<256>(z1, z2, np, out, tw, rescore, theta64, s);
-        case 512: return launch_team_n<512>(z1, z2, np, out, tw, rescore, theta64, s);
-        case 1024: return launch_team_n<1024>(z1, z2, np, out, tw, rescore, theta64, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -80,9 +80,12 @@ struct ca_context {
     std::vector<Plan> h_plans;
     void* d_tw32 = nullptr;   // float2 arena
     void* d_tw64 = nullptr;   // double2 arena
-    // resampler scratch
+    void* d_team_tw[11] = {};  // per-pass team-engine twiddles, index log2(n)
+    // resampler scratch and the list of curves for the general kernel
     void* d_rs = nullptr;
     int64_t rs_slots = 0;
+    int* d_slow = nullptr;          // [0] = count, [1..] = curve indices
+    int64_t slow_cap = 0;
     // all-pairs spectra workspace
     void* d_spec = nullptr;
     size_t spec_bytes = 0;
@@ -156,6 +159,52 @@ const void* tw32_for(ca_context* c, int n) {
     return (const char*)c->d_tw32 + c->h_plans[n].tw_off * 2 * sizeof(float);
 }
 
+// Team-engine twiddles per pass after the first: (radix RP, stride NS, table offset).
+struct TeamPass { int rp, ns, off; };
+std::vector<TeamPass> team_passes(int n) {
+    switch (n) {
+        case 64: return {{8, 8, 0}};
+        case 128: return {{8, 16, 0}};
+        case 256: return {{16, 16, 0}};
+        case 512: return {{16, 16, 0}, {2, 256, 240}};
+        case 1024: return {{16, 16, 0}, {4, 256, 240}};
+        default: return {};
+    }
+}
+
+ca_status_t ensure_team_tables(ca_context* c) {
+    if (c->d_team_tw[6]) return CA_OK;
+    for (int n : {64, 128, 256, 512, 1024}) {
+        int lg = 0;
+        while ((1 << lg) < n) ++lg;
+        std::vector<float> tab(2 * (size_t)ca::team_twiddle_count(n), 0.0f);
+        std::vector<double> re, im;
+        for (const TeamPass& p : team_passes(n)) {
+            const int M = p.ns * p.rp;
+            twiddles(M, re, im);
+            for (int r = 1; r < p.rp; ++r)
+                for (int k = 0; k < p.ns; ++k) {
+                    const size_t e = (size_t)p.off + (size_t)(r - 1) * p.ns + k;
+                    tab[2 * e] = (float)re[(r * k) % M];
+                    tab[2 * e + 1] = (float)im[(r * k) % M];
+                }
+        }
+        void* d = nullptr;
+        if (hipMalloc(&d, tab.size() * sizeof(float)) != hipSuccess)
+            return fail(CA_ERR_OOM, "team twiddle table");
+        hipError_t e = hipMemcpy(d, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "team twiddle upload");
+        c->d_team_tw[lg] = d;
+    }
+    return CA_OK;
+}
+
+const void* team_tw_for(ca_context* c, int n) {
+    int lg = 0;
+    while ((1 << lg) < n) ++lg;
+    return c->d_team_tw[lg];
+}
+
 ca_status_t parse_opts(const ca_options_t* opt, ca_options_t& o) {
     o = ca_options_t{CA_PREC_FP32, CA_RESCORE_TOP2, 0, 0};
     if (!opt) return CA_OK;
@@ -223,7 +272,10 @@ ca_status_t ca_destroy(ca_context_t c) {
         if (c->d_plans) (void)hipFree(c->d_plans);
         if (c->d_tw32) (void)hipFree(c->d_tw32);
         if (c->d_tw64) (void)hipFree(c->d_tw64);
+        for (void* p : c->d_team_tw)
+            if (p) (void)hipFree(p);
         if (c->d_rs) (void)hipFree(c->d_rs);
+        if (c->d_slow) (void)hipFree(c->d_slow);
         if (c->d_spec) (void)hipFree(c->d_spec);
         if (c->d_norms) (void)hipFree(c->d_norms);
     }
@@ -253,7 +305,10 @@ ca_status_t align_batch(ca_context_t c, const void* z1, const void* z2, const in
     if (st != CA_OK) return st;
     hipError_t e;
     if (o.precision == CA_PREC_FP32 && !offsets && ca::team_supported(n)) {
-        e = ca::launch_align_team(z1, z2, n, num_pairs, out, tw32_for(c, n), o.rescore, o.theta_fp64, s);
+        st = ensure_team_tables(c);
+        if (st != CA_OK) return st;
+        e = ca::launch_align_team(z1, z2, n, num_pairs, out, team_tw_for(c, n), o.rescore, o.theta_fp64,
+                                  c->num_cus, s);
     } else {
         ca::BlkArgs a;
         a.z1 = z1;
@@ -304,6 +359,8 @@ ca_status_t align_all_pairs(ca_context_t c, const void* curves, int32_t m, int32
     hipStream_t s = (hipStream_t)stream;
     st = ensure_tables(c, false);
     if (st != CA_OK) return st;
+    st = ensure_team_tables(c);
+    if (st != CA_OK) return st;
     hipError_t e;
     if (ca::allpairs_supported(n)) {
         const size_t need = (size_t)m * n * 2 * sizeof(float);
@@ -322,9 +379,9 @@ ca_status_t align_all_pairs(ca_context_t c, const void* curves, int32_t m, int32
                 return fail(CA_ERR_OOM, "norms workspace");
             c->norms_count = m;
         }
-        e = ca::launch_spectra(curves, m, n, c->d_spec, c->d_norms, tw32_for(c, n), s);
+        e = ca::launch_spectra(curves, m, n, c->d_spec, c->d_norms, team_tw_for(c, n), s);
         if (e != hipSuccess) return hip_fail(e, "spectra kernel launch");
-        e = ca::launch_allpairs(curves, c->d_spec, c->d_norms, m, n, out_upper, tw32_for(c, n),
+        e = ca::launch_allpairs(curves, c->d_spec, c->d_norms, m, n, out_upper, team_tw_for(c, n),
                                 o.rescore, o.theta_fp64, s);
         if (e != hipSuccess) return hip_fail(e, "all-pairs kernel launch");
         return CA_OK;
@@ -350,9 +407,18 @@ ca_status_t resample_arclength(ca_context_t c, const void* raw, const int64_t* r
             return fail(CA_ERR_OOM, "resampler scratch");
         c->rs_slots = slots;
     }
+    if (num_curves > 0x7fffffffLL) return fail(CA_ERR_INVALID_ARG, "num_curves exceeds 2^31 - 1");
+    if (num_curves + 1 > c->slow_cap) {
+        if (c->d_slow) (void)hipFree(c->d_slow);
+        c->d_slow = nullptr;
+        c->slow_cap = 0;
+        if (hipMalloc(&c->d_slow, (size_t)(num_curves + 1) * sizeof(int)) != hipSuccess)
+            return fail(CA_ERR_OOM, "resampler curve list");
+        c->slow_cap = num_curves + 1;
+    }
     hipError_t e = ca::launch_resample(raw, raw_offsets, num_curves, out_offsets, out, norms_out,
                                        flags_out, mode, c->d_rs, ca::resample_slot_bytes(),
-                                       c->rs_slots, (hipStream_t)stream);
+                                       c->rs_slots, c->d_slow, c->d_slow + 1, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "resample kernel launch");
     return CA_OK;
 }

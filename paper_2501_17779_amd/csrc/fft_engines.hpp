@@ -87,61 +87,83 @@ __device__ void blk_fft(cpx<T>* buf, const Plan& p, const cpx<T>* __restrict__ t
 }
 
 // ------------------------------------------------------------------- team engine
+// LDS exchange layout: element i lives at i + i/16 (one pad slot per 16).
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 
-template <int N, int T, int RP, int NS, bool LAST>
-__device__ __forceinline__ void team_pass(cf (&v)[N / T], cf* lds, const cf* __restrict__ tw, int t) {
+// Radix schedules: N = T * R (T lanes, R values per lane); every radix
+// divides R.  Passes after the first multiply by w_{NS RP}^{r k}; those
+// twiddles are stored per pass as tw[TWO + (r - 1) NS + k], so a lane's
+// twiddles are one base address plus compile-time offsets.
+template <int N> struct TeamCfg;
+template <> struct TeamCfg<64> { static constexpr int T = 8, TW = 56; };      // 8 x 8
+template <> struct TeamCfg<128> { static constexpr int T = 8, TW = 112; };    // 16 x 8
+template <> struct TeamCfg<256> { static constexpr int T = 16, TW = 240; };   // 16 x 16
+template <> struct TeamCfg<512> { static constexpr int T = 32, TW = 496; };   // 16 x 16 x 2
+template <> struct TeamCfg<1024> { static constexpr int T = 64, TW = 1008; }; // 16 x 16 x 4
+
+// One Stockham pass on the team's registers.  Non-final passes scatter the
+// outputs to LDS and gather x[t + T q] back; all LDS addresses are a lane base
+// plus compile-time offsets (the pad function is additive on the pieces).
+template <int N, int T, int RP, int NS, bool LAST, int TWO>
+__device__ __forceinline__ void team_pass(cf (&v)[N / T], cf* lds, const cf* tws, int t) {
     constexpr int R = N / T;
     constexpr int U = R / RP;
     static_assert(R % RP == 0, "radix must divide the per-lane count");
-    constexpr int TS = N / (NS * RP);
+    static_assert(LAST || U == 1, "exchanging passes hold one butterfly per lane");
+    static_assert(NS == 1 || NS % 16 == 0 || LAST, "exchange layout needs NS = 1 or a multiple of 16");
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int j = t + u * T;
-        const int k = j % NS;
+        const int k = j & (NS - 1);
         cf b[RP];
 #pragma unroll
         for (int r = 0; r < RP; ++r) b[r] = v[u + r * U];
         if constexpr (NS > 1) {
 #pragma unroll
-            for (int r = 1; r < RP; ++r) b[r] = mul(b[r], tw[r * k * TS]);
+            for (int r = 1; r < RP; ++r) b[r] = mul(b[r], tws[TWO + (r - 1) * NS + k]);
         }
         dft<RP>(b);
         if constexpr (LAST) {
 #pragma unroll
             for (int r = 0; r < RP; ++r) v[u + r * U] = b[r];
-        } else {
-            const int base = (j - k) * RP + k;
+        } else if constexpr (NS == 1) {
+            cf* wp = lds + (RP * j + ((RP * j) >> 4));
 #pragma unroll
-            for (int r = 0; r < RP; ++r) lds[lpad(base + r * NS)] = b[r];
+            for (int r = 0; r < RP; ++r) wp[r] = b[r];
+        } else {
+            const int i0 = (j - k) * RP + k;
+            cf* wp = lds + lpad(i0);
+#pragma unroll
+            for (int r = 0; r < RP; ++r) wp[r * (NS + NS / 16)] = b[r];
         }
     }
     if constexpr (!LAST) {
         wave_lds_sync();
+        const cf* rp = lds + (t + (t >> 4));
 #pragma unroll
-        for (int q = 0; q < R; ++q) v[q] = lds[lpad(t + T * q)];
+        for (int q = 0; q < R; ++q) v[q] = rp[T * q + ((T * q) >> 4)];
         wave_lds_sync();
     }
 }
 
-// Same pass on two signals with one twiddle fetch.
-template <int N, int T, int RP, int NS, bool LAST>
-__device__ __forceinline__ void team_pass2(cf (&v)[N / T], cf (&w)[N / T], cf* lds,
-                                           const cf* __restrict__ tw, int t) {
+// The same pass on two signals with shared twiddle loads.
+template <int N, int T, int RP, int NS, bool LAST, int TWO>
+__device__ __forceinline__ void team_pass2(cf (&v)[N / T], cf (&w)[N / T], cf* lds, const cf* tws, int t) {
     constexpr int R = N / T;
     constexpr int U = R / RP;
-    constexpr int TS = N / (NS * RP);
+    static_assert(LAST || U == 1, "exchanging passes hold one butterfly per lane");
+    cf bo[LAST ? 1 : RP], co[LAST ? 1 : RP];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int j = t + u * T;
-        const int k = j % NS;
+        const int k = j & (NS - 1);
         cf b[RP], c[RP];
 #pragma unroll
         for (int r = 0; r < RP; ++r) { b[r] = v[u + r * U]; c[r] = w[u + r * U]; }
         if constexpr (NS > 1) {
 #pragma unroll
             for (int r = 1; r < RP; ++r) {
-                const cf f = tw[r * k * TS];
+                const cf f = tws[TWO + (r - 1) * NS + k];
                 b[r] = mul(b[r], f);
                 c[r] = mul(c[r], f);
             }
@@ -152,80 +174,75 @@ __device__ __forceinline__ void team_pass2(cf (&v)[N / T], cf (&w)[N / T], cf* l
 #pragma unroll
             for (int r = 0; r < RP; ++r) { v[u + r * U] = b[r]; w[u + r * U] = c[r]; }
         } else {
-            const int base = (j - k) * RP + k;
 #pragma unroll
-            for (int r = 0; r < RP; ++r) lds[lpad(base + r * NS)] = b[r];
-            wave_lds_sync();
-#pragma unroll
-            for (int q = 0; q < R; ++q) v[q] = lds[lpad(t + T * q)];
-            wave_lds_sync();
-#pragma unroll
-            for (int r = 0; r < RP; ++r) lds[lpad(base + r * NS)] = c[r];
+            for (int r = 0; r < RP; ++r) { bo[r] = b[r]; co[r] = c[r]; }
         }
     }
     if constexpr (!LAST) {
-        static_assert(LAST || U == 1, "two-signal exchange assumes one butterfly per lane");
+        const int j = t;
+        const int k = j & (NS - 1);
+        cf* wp;
+        int stride;
+        if constexpr (NS == 1) { wp = lds + (RP * j + ((RP * j) >> 4)); stride = 1; }
+        else { wp = lds + lpad((j - k) * RP + k); stride = NS + NS / 16; }
+        const cf* rp = lds + (t + (t >> 4));
+#pragma unroll
+        for (int r = 0; r < RP; ++r) wp[r * stride] = bo[r];
         wave_lds_sync();
 #pragma unroll
-        for (int q = 0; q < R; ++q) w[q] = lds[lpad(t + T * q)];
+        for (int q = 0; q < R; ++q) v[q] = rp[T * q + ((T * q) >> 4)];
+        wave_lds_sync();
+#pragma unroll
+        for (int r = 0; r < RP; ++r) wp[r * stride] = co[r];
+        wave_lds_sync();
+#pragma unroll
+        for (int q = 0; q < R; ++q) w[q] = rp[T * q + ((T * q) >> 4)];
         wave_lds_sync();
     }
 }
 
-// Radix schedules of the team engine (product = N, each radix divides N/T).
-template <int N> struct TeamCfg;
-template <> struct TeamCfg<64> { static constexpr int T = 8; };     // 8 x 8
-template <> struct TeamCfg<128> { static constexpr int T = 8; };    // 16 x 8
-template <> struct TeamCfg<256> { static constexpr int T = 16; };   // 16 x 16
-template <> struct TeamCfg<512> { static constexpr int T = 32; };   // 16 x 16 x 2
-template <> struct TeamCfg<1024> { static constexpr int T = 64; };  // 16 x 16 x 4
-
 template <int N, int T>
-__device__ __forceinline__ void team_fft(cf (&v)[N / T], cf* lds, const cf* __restrict__ tw, int t) {
+__device__ __forceinline__ void team_fft(cf (&v)[N / T], cf* lds, const cf* tws, int t) {
     if constexpr (N == 64) {
-        team_pass<64, T, 8, 1, false>(v, lds, tw, t);
-        team_pass<64, T, 8, 8, true>(v, lds, tw, t);
+        team_pass<64, T, 8, 1, false, 0>(v, lds, tws, t);
+        team_pass<64, T, 8, 8, true, 0>(v, lds, tws, t);
     } else if constexpr (N == 128) {
-        team_pass<128, T, 16, 1, false>(v, lds, tw, t);
-        team_pass<128, T, 8, 16, true>(v, lds, tw, t);
+        team_pass<128, T, 16, 1, false, 0>(v, lds, tws, t);
+        team_pass<128, T, 8, 16, true, 0>(v, lds, tws, t);
     } else if constexpr (N == 256) {
-        team_pass<256, T, 16, 1, false>(v, lds, tw, t);
-        team_pass<256, T, 16, 16, true>(v, lds, tw, t);
+        team_pass<256, T, 16, 1, false, 0>(v, lds, tws, t);
+        team_pass<256, T, 16, 16, true, 0>(v, lds, tws, t);
     } else if constexpr (N == 512) {
-        team_pass<512, T, 16, 1, false>(v, lds, tw, t);
-        team_pass<512, T, 16, 16, false>(v, lds, tw, t);
-        team_pass<512, T, 2, 256, true>(v, lds, tw, t);
+        team_pass<512, T, 16, 1, false, 0>(v, lds, tws, t);
+        team_pass<512, T, 16, 16, false, 0>(v, lds, tws, t);
+        team_pass<512, T, 2, 256, true, 240>(v, lds, tws, t);
     } else {
         static_assert(N == 1024, "team engine sizes: 64..1024");
-        team_pass<1024, T, 16, 1, false>(v, lds, tw, t);
-        team_pass<1024, T, 16, 16, false>(v, lds, tw, t);
-        team_pass<1024, T, 4, 256, true>(v, lds, tw, t);
+        team_pass<1024, T, 16, 1, false, 0>(v, lds, tws, t);
+        team_pass<1024, T, 16, 16, false, 0>(v, lds, tws, t);
+        team_pass<1024, T, 4, 256, true, 240>(v, lds, tws, t);
     }
 }
 
-// Forward transforms of two signals.  Passes whose radix equals N/T (one
-// butterfly per lane) share their twiddle loads between the two signals.
 template <int N, int T>
-__device__ __forceinline__ void team_fft2(cf (&v)[N / T], cf (&w)[N / T], cf* lds,
-                                          const cf* __restrict__ tw, int t) {
+__device__ __forceinline__ void team_fft2(cf (&v)[N / T], cf (&w)[N / T], cf* lds, const cf* tws, int t) {
     if constexpr (N == 64) {
-        team_pass<64, T, 8, 1, false>(v, lds, tw, t);
-        team_pass<64, T, 8, 1, false>(w, lds, tw, t);
-        team_pass2<64, T, 8, 8, true>(v, w, lds, tw, t);
+        team_pass2<64, T, 8, 1, false, 0>(v, w, lds, tws, t);
+        team_pass2<64, T, 8, 8, true, 0>(v, w, lds, tws, t);
     } else if constexpr (N == 128) {
-        team_pass2<128, T, 16, 1, false>(v, w, lds, tw, t);
-        team_pass2<128, T, 8, 16, true>(v, w, lds, tw, t);
+        team_pass2<128, T, 16, 1, false, 0>(v, w, lds, tws, t);
+        team_pass2<128, T, 8, 16, true, 0>(v, w, lds, tws, t);
     } else if constexpr (N == 256) {
-        team_pass2<256, T, 16, 1, false>(v, w, lds, tw, t);
-        team_pass2<256, T, 16, 16, true>(v, w, lds, tw, t);
+        team_pass2<256, T, 16, 1, false, 0>(v, w, lds, tws, t);
+        team_pass2<256, T, 16, 16, true, 0>(v, w, lds, tws, t);
     } else if constexpr (N == 512) {
-        team_pass2<512, T, 16, 1, false>(v, w, lds, tw, t);
-        team_pass2<512, T, 16, 16, false>(v, w, lds, tw, t);
-        team_pass2<512, T, 2, 256, true>(v, w, lds, tw, t);
+        team_pass2<512, T, 16, 1, false, 0>(v, w, lds, tws, t);
+        team_pass2<512, T, 16, 16, false, 0>(v, w, lds, tws, t);
+        team_pass2<512, T, 2, 256, true, 240>(v, w, lds, tws, t);
     } else {
-        team_pass2<1024, T, 16, 1, false>(v, w, lds, tw, t);
-        team_pass2<1024, T, 16, 16, false>(v, w, lds, tw, t);
-        team_pass2<1024, T, 4, 256, true>(v, w, lds, tw, t);
+        team_pass2<1024, T, 16, 1, false, 0>(v, w, lds, tws, t);
+        team_pass2<1024, T, 16, 16, false, 0>(v, w, lds, tws, t);
+        team_pass2<1024, T, 4, 256, true, 240>(v, w, lds, tws, t);
     }
 }
 

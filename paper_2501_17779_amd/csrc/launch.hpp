@@ -31,10 +31,13 @@ hipError_t launch_align_blk_f32(const BlkArgs& a, hipStream_t s);
 hipError_t launch_align_blk_f64(const BlkArgs& a, hipStream_t s);
 
 // Register-resident team FFT for n in {64, 128, 256, 512, 1024}, FP32.
+// `tw` is the per-pass twiddle table of team_twiddle_count(n) entries
+// (see TeamCfg): entry TWO + (r - 1) NS + k = w_{NS RP}^{r k}.
 bool team_supported(int n);
+int team_twiddle_count(int n);
 hipError_t launch_align_team(const void* z1, const void* z2, int n, int64_t num_pairs,
                              ca_result_t* out, const void* tw, int rescore, int theta64,
-                             hipStream_t s);
+                             int num_cus, hipStream_t s);
 
 // All-pairs: per-curve spectra, then the upper-triangle tile kernel.
 hipError_t launch_spectra(const void* curves, int m, int n, void* spectra, double* norms,
@@ -45,9 +48,13 @@ hipError_t launch_allpairs(const void* curves, const void* spectra, const double
 bool allpairs_supported(int n);
 
 // Arc-length resampling, one workgroup per curve.
+// A wave-per-curve fast kernel handles every curve it can; the others (fewer
+// than 3 vertices, duplicates, non-finite values, above the vertex cap) are
+// listed in slow_list (count in *slow_count, device) and resampled by the
+// general workgroup-per-curve kernel with `slots` scratch slots.
 hipError_t launch_resample(const void* raw, const int64_t* raw_off, int64_t num_curves,
                            const int64_t* out_off, void* out, double* norms, uint32_t* flags,
-                           int mode, void* scratch, int64_t scratch_per_curve_bytes,
-                           int64_t curves_per_launch, hipStream_t s);
+                           int mode, void* scratch, int64_t slot_bytes, int64_t slots,
+                           int* slow_count, int* slow_list, hipStream_t s);
 
 }  // namespace ca

@@ -161,12 +161,16 @@ __global__ __launch_bounds__(kRsNT) void k_resample(const cf* __restrict__ raw, 
                                                     int64_t num_curves, const int64_t* __restrict__ out_off,
                                                     cf* __restrict__ out, double* __restrict__ norms,
                                                     uint32_t* __restrict__ flags, int mode,
-                                                    unsigned char* __restrict__ scratch, int64_t slot_bytes) {
+                                                    unsigned char* __restrict__ scratch, int64_t slot_bytes,
+                                                    const int* __restrict__ list_count,
+                                                    const int* __restrict__ list) {
     __shared__ double shd[4];
     __shared__ int shi[4];
     const RsSlot S = rs_slot(scratch + (int64_t)blockIdx.x * slot_bytes);
     const int tid = threadIdx.x;
-    for (int64_t c = blockIdx.x; c < num_curves; c += gridDim.x) {
+    const int64_t count = list_count ? (int64_t)*list_count : num_curves;
+    for (int64_t li = blockIdx.x; li < count; li += gridDim.x) {
+        const int64_t c = list ? (int64_t)list[li] : li;
         const int64_t r0 = raw_off[c];
         const int64_t mraw = raw_off[c + 1] - r0;
         const int64_t o0 = out_off[c];
@@ -330,13 +334,259 @@ __global__ __launch_bounds__(kRsNT) void k_resample(const cf* __restrict__ raw, 
     }
 }
 
+// ----------------------------------------------------------------- fast path
+// One wave per curve, no workgroup barriers.  Pass 1 streams the polygon once
+// for the perimeter (FP64) and rejects curves that need the general path
+// (duplicate or non-finite vertices, fewer than 3 or more than the cap).
+// Pass 2 walks the curve in tiles of kFtK knots (consecutive tiles share one
+// knot): the tile and a halo of kRsW + 1 knots on each side are staged in
+// LDS, chord lengths, right-hand sides, tile-relative arc-length parameters
+// and the local spline solves are computed there, and every output node
+// whose parameter falls in the tile is evaluated after a binary search over
+// the tile's knots.  Pass 3 centres the nodes and accumulates their norm.
+constexpr int kFtK = 512;                  // knots per tile
+constexpr int kFtH = kRsW + 1;             // halo on each side
+constexpr int kFtP = kFtK + 2 * kFtH;      // staged knots
+constexpr int kFtC = 8;                    // knots per lane in the local solve
+
+__device__ __forceinline__ int wrapm(int i, int m) {
+    while (i < 0) i += m;
+    while (i >= m) i -= m;
+    return i;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) { return team_sum<64>(v); }
+
+__global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw, const int64_t* __restrict__ raw_off,
+                                                      int64_t num_curves, const int64_t* __restrict__ out_off,
+                                                      cf* __restrict__ out, double* __restrict__ norms,
+                                                      uint32_t* __restrict__ flags, int mode,
+                                                      int* __restrict__ slow_count, int* __restrict__ slow_list) {
+    __shared__ cf sP[kFtP];
+    __shared__ float sH[kFtP];
+    __shared__ cf sR[kFtP];
+    __shared__ float sS[kFtK];
+    __shared__ cf sM[kFtK];
+    const int64_t c = blockIdx.x;
+    if (c >= num_curves) return;
+    const int lane = threadIdx.x;
+    const int64_t r0 = raw_off[c];
+    const int64_t mraw = raw_off[c + 1] - r0;
+    const int64_t o0 = out_off[c];
+    const int N = (int)(out_off[c + 1] - o0);
+    cf* o = out + o0;
+    const cf* P = raw + r0;
+    bool general = (mraw < 3 || mraw > kRsMCap || N < 1);
+    const int M = general ? 0 : (int)mraw;
+
+    // pass 1: perimeter, duplicates, non-finite values
+    double Ls = 0.0;
+    int bad = 0;
+    for (int j = lane; j < M; j += 64) {
+        const cf a = P[j];
+        const cf b = P[j + 1 < M ? j + 1 : 0];
+        const float dx = b.x - a.x, dy = b.y - a.y;
+        const float h = sqrtf(dx * dx + dy * dy);
+        if (!(h > 0.0f) || !isfinite(h)) bad = 1;
+        Ls += (double)h;
+    }
+    general = general || (__ballot(bad) != 0ull);
+    if (general) {
+        if (lane == 0) {
+            const int pos = atomicAdd(slow_count, 1);
+            slow_list[pos] = (int)c;
+        }
+        return;
+    }
+    const double L = wave_sum_d(Ls);
+    const double invL = 1.0 / L;
+    const double uN = L / (double)N;           // arc length between output nodes
+
+    // pass 2: tiles of kFtK knots starting at a; segments [a, a + kFtK - 1)
+    double carry = 0.0;                        // arc length at knot a
+    double sx = 0.0, sy = 0.0;
+    for (int a = 0; a < M; a += kFtK - 1) {
+        const bool last = (a + kFtK - 1 >= M);
+        const int kt = last ? (M - a + 1) : kFtK;       // knots in this tile incl. the right end
+        // stage knots a - kFtH .. a + kFtK + kFtH - 1 (cyclic)
+        for (int i = lane; i < kFtP; i += 64) sP[i] = P[wrapm(a - kFtH + i, M)];
+        wave_lds_sync();
+        for (int i = lane; i < kFtP - 1; i += 64) {
+            const cf p = sP[i], q = sP[i + 1];
+            const float dx = q.x - p.x, dy = q.y - p.y;
+            sH[i] = sqrtf(dx * dx + dy * dy);
+        }
+        wave_lds_sync();
+        if (mode == CA_RESAMPLE_SPLINE) {
+            for (int i = lane + 1; i < kFtP - 1; i += 64) {
+                const cf pm = sP[i - 1], p = sP[i], q = sP[i + 1];
+                const float hm = sH[i - 1], h = sH[i];
+                const float ih = 1.0f / h, ihm = 1.0f / hm;
+                sR[i] = {6.0f * ((q.x - p.x) * ih - (p.x - pm.x) * ihm),
+                         6.0f * ((q.y - p.y) * ih - (p.y - pm.y) * ihm)};
+            }
+        }
+        // tile-relative arc length: lane owns local knots [8 lane, 8 lane + 8)
+        float loc[kFtC];
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < kFtC; ++k) {
+            loc[k] = (float)acc;
+            acc += (double)sH[kFtH + kFtC * lane + k];
+        }
+        double incl = acc;
+#pragma unroll
+        for (int o2 = 1; o2 < 64; o2 <<= 1) {
+            const double y = __shfl_up(incl, o2, 64);
+            if (lane >= o2) incl += y;
+        }
+        const double base = incl - acc;        // arc length from knot a to knot a + 8 lane
+#pragma unroll
+        for (int k = 0; k < kFtC; ++k) sS[kFtC * lane + k] = (float)(base + (double)loc[k]);
+        // arc length from knot a to knot a + kt - 1 (tile end), exact in FP64
+        double span;
+        {
+            const int e = kt - 1;              // local index of the right end
+            const int el = e / kFtC, ek = e % kFtC;
+            double part = 0.0;
+#pragma unroll
+            for (int k = 0; k < kFtC; ++k)
+                if (k < ek) part += (double)sH[kFtH + kFtC * el + k];
+            span = __shfl(base, el, 64) + __shfl(part, el, 64);
+        }
+        wave_lds_sync();
+        if (mode == CA_RESAMPLE_SPLINE) {
+            // local solve for knots [8 lane, 8 lane + 8): window kRsW each side
+            float al[kFtC];
+            cf de[kFtC];
+            const int i0 = kFtH + kFtC * lane;           // staged index of the chunk's first knot
+            float hprev = sH[i0 - kRsW - 1];
+            float alpha = 0.0f;
+            cf delta = {0.0f, 0.0f};
+#pragma unroll
+            for (int i = 0; i < kRsW + kFtC; ++i) {
+                const int j = i0 - kRsW + i;
+                const float hj = sH[j];
+                const cf d = sR[j];
+                const float b = 2.0f * (hprev + hj);
+                if (i == 0) {
+                    alpha = b;
+                    delta = d;
+                } else {
+                    const float f = hprev / alpha;
+                    alpha = b - f * hprev;
+                    delta = {d.x - f * delta.x, d.y - f * delta.y};
+                }
+                hprev = hj;
+                if (i >= kRsW) { al[i - kRsW] = alpha; de[i - kRsW] = delta; }
+            }
+            const int e = i0 + kFtC;
+            float beta = 0.0f, anext = 0.0f;
+            cf eps = {0.0f, 0.0f};
+#pragma unroll
+            for (int i = kRsW - 1; i >= 0; --i) {
+                const int j = e + i;
+                const float hj = sH[j], hjm = sH[j - 1];
+                const cf d = sR[j];
+                const float b = 2.0f * (hjm + hj);
+                if (i == kRsW - 1) {
+                    beta = b;
+                    eps = d;
+                } else {
+                    const float g = hj / beta;
+                    beta = b - g * anext;
+                    eps = {d.x - g * eps.x, d.y - g * eps.y};
+                }
+                anext = hjm;
+            }
+            const float ae = sH[e - 1];
+            const float aL = al[kFtC - 1];
+            const cf dL = de[kFtC - 1];
+            const float den = beta - ae * ae / aL;
+            cf Mn = {(eps.x - ae * dL.x / aL) / den, (eps.y - ae * dL.y / aL) / den};
+#pragma unroll
+            for (int i = kFtC - 1; i >= 0; --i) {
+                const float cj = sH[i0 + i];
+                const cf Mi = {(de[i].x - cj * Mn.x) / al[i], (de[i].y - cj * Mn.y) / al[i]};
+                sM[kFtC * lane + i] = Mi;
+                Mn = Mi;
+            }
+        }
+        wave_lds_sync();
+        // output nodes with arc length in [carry, carry + span) (up to N on the last tile)
+        const int nlo = (int)ceil(carry / uN);
+        const int nhi = last ? N : min(N, (int)ceil((carry + span) / uN));
+        const float il = (float)invL;
+        for (int nn = nlo + lane; nn < nhi; nn += 64) {
+            const float u = (float)((double)nn * uN - carry);
+            // largest j in [0, kt - 2] with sS[j] <= u
+            int lo = 0, hi = kt - 2;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (sS[mid] <= u) lo = mid; else hi = mid - 1;
+            }
+            const int j = lo;
+            const float hj = sH[kFtH + j];
+            const float bb = u - sS[j];
+            const float aa = hj - bb;
+            const cf qj = sP[kFtH + j], qp = sP[kFtH + j + 1];
+            cf z;
+            if (mode == CA_RESAMPLE_SPLINE) {
+                const cf mj = sM[j], mp = sM[j + 1];
+                const float ih = 1.0f / hj;
+                const float ca = aa * aa * aa * ih * (1.0f / 6.0f);
+                const float cb = bb * bb * bb * ih * (1.0f / 6.0f);
+                const float h6 = hj * hj * (1.0f / 6.0f);
+                const float ua = aa * ih, ub = bb * ih;
+                z.x = mj.x * ca + mp.x * cb + (qj.x - mj.x * h6) * ua + (qp.x - mp.x * h6) * ub;
+                z.y = mj.y * ca + mp.y * cb + (qj.y - mj.y * h6) * ua + (qp.y - mp.y * h6) * ub;
+            } else {
+                const float ub = bb / hj, ua = 1.0f - ub;
+                z.x = qj.x * ua + qp.x * ub;
+                z.y = qj.y * ua + qp.y * ub;
+            }
+            z.x *= il;
+            z.y *= il;
+            o[nn] = z;
+            sx += z.x;
+            sy += z.y;
+        }
+        carry += span;
+        wave_lds_sync();
+    }
+    // pass 3: centre on the node mean, norms (other lanes wrote these nodes)
+    __syncthreads();
+    sx = wave_sum_d(sx);
+    sy = wave_sum_d(sy);
+    const float mx = (float)(sx / N), my = (float)(sy / N);
+    double q2 = 0.0;
+    for (int nn = lane; nn < N; nn += 64) {
+        cf z = o[nn];
+        z.x -= mx;
+        z.y -= my;
+        o[nn] = z;
+        q2 = fma((double)z.x, (double)z.x, fma((double)z.y, (double)z.y, q2));
+    }
+    q2 = wave_sum_d(q2);
+    if (lane == 0) {
+        if (norms) norms[c] = q2 / N;
+        if (flags) flags[c] = 0;
+    }
+}
+
+__global__ void k_zero_int(int* p) { *p = 0; }
+
 hipError_t launch_resample(const void* raw, const int64_t* raw_off, int64_t num_curves,
                            const int64_t* out_off, void* out, double* norms, uint32_t* flags, int mode,
-                           void* scratch, int64_t slot_bytes, int64_t slots, hipStream_t s) {
+                           void* scratch, int64_t slot_bytes, int64_t slots, int* slow_count, int* slow_list,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, slow_count);
+    hipLaunchKernelGGL(k_resample_fast, dim3((unsigned)num_curves), dim3(64), 0, s, (const cf*)raw, raw_off,
+                       num_curves, out_off, (cf*)out, norms, flags, mode, slow_count, slow_list);
     const int64_t grid = num_curves < slots ? num_curves : slots;
     hipLaunchKernelGGL(k_resample, dim3((unsigned)grid), dim3(kRsNT), 0, s, (const cf*)raw, raw_off,
                        num_curves, out_off, (cf*)out, norms, flags, mode, (unsigned char*)scratch,
-                       slot_bytes);
+                       slot_bytes, (const int*)slow_count, (const int*)slow_list);
     return hipGetLastError();
 }
 
