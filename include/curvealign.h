@@ -74,7 +74,7 @@ typedef struct {
 enum {
     CA_FLAG_NEAR_TIE = 1u << 0,     /* best and runner-up |C| within 1e-6 relative   */
     CA_FLAG_RESCORED = 1u << 1,     /* more than one shift was re-scored in FP64     */
-    CA_FLAG_CAND_CAPPED = 1u << 2,  /* candidate window exceeded its cap (32)        */
+    CA_FLAG_CAND_CAPPED = 1u << 2,  /* candidate window held more than 32 shifts     */
     CA_FLAG_DEGENERATE = 1u << 3,   /* a curve has zero norm; shift 0, theta 0,
                                        e0 = n1 + n2                                  */
     CA_FLAG_NONFINITE = 1u << 4,    /* NaN/Inf in the input; shift 0, theta 0, e0 NaN */
@@ -89,7 +89,9 @@ enum { CA_PREC_FP32 = 0, CA_PREC_SPLIT_BF16 = 1, CA_PREC_FP64 = 2 };
  *   TOP2   (default): the FP32 best and runner-up, when their |C| gap is below
  *          twice the FP32 error bound.
  *   WINDOW: every shift whose FP32 |C| lies within twice the error bound of
- *          the maximum, at most 32 (CA_FLAG_CAND_CAPPED beyond; then TOP2).   */
+ *          the maximum; beyond 32 such shifts (CA_FLAG_CAND_CAPPED) the 32
+ *          largest are kept (power-of-two n up to 1024 and the split-BF16
+ *          path, by bisection on |C|^2) or the TOP2 pair (other n).          */
 enum { CA_RESCORE_TOP2 = 0, CA_RESCORE_WINDOW = 1 };
 
 enum { CA_RESAMPLE_SPLINE = 0, CA_RESAMPLE_LINEAR = 1 };
@@ -134,7 +136,9 @@ ca_status_t align_pair(ca_context_t ctx, const void* z1, const void* z2, int32_t
  *     [offsets[p], offsets[p+1]) of both z1 and z2; `n` is ignored.  A pair
  *     whose size is not supported gets CA_FLAG_UNSUPPORTED_N and is skipped.
  *   out: num_pairs results in device memory (pair order).
- *   precision SPLIT_BF16 requires a uniform batch with n == 128.
+ *   precision SPLIT_BF16 requires a uniform batch with n == 128; it always
+ *   re-scores the whole candidate window (its |C| error, ~1e-5 relative, is
+ *   above the near-tie threshold), so options.rescore is ignored there.
  * num_pairs == 0 is a no-op.
  */
 ca_status_t align_batch(ca_context_t ctx, const void* z1, const void* z2,

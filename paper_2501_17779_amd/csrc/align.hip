@@ -6,174 +6,10 @@
 //  separate inverse transform.)
 #include <math.h>
 
-#include "fft_engines.hpp"
+#include "epilogue.hpp"
 #include "launch.hpp"
 
 namespace ca {
-
-// ------------------------------------------------------------ shared epilogue
-// Selection state of the FP64 re-scoring: best |C64|^2 (smallest shift on
-// equal values), its C64, and the second best value.
-struct Pick {
-    double best = -1.0, second = -1.0, re = 0.0, im = 0.0;
-    int shift = -1, count = 0;
-    __device__ __forceinline__ void offer(int c, double r, double i) {
-        const double m = r * r + i * i;
-        if (m > best || (m == best && c < shift)) {
-            second = best; best = m; shift = c; re = r; im = i;
-        } else if (m > second) {
-            second = m;
-        }
-        ++count;
-    }
-};
-
-__device__ __forceinline__ float wrap_pi(float a) {
-    const float pi = 3.14159265358979323846f;
-    return (a <= -pi) ? pi : a;
-}
-__device__ __forceinline__ double wrap_pi(double a) {
-    const double pi = 3.14159265358979323846;
-    return (a <= -pi) ? pi : a;
-}
-
-__device__ __forceinline__ void finish(ca_result_t& res, const Pick& pk, int n, double n1, double n2,
-                                       double d1, double d2, double epsD, bool capped,
-                                       double theta_path, int theta64) {
-    uint32_t flags = 0;
-    const double c64 = sqrt(pk.best);
-    if (pk.count > 1) flags |= CA_FLAG_RESCORED;
-    if (capped) flags |= CA_FLAG_CAND_CAPPED;
-    double gap;
-    if (pk.count > 1 && pk.second >= 0.0) gap = (c64 - sqrt(pk.second)) / c64;
-    else gap = (d1 - d2) / d1;
-    if (gap < kNearTie) flags |= CA_FLAG_NEAR_TIE;
-    double th = theta_path;
-    if (theta64) {
-        th = wrap_pi(atan2(pk.im, pk.re));
-        flags |= CA_FLAG_THETA_FP64;
-    }
-    res.shift = pk.shift;
-    res.flags = flags;
-    res.theta = th;
-    res.err_est = (float)(2.0 * epsD / d1);
-    res.gap = (float)gap;
-    res.e0 = n1 + n2 - 2.0 * c64 / (double)n;
-}
-
-__device__ __forceinline__ bool special_case(ca_result_t& res, double n1, double n2, double bv) {
-    res.shift = 0;
-    res.theta = 0.0;
-    res.err_est = 0.0f;
-    res.gap = 0.0f;
-    if (!(isfinite(n1) && isfinite(n2) && isfinite(bv))) {
-        res.flags = CA_FLAG_NONFINITE;
-        res.e0 = __builtin_nan("");
-        return true;
-    }
-    if (!(n1 > 0.0) || !(n2 > 0.0) || !(bv > 0.0)) {
-        res.flags = CA_FLAG_DEGENERATE;
-        res.e0 = n1 + n2;
-        return true;
-    }
-    return false;
-}
-
-// --------------------------------------------------------------- team engine
-// Epilogue of one pair held by a team: d[q] = D[t + T q] (D = n conj C),
-// a0[q] = z1[t + T q] (FP32 nodes of curve 1), zb = LDS copy of curve 2's
-// nodes at padded positions, cand = the team's candidate list in LDS.
-// Returns the finished result (every lane).
-template <int N, int T>
-__device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const cf (&a0)[N / T],
-                                                     const cf* zb, int* cand, int t, double n1, double n2,
-                                                     int rescore, int theta64) {
-    constexpr int R = N / T;
-    float m2[R];
-    float bv = -1.0f;
-    int bi = 0;
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-        m2[q] = norm2(d[q]);
-        if (m2[q] > bv) { bv = m2[q]; bi = t + T * q; }
-    }
-    team_argmax<T>(bv, bi);
-    float cv = -1.0f;
-    int ci = 0;
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-        const int idx = t + T * q;
-        if (idx != bi && m2[q] > cv) { cv = m2[q]; ci = idx; }
-    }
-    team_argmax<T>(cv, ci);
-
-    ca_result_t res;
-    if (special_case(res, n1, n2, (double)bv)) return res;
-    const double d1 = sqrt((double)bv), d2 = sqrt(fmax((double)cv, 0.0));
-    const double epsD = kErrScale * num<float>::u * (double)ilog2_ceil(N) * N * N * sqrt(n1 * n2);
-    const bool two = d1 - d2 < 2.0 * epsD;
-
-    // candidate list (team-uniform order: by register, then by lane)
-    int cnt = 0;
-    bool capped = false;
-    if (rescore == CA_RESCORE_WINDOW) {
-        const double thr = d1 - 2.0 * epsD;
-        const float thr2 = thr > 0.0 ? (float)(thr * thr) : 0.0f;
-        int loc = 0;
-#pragma unroll
-        for (int q = 0; q < R; ++q) loc += (m2[q] >= thr2) ? 1 : 0;
-        const int total = team_sum<T>(loc);
-        if (thr > 0.0 && total <= kCandCap) {
-            const int lane = threadIdx.x & 63;
-            const int base = lane - t;
-            const uint64_t tmask = (T == 64) ? ~0ull : (((1ull << T) - 1ull) << base);
-            const uint64_t below = (1ull << lane) - 1ull;
-#pragma unroll
-            for (int q = 0; q < R; ++q) {
-                const bool hit = m2[q] >= thr2;
-                const uint64_t msk = __ballot(hit) & tmask;
-                if (hit) cand[cnt + __popcll(msk & below)] = t + T * q;
-                cnt += __popcll(msk);
-            }
-        }
-        if (cnt == 0) capped = true;
-    }
-    if (rescore != CA_RESCORE_WINDOW || capped) {
-        if (t == 0) {
-            cand[0] = bi;
-            cand[1] = ci;
-        }
-        cnt = two ? 2 : 1;
-    }
-    wave_lds_sync();
-    Pick pk;
-    for (int k = 0; k < cnt; ++k) {
-        const int c = cand[k];
-        double re = 0.0, im = 0.0;
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const cf zz = zb[lpad((t + T * q - c) & (N - 1))];
-            const double ax = a0[q].x, ay = a0[q].y, bx = zz.x, by = zz.y;
-            re = fma(ax, bx, fma(ay, by, re));
-            im = fma(ay, bx, fma(-ax, by, im));
-        }
-        re = team_sum<T>(re);
-        im = team_sum<T>(im);
-        pk.offer(c, re, im);
-    }
-    wave_lds_sync();
-    // the path's own C at the chosen shift: arg C = atan2(-Im D, Re D)
-    const int qs = pk.shift / T, ls = pk.shift % T;
-    cf sel = d[0];
-#pragma unroll
-    for (int q = 1; q < R; ++q)
-        if (q == qs) sel = d[q];
-    sel.x = __shfl(sel.x, ls, T);
-    sel.y = __shfl(sel.y, ls, T);
-    const double thp = (double)wrap_pi(atan2f(-sel.y, sel.x));
-    finish(res, pk, N, n1, n2, d1, d2, epsD, capped, thp, theta64);
-    return res;
-}
 
 template <int TW>
 __device__ __forceinline__ void load_twiddles(cf* tws, const cf* __restrict__ tw) {

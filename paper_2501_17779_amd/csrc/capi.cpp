@@ -81,6 +81,7 @@ struct ca_context {
     void* d_tw32 = nullptr;   // float2 arena
     void* d_tw64 = nullptr;   // double2 arena
     void* d_team_tw[11] = {};  // per-pass team-engine twiddles, index log2(n)
+    void* d_bf16 = nullptr;    // split-BF16 per-lane constants (64 x 128 bytes)
     // resampler scratch and the list of curves for the general kernel
     void* d_rs = nullptr;
     int64_t rs_slots = 0;
@@ -199,6 +200,69 @@ ca_status_t ensure_team_tables(ca_context* c) {
     return CA_OK;
 }
 
+// BF16 round-to-nearest-even of a float; the split of w into hi + lo.
+uint16_t bf16_rne(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+double bf16_value(uint16_t h) {
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+void split_bf16(double w, uint16_t& hi, uint16_t& lo) {
+    hi = bf16_rne((float)w);
+    lo = bf16_rne((float)(w - bf16_value(hi)));
+}
+
+// Per-lane operands of the n = 128 split-BF16 kernel (layout of Bf16Lane).
+ca_status_t ensure_bf16_tables(ca_context* c) {
+    if (c->d_bf16) return CA_OK;
+    struct Lane {
+        uint16_t s1[4][8];
+        uint16_t s2[2][8];
+        float tw[4][2];
+    };
+    static_assert(sizeof(Lane) == 128, "lane block");
+    std::vector<Lane> lanes(64);
+    const long double tp = 6.283185307179586476925286766559005768L;
+    auto wr = [&](int a, int b, int m) { return (double)cosl(tp * (long double)((a * b) % m) / m); };
+    auto wi = [&](int a, int b, int m) { return (double)-sinl(tp * (long double)((a * b) % m) / m); };
+    for (int l = 0; l < 64; ++l) {
+        const int i = l % 16;
+        for (int e = 0; e < 8; ++e) {
+            const int k = 8 * (l / 16) + e;
+            // stage 1: rows k1 = i; columns (Re n1 0..15, Im n1 0..15)
+            const int n1 = k & 15;
+            const double are = k < 16 ? wr(i, n1, 16) : -wi(i, n1, 16);
+            const double aim = k < 16 ? wi(i, n1, 16) : wr(i, n1, 16);
+            split_bf16(are, lanes[l].s1[0][e], lanes[l].s1[1][e]);
+            split_bf16(aim, lanes[l].s1[2][e], lanes[l].s1[3][e]);
+            // stage 2: rows (Re k2 0..7, Im k2 0..7); columns (Re n2 0..7, Im n2 0..7), twice
+            const int kk = k & 15, n2 = kk & 7, k2 = i & 7;
+            double a2;
+            if (i < 8) a2 = kk < 8 ? wr(k2, n2, 8) : -wi(k2, n2, 8);
+            else a2 = kk < 8 ? wi(k2, n2, 8) : wr(k2, n2, 8);
+            uint16_t h, lo;
+            split_bf16(a2, h, lo);
+            lanes[l].s2[0][e] = h;
+            lanes[l].s2[1][e] = k < 16 ? lo : (uint16_t)0;
+        }
+        for (int r = 0; r < 4; ++r) {
+            const int n2 = l % 8, k1 = 4 * (l / 16) + r;
+            lanes[l].tw[r][0] = (float)wr(n2, k1, 128);
+            lanes[l].tw[r][1] = (float)wi(n2, k1, 128);
+        }
+    }
+    if (hipMalloc(&c->d_bf16, sizeof(Lane) * 64) != hipSuccess) return fail(CA_ERR_OOM, "BF16 constants");
+    hipError_t e = hipMemcpy(c->d_bf16, lanes.data(), sizeof(Lane) * 64, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "BF16 constants upload");
+    return CA_OK;
+}
+
 const void* team_tw_for(ca_context* c, int n) {
     int lg = 0;
     while ((1 << lg) < n) ++lg;
@@ -274,6 +338,7 @@ ca_status_t ca_destroy(ca_context_t c) {
         if (c->d_tw64) (void)hipFree(c->d_tw64);
         for (void* p : c->d_team_tw)
             if (p) (void)hipFree(p);
+        if (c->d_bf16) (void)hipFree(c->d_bf16);
         if (c->d_rs) (void)hipFree(c->d_rs);
         if (c->d_slow) (void)hipFree(c->d_slow);
         if (c->d_spec) (void)hipFree(c->d_spec);
@@ -296,15 +361,19 @@ ca_status_t align_batch(ca_context_t c, const void* z1, const void* z2, const in
     if (num_pairs > 0x7fffffffLL) return fail(CA_ERR_INVALID_ARG, "num_pairs exceeds 2^31 - 1");
     if (!offsets && !smooth7(n))
         return fail(CA_ERR_UNSUPPORTED_N, "n must be in [2, 4096] with prime factors 2, 3, 5, 7");
-    if (o.precision == CA_PREC_SPLIT_BF16)
-        return fail(CA_ERR_UNSUPPORTED_N, "split-BF16 precision is not available for this n");
+    if (o.precision == CA_PREC_SPLIT_BF16 && (offsets || n != 128))
+        return fail(CA_ERR_UNSUPPORTED_N, "split-BF16 precision needs a uniform batch with n = 128");
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
     st = ensure_tables(c, o.precision == CA_PREC_FP64);
     if (st != CA_OK) return st;
     hipError_t e;
-    if (o.precision == CA_PREC_FP32 && !offsets && ca::team_supported(n)) {
+    if (o.precision == CA_PREC_SPLIT_BF16) {
+        st = ensure_bf16_tables(c);
+        if (st != CA_OK) return st;
+        e = ca::launch_align_bf16(z1, z2, num_pairs, out, c->d_bf16, o.theta_fp64, c->num_cus, s);
+    } else if (o.precision == CA_PREC_FP32 && !offsets && ca::team_supported(n)) {
         st = ensure_team_tables(c);
         if (st != CA_OK) return st;
         e = ca::launch_align_team(z1, z2, n, num_pairs, out, team_tw_for(c, n), o.rescore, o.theta_fp64,

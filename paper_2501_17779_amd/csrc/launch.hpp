@@ -39,6 +39,12 @@ hipError_t launch_align_team(const void* z1, const void* z2, int n, int64_t num_
                              ca_result_t* out, const void* tw, int rescore, int theta64,
                              int num_cus, hipStream_t s);
 
+// Split-BF16 MFMA path, n = 128.  lane_consts: 64 per-lane blocks of 128
+// bytes (stage-1 and stage-2 DFT matrices as BF16 hi/lo operands in the
+// 16x16x32 MFMA A layout, and the stage-1 twiddles).
+hipError_t launch_align_bf16(const void* z1, const void* z2, int64_t num_pairs, ca_result_t* out,
+                             const void* lane_consts, int theta64, int num_cus, hipStream_t s);
+
 // All-pairs: per-curve spectra, then the upper-triangle tile kernel.
 hipError_t launch_spectra(const void* curves, int m, int n, void* spectra, double* norms,
                           const void* tw, hipStream_t s);
