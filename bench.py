@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--config", default="batch",
                     choices=["batch", "pair", "allpairs", "ragged", "bf16", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch every step from Python instead of replaying a captured HIP graph")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target wall time of the CPU oracle sample")
     return ap.parse_args()
@@ -64,20 +66,40 @@ def traffic_for(kernel_key: str, digest: str, per_launch_units: float):
     return float(e["bytes_per_unit"]) * per_launch_units
 
 
-def time_steps(fn, steps, warmup, torch):
+def graphed(fn, torch):
+    """Capture one call of fn (its kernel launches) in a HIP graph; returns a
+    replay function.  The first eager call builds the library's tables."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    torch.cuda.synchronize()
+    return g.replay
+
+
+def time_steps(fn, steps, warmup, torch, graph=False):
+    if graph:
+        fn = graphed(fn, torch)
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    start.record()
-    for _ in range(steps):
+    ev[0].record()
+    for i in range(steps):
         fn()
-    stop.record()
+        ev[i + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return start.elapsed_time(stop) / steps, wall
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    if os.environ.get("BENCH_PER_STEP"):
+        print("per-step ms:", " ".join(f"{x:.4f}" for x in per), file=sys.stderr, flush=True)
+    return ev[0].elapsed_time(ev[steps]) / steps, wall
 
 
 def cpu_baseline_batch(raw1, raw2, n, seconds):
@@ -113,10 +135,11 @@ def bench_batch(args, torch, ca):
     out = ca.empty_results(B, dev)
     torch.cuda.synchronize()
     assert int((flags != 0).sum().item()) == 0
-    ms, wall = time_steps(lambda: ca.align_batch(z1, z2, out=out), args.steps, args.warmup, torch)
+    ms, wall = time_steps(lambda: ca.align_batch(z1, z2, out=out), args.steps, args.warmup, torch,
+                          graph=not args.no_graph)
     algo_bytes = B * (2 * n * 8 + RESULT_BYTES)
     achieved = algo_bytes / (ms * 1e-3) / 1e9
-    digest = sources_digest(["align.hip", "fft_engines.hpp", "dft_small.hpp", "common.hpp"])
+    digest = sources_digest(["align.hip", "epilogue.hpp", "fft_engines.hpp", "dft_small.hpp", "common.hpp"])
     traffic = traffic_for("k_align_team_1024", digest, B)
     line = {
         "metric": "curve-pair alignments/sec at N=1024, FP32 vs split-BF16, err vs FP64 oracle",
@@ -132,6 +155,8 @@ def bench_batch(args, torch, ca):
         k = min(B, 8192)
         line["cpu_baseline"] = cpu_baseline_batch(r1[:k].cpu().numpy(), r2[:k].cpu().numpy(), n,
                                                   args.cpu_seconds)
+        line["accuracy"] = accuracy_sample(torch, ca, r1[:128].cpu().numpy(), r2[:128].cpu().numpy(), n,
+                                           ["fp32"], k=128)
     return line
 
 
@@ -167,6 +192,9 @@ def bench_pair(args, torch, ca):
                       "pairs": 1, "n": 256})
     line["steps"] = steps
     line["us_per_call"] = ms * 1e3
+    msg, _ = time_steps(lambda: ca.align_pair(z1, z2, precision="fp64", out=out), steps, args.warmup, torch,
+                        graph=True)
+    line["us_per_call_graph_replay"] = msg * 1e3
     return line
 
 
@@ -182,7 +210,8 @@ def bench_allpairs(args, torch, ca):
     g = g.view(M, n)
     P = M * (M - 1) // 2
     out = ca.empty_results(P, dev)
-    ms, _ = time_steps(lambda: ca.align_all_pairs(g, out=out), args.steps, args.warmup, torch)
+    ms, _ = time_steps(lambda: ca.align_all_pairs(g, out=out), args.steps, args.warmup, torch,
+                       graph=not args.no_graph)
     flops = P * (5 * n * 9 + 9 * n)       # correlation FFT + product + |C|^2, per pair
     achieved = flops / (ms * 1e-3) / 1e12
     line = base_line(args, P / (ms * 1e-3), "pairs/s", ms, "f32",
@@ -223,7 +252,7 @@ def bench_ragged(args, torch, ca):
         ca.resample_arclength(raw, roff, ooff, out=nodes, with_norms=False, with_flags=False)
         ca.align_batch(nodes[:half], nodes[half:], offsets=off, out=out)
 
-    ms, _ = time_steps(step, args.steps, args.warmup, torch)
+    ms, _ = time_steps(step, args.steps, args.warmup, torch, graph=not args.no_graph)
     algo = raw.numel() * 8 + B * RESULT_BYTES
     achieved = algo / (ms * 1e-3) / 1e9
     line = base_line(args, B / (ms * 1e-3), "pairs/s", ms, "f32",
@@ -235,8 +264,45 @@ def bench_ragged(args, torch, ca):
     return line
 
 
+def accuracy_sample(torch, ca, raw1, raw2, n, precisions, k=256):
+    """Accuracy against the FP64 oracle on k pairs of the workload: the raw
+    polygons are resampled by the oracle, aligned on the GPU with each
+    precision and by the oracle, and compared (max/mean theta and e0 error,
+    shift mismatches outside near-ties)."""
+    import oracle
+    from oracle import resample_ref as rr
+    z1 = np.stack([rr.resample(raw1[i].astype(np.float64), n)[0] for i in range(k)]).astype(np.complex64)
+    z2 = np.stack([rr.resample(raw2[i].astype(np.float64), n)[0] for i in range(k)]).astype(np.complex64)
+    orc = []
+    for i in range(k):
+        T, th, m, thp = oracle.per_shift_arrays(z1[i], z2[i])
+        orc.append((T, th, m, thp))
+    out = {}
+    for prec in precisions:
+        res = ca.to_numpy(ca.align_batch(torch.from_numpy(z1).cuda(), torch.from_numpy(z2).cuda(),
+                                         precision=prec))
+        dth, de, mism, near = [], [], 0, 0
+        for i in range(k):
+            T, th, m, thp = orc[i]
+            s0 = int(np.argmax(T))
+            T2 = np.max(np.delete(T, s0))
+            s = int(res["shift"][i])
+            if (T[s0] - T2) / T[s0] < 1e-6:
+                near += 1
+            elif s != s0:
+                mism += 1
+            dth.append(abs(float(oracle.wrap_angle(res["theta"][i] - th[s]))))
+            E = oracle.energy(z1[i], z2[i], int(m[s]), float(thp[s]))
+            de.append(abs(res["e0"][i] - E) / max(E, 1e-300))
+        out[prec] = {"pairs": k, "theta_err_max": max(dth), "theta_err_mean": float(np.mean(dth)),
+                     "e0_rel_err_max": max(de), "e0_rel_err_mean": float(np.mean(de)),
+                     "shift_mismatch_outside_near_ties": mism, "near_ties": near}
+    return out
+
+
 def bench_small_batch(args, torch, ca):
-    """1,048,576 pairs at n = 128 (FP32 team engine; split-BF16 when available)."""
+    """1,048,576 pairs at n = 128: split-BF16 MFMA path, with the FP32 FFT path
+    timed on the same inputs."""
     from synth import curves
     B, n = 1 << 20, 128
     dev = torch.device("cuda:0")
@@ -246,13 +312,26 @@ def bench_small_batch(args, torch, ca):
     nodes, _, _ = ca.resample_arclength(raw, roff, roff)
     z1, z2 = nodes[: B * n].view(B, n), nodes[B * n:].view(B, n)
     out = ca.empty_results(B, dev)
-    ms, _ = time_steps(lambda: ca.align_batch(z1, z2, out=out), args.steps, args.warmup, torch)
-    algo = B * (2 * n * 8 + RESULT_BYTES)
-    achieved = algo / (ms * 1e-3) / 1e9
-    line = base_line(args, B / (ms * 1e-3), "pairs/s", ms, "f32",
-                     {"workload": "batch of 1048576 curve pairs, n=128 nodes, FP32", "pairs": B, "n": n})
-    line["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    ms16, _ = time_steps(lambda: ca.align_batch(z1, z2, precision="split_bf16", out=out), args.steps,
+                         args.warmup, torch, graph=not args.no_graph)
+    ms32, _ = time_steps(lambda: ca.align_batch(z1, z2, out=out), args.steps, args.warmup, torch,
+                         graph=not args.no_graph)
+    flops = B * 3 * 3 * (2 * 32 * 32 * 8 + 2 * 16 * 16 * 16)   # split products x transforms x stages
+    achieved = flops / (ms16 * 1e-3) / 1e12
+    line = base_line(args, B / (ms16 * 1e-3), "pairs/s", ms16, "bf16x3 (fp32 accumulate)",
+                     {"workload": "batch of 1048576 curve pairs, n=128 nodes, split-BF16 MFMA DFT vs FP32 FFT",
+                      "pairs": B, "n": n})
+    line["fp32_same_inputs"] = {"value": B / (ms32 * 1e-3), "ms_per_step": ms32,
+                                "hbm_frac": B * (2 * n * 8 + RESULT_BYTES) / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    line["speedup_vs_fp32"] = ms32 / ms16
+    line["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",
+                        "frac": achieved / 2500.0, "traffic": None}
+    if not args.no_cpu_baseline:
+        k = 4096
+        line["cpu_baseline"] = cpu_baseline_batch(r1[:k].cpu().numpy(), r2[:k].cpu().numpy(), n,
+                                                  args.cpu_seconds)
+        line["accuracy"] = accuracy_sample(torch, ca, r1[:256].cpu().numpy(), r2[:256].cpu().numpy(), n,
+                                           ["fp32", "split_bf16"])
     return line
 
 

@@ -280,137 +280,164 @@ hipError_t launch_allpairs(const void* curves, const void* spec, const double* n
 }
 
 // -------------------------------------------------------------- block engine
-template <typename T, int NT>
+// Persistent kernels, one pair per workgroup at a time; each launch serves
+// the pairs whose size lies in [nlo, nhi] (a size class) with NT threads and
+// LDS for NMAX nodes per signal.  Unsupported sizes are flagged by the class
+// that has nlo == 0.
+template <typename T, int NT, int NMAX>
 __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1, const cpx<T>* __restrict__ z2,
                                                   const int64_t* __restrict__ offsets, int n_uniform,
                                                   int64_t num_pairs, ca_result_t* __restrict__ out,
                                                   const Plan* __restrict__ plans,
-                                                  const cpx<T>* __restrict__ arena, int rescore, int theta64) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+                                                  const cpx<T>* __restrict__ arena, int rescore, int theta64,
+                                                  int nlo, int nhi) {
+    __shared__ cpx<T> A[NMAX];
+    __shared__ cpx<T> B[NMAX];
     __shared__ double red[2 * (NT / 64)];
     __shared__ int clist[kCandCap + 1];
-    const int64_t pair = blockIdx.x;
-    if (pair >= num_pairs) return;
-    int64_t off;
-    int n;
-    if (offsets) {
-        off = offsets[pair];
-        const int64_t len = offsets[pair + 1] - off;
-        n = (len >= 2 && len <= kMaxN) ? (int)len : 0;
-    } else {
-        off = pair * (int64_t)n_uniform;
-        n = n_uniform;
-    }
-    if (n == 0 || plans[n].n != n) {
-        if (threadIdx.x == 0) {
-            ca_result_t r;
-            r.shift = 0; r.flags = CA_FLAG_UNSUPPORTED_N; r.theta = 0.0; r.err_est = 0.0f; r.gap = 0.0f;
-            r.e0 = __builtin_nan("");
-            out[pair] = r;
+    for (int64_t pair = blockIdx.x; pair < num_pairs; pair += gridDim.x) {
+        int64_t off;
+        int n;
+        bool bad = false;
+        if (offsets) {
+            off = offsets[pair];
+            const int64_t len = offsets[pair + 1] - off;
+            n = (len >= 2 && len <= kMaxN) ? (int)len : 0;
+            bad = n == 0 || plans[n].n != n;
+        } else {
+            off = pair * (int64_t)n_uniform;
+            n = n_uniform;
         }
-        return;
-    }
-    const Plan& p = plans[n];
-    const cpx<T>* tw = arena + p.tw_off;
-    cpx<T>* A = reinterpret_cast<cpx<T>*>(smem);
-    cpx<T>* B = A + n;
-    const cpx<T>* pa = z1 + off;
-    const cpx<T>* pb = z2 + off;
-
-    double q1 = 0.0, q2 = 0.0;
-    for (int k = threadIdx.x; k < n; k += NT) {
-        const cpx<T> a = pa[k], b = pb[k];
-        A[k] = a;
-        B[k] = b;
-        q1 = fma((double)a.x, (double)a.x, fma((double)a.y, (double)a.y, q1));
-        q2 = fma((double)b.x, (double)b.x, fma((double)b.y, (double)b.y, q2));
-    }
-    const double n1 = block_sum<NT>(q1, red) / n;   // block_sum synchronises
-    const double n2 = block_sum<NT>(q2, red) / n;
-    blk_fft<NT>(A, p, tw);
-    blk_fft<NT>(B, p, tw);
-    for (int k = threadIdx.x; k < n; k += NT) A[k] = cjmul(A[k], B[k]);
-    __syncthreads();
-    blk_fft<NT>(A, p, tw);
-    for (int k = threadIdx.x; k < n; k += NT) B[k] = pb[k];   // z2 again, for re-scoring
-
-    T bv = T(-1);
-    int bi = 0;
-    for (int k = threadIdx.x; k < n; k += NT) {
-        const T m = norm2(A[k]);
-        if (m > bv) { bv = m; bi = k; }
-    }
-    block_argmax<NT>(bv, bi, red);
-    T cv = T(-1);
-    int ci = 0;
-    for (int k = threadIdx.x; k < n; k += NT) {
-        const T m = norm2(A[k]);
-        if (k != bi && m > cv) { cv = m; ci = k; }
-    }
-    block_argmax<NT>(cv, ci, red);
-
-    ca_result_t res;
-    if (!special_case(res, n1, n2, (double)bv)) {
-        const double d1 = sqrt((double)bv), d2 = sqrt(fmax((double)cv, 0.0));
-        double lg = 0.0;
-        for (int m = 1; m < n; m <<= 1) lg += 1.0;
-        const double epsD = kErrScale * num<T>::u * lg * (double)n * (double)n * sqrt(n1 * n2);
-        Pick pk;
-        auto rescore_one = [&](int c) {
-            double re = 0.0, im = 0.0;
-            for (int k = threadIdx.x; k < n; k += NT) {
-                int idx = k - c;
-                if (idx < 0) idx += n;
-                const cpx<T> a = pa[k], b = B[idx];
-                const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
-                re = fma(ax, bx, fma(ay, by, re));
-                im = fma(ay, bx, fma(-ax, by, im));
+        if (bad) {
+            if (nlo == 0 && threadIdx.x == 0) {
+                ca_result_t r;
+                r.shift = 0; r.flags = CA_FLAG_UNSUPPORTED_N; r.theta = 0.0; r.err_est = 0.0f; r.gap = 0.0f;
+                r.e0 = __builtin_nan("");
+                out[pair] = r;
             }
-            re = block_sum<NT>(re, red);
-            im = block_sum<NT>(im, red);
-            pk.offer(c, re, im);
-        };
-        bool capped = false;
-        if (rescore == CA_RESCORE_WINDOW) {
-            const double thr = d1 - 2.0 * epsD;
-            const double thr2 = thr > 0.0 ? thr * thr : 0.0;
-            if (threadIdx.x == 0) clist[0] = 0;
-            __syncthreads();
-            for (int k = threadIdx.x; k < n; k += NT) {
-                if ((double)norm2(A[k]) >= thr2) {
-                    const int pos = atomicAdd(&clist[0], 1);
-                    if (pos < kCandCap) clist[1 + pos] = k;
+            continue;
+        }
+        if (n < nlo || n > nhi) continue;
+        const Plan& p = plans[n];
+        const cpx<T>* tw = arena + p.tw_off;
+        const cpx<T>* pa = z1 + off;
+        const cpx<T>* pb = z2 + off;
+
+        double q1 = 0.0, q2 = 0.0;
+        for (int k = threadIdx.x; k < n; k += NT) {
+            const cpx<T> a = pa[k], b = pb[k];
+            A[k] = a;
+            B[k] = b;
+            q1 = fma((double)a.x, (double)a.x, fma((double)a.y, (double)a.y, q1));
+            q2 = fma((double)b.x, (double)b.x, fma((double)b.y, (double)b.y, q2));
+        }
+        const double n1 = block_sum<NT>(q1, red) / n;   // block_sum synchronises
+        const double n2 = block_sum<NT>(q2, red) / n;
+        blk_fft<NT, NMAX>(A, p, tw);
+        blk_fft<NT, NMAX>(B, p, tw);
+        for (int k = threadIdx.x; k < n; k += NT) A[k] = cjmul(A[k], B[k]);
+        __syncthreads();
+        blk_fft<NT, NMAX>(A, p, tw);
+        for (int k = threadIdx.x; k < n; k += NT) B[k] = pb[k];   // z2 again, for re-scoring
+
+        T bv = T(-1);
+        int bi = 0;
+        for (int k = threadIdx.x; k < n; k += NT) {
+            const T m = norm2(A[k]);
+            if (m > bv) { bv = m; bi = k; }
+        }
+        block_argmax<NT>(bv, bi, red);
+        T cv = T(-1);
+        int ci = 0;
+        for (int k = threadIdx.x; k < n; k += NT) {
+            const T m = norm2(A[k]);
+            if (k != bi && m > cv) { cv = m; ci = k; }
+        }
+        block_argmax<NT>(cv, ci, red);
+
+        ca_result_t res;
+        if (!special_case(res, n1, n2, (double)bv)) {
+            const double d1 = sqrt((double)bv), d2 = sqrt(fmax((double)cv, 0.0));
+            double lg = 0.0;
+            for (int m = 1; m < n; m <<= 1) lg += 1.0;
+            const double epsD = kErrScale * num<T>::u * lg * (double)n * (double)n * sqrt(n1 * n2);
+            Pick pk;
+            auto rescore_one = [&](int c) {
+                double re = 0.0, im = 0.0;
+                for (int k = threadIdx.x; k < n; k += NT) {
+                    int idx = k - c;
+                    if (idx < 0) idx += n;
+                    const cpx<T> a = pa[k], b = B[idx];
+                    const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
+                    re = fma(ax, bx, fma(ay, by, re));
+                    im = fma(ay, bx, fma(-ax, by, im));
+                }
+                re = block_sum<NT>(re, red);
+                im = block_sum<NT>(im, red);
+                pk.offer(c, re, im);
+            };
+            bool capped = false;
+            if (rescore == CA_RESCORE_WINDOW) {
+                const double thr = d1 - 2.0 * epsD;
+                const double thr2 = thr > 0.0 ? thr * thr : 0.0;
+                if (threadIdx.x == 0) clist[0] = 0;
+                __syncthreads();
+                for (int k = threadIdx.x; k < n; k += NT) {
+                    if ((double)norm2(A[k]) >= thr2) {
+                        const int pos = atomicAdd(&clist[0], 1);
+                        if (pos < kCandCap) clist[1 + pos] = k;
+                    }
+                }
+                __syncthreads();
+                const int cnt = clist[0];
+                if (thr > 0.0 && cnt <= kCandCap) {
+                    for (int c = 0; c < cnt; ++c) rescore_one(clist[1 + c]);
+                } else {
+                    capped = true;
                 }
             }
-            __syncthreads();
-            const int cnt = clist[0];
-            if (thr > 0.0 && cnt <= kCandCap) {
-                for (int c = 0; c < cnt; ++c) rescore_one(clist[1 + c]);
-            } else {
-                capped = true;
+            if (rescore != CA_RESCORE_WINDOW || capped || pk.count == 0) {
+                rescore_one(bi);
+                if (d1 - d2 < 2.0 * epsD) rescore_one(ci);
             }
+            const cpx<T> sel = A[pk.shift];
+            const double thp = wrap_pi(atan2(-(double)sel.y, (double)sel.x));
+            finish(res, pk, n, n1, n2, d1, d2, epsD, capped, thp, theta64);
         }
-        if (rescore != CA_RESCORE_WINDOW || capped || pk.count == 0) {
-            rescore_one(bi);
-            if (d1 - d2 < 2.0 * epsD) rescore_one(ci);
-        }
-        const cpx<T> sel = A[pk.shift];
-        const double thp = wrap_pi(atan2(-(double)sel.y, (double)sel.x));
-        finish(res, pk, n, n1, n2, d1, d2, epsD, capped, thp, theta64);
+        if (threadIdx.x == 0) out[pair] = res;
+        __syncthreads();
     }
-    if (threadIdx.x == 0) out[pair] = res;
 }
 
-size_t blk_dynamic_lds(int n_max, size_t elem) { return 2 * (size_t)n_max * elem; }
 
+template <typename T, int NT, int NMAX>
+static hipError_t launch_blk_class(const BlkArgs& a, int nlo, int nhi, hipStream_t s) {
+    static int per_cu = -1;
+    if (per_cu < 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_align_blk<T, NT, NMAX>, NT, 0) != hipSuccess ||
+            nb < 1)
+            nb = 1;
+        per_cu = nb;
+    }
+    int64_t grid = (int64_t)a.num_cus * per_cu;
+    if (grid > a.num_pairs) grid = a.num_pairs;
+    hipLaunchKernelGGL((k_align_blk<T, NT, NMAX>), dim3((unsigned)grid), dim3(NT), 0, s,
+                       (const cpx<T>*)a.z1, (const cpx<T>*)a.z2, a.offsets, a.n_uniform, a.num_pairs, a.out,
+                       a.plans, (const cpx<T>*)a.tw_arena, a.rescore, a.theta64, nlo, nhi);
+    return hipGetLastError();
+}
+
+// Size classes: (64 threads, n <= 512), (128, <= 1024), (256, <= 2048), (256, <= 4096).
 template <typename T>
 static hipError_t launch_blk(const BlkArgs& a, hipStream_t s) {
-    constexpr int NT = 256;
-    const size_t lds = blk_dynamic_lds(a.n_max, sizeof(cpx<T>));
-    hipLaunchKernelGGL((k_align_blk<T, NT>), dim3((unsigned)a.num_pairs), dim3(NT), lds, s,
-                       (const cpx<T>*)a.z1, (const cpx<T>*)a.z2, a.offsets, a.n_uniform, a.num_pairs,
-                       a.out, a.plans, (const cpx<T>*)a.tw_arena, a.rescore, a.theta64);
-    return hipGetLastError();
+    const int lo = a.offsets ? 0 : a.n_uniform, hi = a.offsets ? kMaxN : a.n_uniform;
+    hipError_t e = hipSuccess;
+    if (lo <= 512 && e == hipSuccess) e = launch_blk_class<T, 64, 512>(a, a.offsets ? 0 : lo, 512, s);
+    if (hi > 512 && lo <= 1024 && e == hipSuccess) e = launch_blk_class<T, 128, 1024>(a, 513, 1024, s);
+    if (hi > 1024 && lo <= 2048 && e == hipSuccess) e = launch_blk_class<T, 256, 2048>(a, 1025, 2048, s);
+    if (hi > 2048 && e == hipSuccess) e = launch_blk_class<T, 256, 4096>(a, 2049, 4096, s);
+    return e;
 }
 
 hipError_t launch_align_blk_f32(const BlkArgs& a, hipStream_t s) { return launch_blk<float>(a, s); }

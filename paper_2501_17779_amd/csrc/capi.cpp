@@ -390,9 +390,7 @@ ca_status_t align_batch(ca_context_t c, const void* z1, const void* z2, const in
         a.plans = c->d_plans;
         a.rescore = o.rescore;
         a.theta64 = o.theta_fp64;
-        const size_t elem = o.precision == CA_PREC_FP64 ? 16 : 8;
-        if (ca::blk_dynamic_lds(a.n_max, elem) + 1024 > c->lds_per_block)
-            return fail(CA_ERR_UNSUPPORTED_N, "curve size needs more LDS than one workgroup has");
+        a.num_cus = c->num_cus;
         if (o.precision == CA_PREC_FP64) {
             a.tw_arena = c->d_tw64;
             e = ca::launch_align_blk_f64(a, s);

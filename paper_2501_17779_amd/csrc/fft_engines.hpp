@@ -35,17 +35,28 @@ struct Plan {
     int64_t tw_off;      // offset of the w_n^m table in the twiddle arena
 };
 
-template <int R, int NT, typename T>
+// j mod ns for 0 <= j < 2^13 and ns >= 1 through a float reciprocal and one
+// correction step (the quotient estimate is off by at most one).
+__device__ __forceinline__ int mod_small(int j, int ns, float inv_ns) {
+    int q = (int)((float)j * inv_ns);
+    int r = j - q * ns;
+    if (r < 0) r += ns;
+    else if (r >= ns) r -= ns;
+    return r;
+}
+
+template <int R, int NT, int NMAX, typename T>
 __device__ __forceinline__ void blk_pass(cpx<T>* buf, int n, int ns, const cpx<T>* __restrict__ tw) {
-    constexpr int UM = (kMaxN / R + NT - 1) / NT;
+    constexpr int UM = (NMAX / R + NT - 1) / NT;
     const int nb = n / R;
     const int tstride = n / (ns * R);
+    const float inv_ns = 1.0f / (float)ns;
     cpx<T> v[UM][R];
 #pragma unroll
     for (int u = 0; u < UM; ++u) {
         const int j = threadIdx.x + u * NT;
         if (j < nb) {
-            const int k = j % ns;
+            const int k = mod_small(j, ns, inv_ns);
 #pragma unroll
             for (int r = 0; r < R; ++r) v[u][r] = buf[j + r * nb];
             if (ns > 1) {
@@ -60,7 +71,7 @@ __device__ __forceinline__ void blk_pass(cpx<T>* buf, int n, int ns, const cpx<T
     for (int u = 0; u < UM; ++u) {
         const int j = threadIdx.x + u * NT;
         if (j < nb) {
-            const int k = j % ns;
+            const int k = mod_small(j, ns, inv_ns);
             const int base = (j - k) * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) buf[base + r * ns] = v[u][r];
@@ -69,18 +80,18 @@ __device__ __forceinline__ void blk_pass(cpx<T>* buf, int n, int ns, const cpx<T
     __syncthreads();
 }
 
-template <int NT, typename T>
+template <int NT, int NMAX, typename T>
 __device__ void blk_fft(cpx<T>* buf, const Plan& p, const cpx<T>* __restrict__ tw) {
     int ns = 1;
     for (int i = 0; i < p.npass; ++i) {
         const int r = p.radix[i];
         switch (r) {
-            case 2: blk_pass<2, NT>(buf, p.n, ns, tw); break;
-            case 3: blk_pass<3, NT>(buf, p.n, ns, tw); break;
-            case 4: blk_pass<4, NT>(buf, p.n, ns, tw); break;
-            case 5: blk_pass<5, NT>(buf, p.n, ns, tw); break;
-            case 7: blk_pass<7, NT>(buf, p.n, ns, tw); break;
-            default: blk_pass<8, NT>(buf, p.n, ns, tw); break;
+            case 2: blk_pass<2, NT, NMAX>(buf, p.n, ns, tw); break;
+            case 3: blk_pass<3, NT, NMAX>(buf, p.n, ns, tw); break;
+            case 4: blk_pass<4, NT, NMAX>(buf, p.n, ns, tw); break;
+            case 5: blk_pass<5, NT, NMAX>(buf, p.n, ns, tw); break;
+            case 7: blk_pass<7, NT, NMAX>(buf, p.n, ns, tw); break;
+            default: blk_pass<8, NT, NMAX>(buf, p.n, ns, tw); break;
         }
         ns *= r;
     }

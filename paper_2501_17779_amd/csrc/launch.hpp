@@ -22,11 +22,11 @@ struct BlkArgs {
     const void* tw_arena;     // device twiddle arena (float2 or double2)
     int rescore;
     int theta64;
+    int num_cus;
 };
 
-// One pair per workgroup, LDS-resident Stockham FFT, any supported n.
-// Dynamic LDS bytes of one launch (the caller checks it against the device).
-size_t blk_dynamic_lds(int n_max, size_t elem);
+// Persistent size-class kernels, one pair per workgroup at a time,
+// LDS-resident Stockham FFT, any supported n.
 hipError_t launch_align_blk_f32(const BlkArgs& a, hipStream_t s);
 hipError_t launch_align_blk_f64(const BlkArgs& a, hipStream_t s);
 

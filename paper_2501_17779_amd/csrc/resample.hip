@@ -348,6 +348,12 @@ constexpr int kFtK = 512;                  // knots per tile
 constexpr int kFtH = kRsW + 1;             // halo on each side
 constexpr int kFtP = kFtK + 2 * kFtH;      // staged knots
 constexpr int kFtC = 8;                    // knots per lane in the local solve
+// Per-knot LDS arrays are padded with one slot per 8 entries: the local solve
+// and the scan give lane l the knots [8 l, 8 l + 8), a stride that would put
+// lanes 8 apart in the same bank.
+constexpr int kFtPP = kFtP + kFtP / 8 + 1;
+constexpr int kFtKP = kFtK + kFtK / 8 + 1;
+__device__ __forceinline__ int kp(int i) { return i + (i >> 3); }
 
 __device__ __forceinline__ int wrapm(int i, int m) {
     while (i < 0) i += m;
@@ -357,16 +363,20 @@ __device__ __forceinline__ int wrapm(int i, int m) {
 
 __device__ __forceinline__ double wave_sum_d(double v) { return team_sum<64>(v); }
 
+// Hardware reciprocal (1 ulp): the spline quantities are positive, finite and
+// far from the denormal range on the fast path.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw, const int64_t* __restrict__ raw_off,
                                                       int64_t num_curves, const int64_t* __restrict__ out_off,
                                                       cf* __restrict__ out, double* __restrict__ norms,
                                                       uint32_t* __restrict__ flags, int mode,
                                                       int* __restrict__ slow_count, int* __restrict__ slow_list) {
-    __shared__ cf sP[kFtP];
-    __shared__ float sH[kFtP];
-    __shared__ cf sR[kFtP];
-    __shared__ float sS[kFtK];
-    __shared__ cf sM[kFtK];
+    __shared__ cf sP[kFtPP];
+    __shared__ float sH[kFtPP];
+    __shared__ cf sR[kFtPP];
+    __shared__ float sS[kFtKP];
+    __shared__ cf sM[kFtKP];
     const int64_t c = blockIdx.x;
     if (c >= num_curves) return;
     const int lane = threadIdx.x;
@@ -409,20 +419,20 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
         const bool last = (a + kFtK - 1 >= M);
         const int kt = last ? (M - a + 1) : kFtK;       // knots in this tile incl. the right end
         // stage knots a - kFtH .. a + kFtK + kFtH - 1 (cyclic)
-        for (int i = lane; i < kFtP; i += 64) sP[i] = P[wrapm(a - kFtH + i, M)];
+        for (int i = lane; i < kFtP; i += 64) sP[kp(i)] = P[wrapm(a - kFtH + i, M)];
         wave_lds_sync();
         for (int i = lane; i < kFtP - 1; i += 64) {
-            const cf p = sP[i], q = sP[i + 1];
+            const cf p = sP[kp(i)], q = sP[kp(i + 1)];
             const float dx = q.x - p.x, dy = q.y - p.y;
-            sH[i] = sqrtf(dx * dx + dy * dy);
+            sH[kp(i)] = sqrtf(dx * dx + dy * dy);
         }
         wave_lds_sync();
         if (mode == CA_RESAMPLE_SPLINE) {
             for (int i = lane + 1; i < kFtP - 1; i += 64) {
-                const cf pm = sP[i - 1], p = sP[i], q = sP[i + 1];
-                const float hm = sH[i - 1], h = sH[i];
-                const float ih = 1.0f / h, ihm = 1.0f / hm;
-                sR[i] = {6.0f * ((q.x - p.x) * ih - (p.x - pm.x) * ihm),
+                const cf pm = sP[kp(i - 1)], p = sP[kp(i)], q = sP[kp(i + 1)];
+                const float hm = sH[kp(i - 1)], h = sH[kp(i)];
+                const float ih = frcp(h), ihm = frcp(hm);
+                sR[kp(i)] = {6.0f * ((q.x - p.x) * ih - (p.x - pm.x) * ihm),
                          6.0f * ((q.y - p.y) * ih - (p.y - pm.y) * ihm)};
             }
         }
@@ -432,7 +442,7 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
 #pragma unroll
         for (int k = 0; k < kFtC; ++k) {
             loc[k] = (float)acc;
-            acc += (double)sH[kFtH + kFtC * lane + k];
+            acc += (double)sH[kp(kFtH + kFtC * lane + k)];
         }
         double incl = acc;
 #pragma unroll
@@ -442,7 +452,7 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
         }
         const double base = incl - acc;        // arc length from knot a to knot a + 8 lane
 #pragma unroll
-        for (int k = 0; k < kFtC; ++k) sS[kFtC * lane + k] = (float)(base + (double)loc[k]);
+        for (int k = 0; k < kFtC; ++k) sS[kp(kFtC * lane + k)] = (float)(base + (double)loc[k]);
         // arc length from knot a to knot a + kt - 1 (tile end), exact in FP64
         double span;
         {
@@ -451,7 +461,7 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
             double part = 0.0;
 #pragma unroll
             for (int k = 0; k < kFtC; ++k)
-                if (k < ek) part += (double)sH[kFtH + kFtC * el + k];
+                if (k < ek) part += (double)sH[kp(kFtH + kFtC * el + k)];
             span = __shfl(base, el, 64) + __shfl(part, el, 64);
         }
         wave_lds_sync();
@@ -460,20 +470,20 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
             float al[kFtC];
             cf de[kFtC];
             const int i0 = kFtH + kFtC * lane;           // staged index of the chunk's first knot
-            float hprev = sH[i0 - kRsW - 1];
+            float hprev = sH[kp(i0 - kRsW - 1)];
             float alpha = 0.0f;
             cf delta = {0.0f, 0.0f};
 #pragma unroll
             for (int i = 0; i < kRsW + kFtC; ++i) {
                 const int j = i0 - kRsW + i;
-                const float hj = sH[j];
-                const cf d = sR[j];
+                const float hj = sH[kp(j)];
+                const cf d = sR[kp(j)];
                 const float b = 2.0f * (hprev + hj);
                 if (i == 0) {
                     alpha = b;
                     delta = d;
                 } else {
-                    const float f = hprev / alpha;
+                    const float f = hprev * frcp(alpha);
                     alpha = b - f * hprev;
                     delta = {d.x - f * delta.x, d.y - f * delta.y};
                 }
@@ -486,29 +496,31 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
 #pragma unroll
             for (int i = kRsW - 1; i >= 0; --i) {
                 const int j = e + i;
-                const float hj = sH[j], hjm = sH[j - 1];
-                const cf d = sR[j];
+                const float hj = sH[kp(j)], hjm = sH[kp(j - 1)];
+                const cf d = sR[kp(j)];
                 const float b = 2.0f * (hjm + hj);
                 if (i == kRsW - 1) {
                     beta = b;
                     eps = d;
                 } else {
-                    const float g = hj / beta;
+                    const float g = hj * frcp(beta);
                     beta = b - g * anext;
                     eps = {d.x - g * eps.x, d.y - g * eps.y};
                 }
                 anext = hjm;
             }
-            const float ae = sH[e - 1];
+            const float ae = sH[kp(e - 1)];
             const float aL = al[kFtC - 1];
             const cf dL = de[kFtC - 1];
-            const float den = beta - ae * ae / aL;
-            cf Mn = {(eps.x - ae * dL.x / aL) / den, (eps.y - ae * dL.y / aL) / den};
+            const float iaL = frcp(aL);
+            const float iden = frcp(beta - ae * ae * iaL);
+            cf Mn = {(eps.x - ae * dL.x * iaL) * iden, (eps.y - ae * dL.y * iaL) * iden};
 #pragma unroll
             for (int i = kFtC - 1; i >= 0; --i) {
-                const float cj = sH[i0 + i];
-                const cf Mi = {(de[i].x - cj * Mn.x) / al[i], (de[i].y - cj * Mn.y) / al[i]};
-                sM[kFtC * lane + i] = Mi;
+                const float cj = sH[kp(i0 + i)];
+                const float ia = frcp(al[i]);
+                const cf Mi = {(de[i].x - cj * Mn.x) * ia, (de[i].y - cj * Mn.y) * ia};
+                sM[kp(kFtC * lane + i)] = Mi;
                 Mn = Mi;
             }
         }
@@ -523,17 +535,17 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
             int lo = 0, hi = kt - 2;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (sS[mid] <= u) lo = mid; else hi = mid - 1;
+                if (sS[kp(mid)] <= u) lo = mid; else hi = mid - 1;
             }
             const int j = lo;
-            const float hj = sH[kFtH + j];
-            const float bb = u - sS[j];
+            const float hj = sH[kp(kFtH + j)];
+            const float bb = u - sS[kp(j)];
             const float aa = hj - bb;
-            const cf qj = sP[kFtH + j], qp = sP[kFtH + j + 1];
+            const cf qj = sP[kp(kFtH + j)], qp = sP[kp(kFtH + j + 1)];
             cf z;
             if (mode == CA_RESAMPLE_SPLINE) {
-                const cf mj = sM[j], mp = sM[j + 1];
-                const float ih = 1.0f / hj;
+                const cf mj = sM[kp(j)], mp = sM[kp(j + 1)];
+                const float ih = frcp(hj);
                 const float ca = aa * aa * aa * ih * (1.0f / 6.0f);
                 const float cb = bb * bb * bb * ih * (1.0f / 6.0f);
                 const float h6 = hj * hj * (1.0f / 6.0f);
@@ -541,7 +553,7 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
                 z.x = mj.x * ca + mp.x * cb + (qj.x - mj.x * h6) * ua + (qp.x - mp.x * h6) * ub;
                 z.y = mj.y * ca + mp.y * cb + (qj.y - mj.y * h6) * ua + (qp.y - mp.y * h6) * ub;
             } else {
-                const float ub = bb / hj, ua = 1.0f - ub;
+                const float ub = bb * frcp(hj), ua = 1.0f - ub;
                 z.x = qj.x * ua + qp.x * ub;
                 z.y = qj.y * ua + qp.y * ub;
             }
