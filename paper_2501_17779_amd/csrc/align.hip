@@ -25,7 +25,7 @@ __global__ __launch_bounds__(256, 2) void k_align_team(const cf* __restrict__ z1
     constexpr int T = TeamCfg<N>::T;
     constexpr int R = N / T;
     constexpr int TEAMS = 256 / T;
-    constexpr int PADN = N + N / 16;
+    constexpr int PADN = team_padn<N>();
     __shared__ cf tws[TeamCfg<N>::TW];
     __shared__ cf lds_all[TEAMS * PADN];
     __shared__ int cand_all[TEAMS * kCandCap];
@@ -56,9 +56,10 @@ __global__ __launch_bounds__(256, 2) void k_align_team(const cf* __restrict__ z1
         const double n1 = team_sum<T>(q1) / N;
         const double n2 = team_sum<T>(q2) / N;
         // z2 nodes for the shifted FP64 dot products
-        const int rb = t + (t >> 4);
+        constexpr int PS = TeamCfg<N>::PS;
+        const int rb = t + (t >> PS);
 #pragma unroll
-        for (int q = 0; q < R; ++q) lds[rb + T * q + ((T * q) >> 4)] = b0[q];
+        for (int q = 0; q < R; ++q) lds[rb + T * q + ((T * q) >> PS)] = b0[q];
         wave_lds_sync();
         const ca_result_t res = team_epilogue<N, T>(v, a0, lds, cand, t, n1, n2, rescore, theta64);
         if (t == 0) out[pair] = res;
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(256) void k_spectra(const cf* __restrict__ curves, 
     constexpr int T = TeamCfg<N>::T;
     constexpr int R = N / T;
     constexpr int TEAMS = 256 / T;
-    constexpr int PADN = N + N / 16;
+    constexpr int PADN = team_padn<N>();
     __shared__ cf tws[TeamCfg<N>::TW];
     __shared__ cf lds_all[TEAMS * PADN];
     load_twiddles<TeamCfg<N>::TW>(tws, tw);
@@ -104,14 +105,14 @@ __global__ __launch_bounds__(256) void k_spectra(const cf* __restrict__ curves, 
 // next column is loaded while the current one is aligned) and shared by the
 // rows.
 template <int N, int JB>
-__global__ __launch_bounds__(256, 2) void k_allpairs(const cf* __restrict__ curves, const cf* __restrict__ spec,
+__global__ __launch_bounds__(256, TeamCfg<N>::AW) void k_allpairs(const cf* __restrict__ curves, const cf* __restrict__ spec,
                                                   const double* __restrict__ norms, int m,
                                                   ca_result_t* __restrict__ out, const cf* __restrict__ tw,
                                                   int rescore, int theta64) {
     constexpr int T = TeamCfg<N>::T;
     constexpr int R = N / T;
     constexpr int TEAMS = 256 / T;
-    constexpr int PADN = N + N / 16;
+    constexpr int PADN = team_padn<N>();
     constexpr int PER = (N + 255) / 256;
     __shared__ cf tws[TeamCfg<N>::TW];
     __shared__ cf sZ[2][N];
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(256, 2) void k_allpairs(const cf* __restrict__ curv
             const int k = threadIdx.x + 256 * p;
             if (k < N) {
                 sZ[b][k] = gZ[p];
-                sz[b][lpad(k)] = gz[p];
+                sz[b][lpad<N>(k)] = gz[p];
             }
         }
     };
@@ -331,10 +332,9 @@ __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1,
             q1 = fma((double)a.x, (double)a.x, fma((double)a.y, (double)a.y, q1));
             q2 = fma((double)b.x, (double)b.x, fma((double)b.y, (double)b.y, q2));
         }
-        const double n1 = block_sum<NT>(q1, red) / n;   // block_sum synchronises
-        const double n2 = block_sum<NT>(q2, red) / n;
-        blk_fft<NT, NMAX>(A, p, tw);
-        blk_fft<NT, NMAX>(B, p, tw);
+        block_sum2<NT>(q1, q2, red);                    // synchronises
+        const double n1 = q1 / n, n2 = q2 / n;
+        blk_fft2<NT, NMAX>(A, B, p, tw);
         for (int k = threadIdx.x; k < n; k += NT) A[k] = cjmul(A[k], B[k]);
         __syncthreads();
         blk_fft<NT, NMAX>(A, p, tw);
@@ -372,8 +372,7 @@ __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1,
                     re = fma(ax, bx, fma(ay, by, re));
                     im = fma(ay, bx, fma(-ax, by, im));
                 }
-                re = block_sum<NT>(re, red);
-                im = block_sum<NT>(im, red);
+                block_sum2<NT>(re, im, red);
                 pk.offer(c, re, im);
             };
             bool capped = false;

@@ -34,7 +34,7 @@ struct Bf16Lane {
 static_assert(sizeof(Bf16Lane) == 128, "per-lane constant block");
 
 constexpr int kBN = 128;
-constexpr int kBPad = kBN + kBN / 16;
+constexpr int kBPad = team_padn<kBN>();
 // Error unit of the split-BF16 path in the |C| bound kErrScale u log2(n) n |z1||z2|.
 // Per product the dropped lo*lo term and the rounding of the two lo parts are
 // each at most 2^-16 relative; they carry random signs, and the measured |C|
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256, 2) void k_align_bf16(const cf* __restrict__ z1
             const int p = idx >> 8, cv = (idx >> 7) & 1, n = idx & (kBN - 1);
             cf val = {0.0f, 0.0f};
             if (p == 0 || has1) val = (cv ? z2 : z1)[(p0 + p) * kBN + n];
-            s_z[wv][p][cv][lpad(n)] = val;
+            s_z[wv][p][cv][lpad<kBN>(n)] = val;
         }
         wave_lds_sync();
         // FP64 norms, one team of 32 lanes per pair
@@ -139,14 +139,14 @@ __global__ __launch_bounds__(256, 2) void k_align_bf16(const cf* __restrict__ z1
         cf a0[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            a0[q] = s_z[wv][p][0][lpad(t + 32 * q)];
-            const cf b = s_z[wv][p][1][lpad(t + 32 * q)];
+            a0[q] = s_z[wv][p][0][lpad<kBN>(t + 32 * q)];
+            const cf b = s_z[wv][p][1][lpad<kBN>(t + 32 * q)];
             q1 = fma((double)a0[q].x, (double)a0[q].x, fma((double)a0[q].y, (double)a0[q].y, q1));
             q2 = fma((double)b.x, (double)b.x, fma((double)b.y, (double)b.y, q2));
         }
         const double n1 = team_sum<32>(q1) / kBN, n2 = team_sum<32>(q2) / kBN;
         for (int cv = 0; cv < 2; ++cv) {
-            dft128x2([&](int pp, int n) { return s_z[wv][pp][cv][lpad(n)]; },
+            dft128x2([&](int pp, int n) { return s_z[wv][pp][cv][lpad<kBN>(n)]; },
                      [&](int pp, int k, int comp, float v) {
                          float* w = reinterpret_cast<float*>(&s_w[wv][pp][cv][k]);
                          w[comp] = v;

@@ -62,18 +62,74 @@ __device__ __forceinline__ void argmax_combine(double& v, int& i, double ov, int
     if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
 }
 
+// Cross-lane moves.  Inside a row of 16 lanes the data-parallel-primitive
+// (DPP) forms exchange at VALU latency: quad_perm [1,0,3,2] and [2,3,0,1]
+// pair lanes i ^ 1 and i ^ 2, row_half_mirror pairs i with 7 - i inside each
+// group of 8, row_mirror pairs i with 15 - i.  After the quad steps every
+// lane of a quad holds the quad result, so the mirror steps complete groups
+// of 8 and 16.  Rows are then combined through v_readlane of lanes 0, 16,
+// 32, 48 (wave-uniform values).  Every lane of a team ends with the same
+// value, computed in the same order.
+enum { kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140 };
+
+template <int CTRL> __device__ __forceinline__ int dpp32(int x) {
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL> __device__ __forceinline__ float dpp(float x) {
+    return __int_as_float(dpp32<CTRL>(__float_as_int(x)));
+}
+template <int CTRL> __device__ __forceinline__ int dpp(int x) { return dpp32<CTRL>(x); }
+template <int CTRL> __device__ __forceinline__ double dpp(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp32<CTRL>((int)(b & 0xffffffffll));
+    const int hi = dpp32<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float rdlane(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ int rdlane(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
+__device__ __forceinline__ double rdlane(double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Reductions across the W lanes of an aligned team (W a power of two <= 64).
 template <int W, typename V> __device__ __forceinline__ V team_sum(V v) {
-#pragma unroll
-    for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+    if constexpr (W >= 2) v += dpp<kDppXor1>(v);
+    if constexpr (W >= 4) v += dpp<kDppXor2>(v);
+    if constexpr (W >= 8) v += dpp<kDppHalfMirror>(v);
+    if constexpr (W >= 16) v += dpp<kDppMirror>(v);
+    if constexpr (W == 32) {
+        const V a = rdlane(v, 0) + rdlane(v, 16), b = rdlane(v, 32) + rdlane(v, 48);
+        v = (threadIdx.x & 32) ? b : a;
+    } else if constexpr (W == 64) {
+        v = (rdlane(v, 0) + rdlane(v, 16)) + (rdlane(v, 32) + rdlane(v, 48));
+    }
     return v;
 }
 template <int W, typename V> __device__ __forceinline__ void team_argmax(V& v, int& i) {
-#pragma unroll
-    for (int o = W / 2; o > 0; o >>= 1) {
-        V ov = __shfl_xor(v, o, W);
-        int oi = __shfl_xor(i, o, W);
-        argmax_combine(v, i, ov, oi);
+    auto step = [&](V ov, int oi) { argmax_combine(v, i, ov, oi); };
+    if constexpr (W >= 2) step(dpp<kDppXor1>(v), dpp<kDppXor1>(i));
+    if constexpr (W >= 4) step(dpp<kDppXor2>(v), dpp<kDppXor2>(i));
+    if constexpr (W >= 8) step(dpp<kDppHalfMirror>(v), dpp<kDppHalfMirror>(i));
+    if constexpr (W >= 16) step(dpp<kDppMirror>(v), dpp<kDppMirror>(i));
+    if constexpr (W >= 32) {
+        V a = rdlane(v, 0), b = rdlane(v, 32);
+        int ia = rdlane(i, 0), ib = rdlane(i, 32);
+        argmax_combine(a, ia, rdlane(v, 16), rdlane(i, 16));
+        argmax_combine(b, ib, rdlane(v, 48), rdlane(i, 48));
+        if constexpr (W == 64) {
+            argmax_combine(a, ia, b, ib);
+            v = a;
+            i = ia;
+        } else {
+            const bool hi = (threadIdx.x & 32) != 0;
+            v = hi ? b : a;
+            i = hi ? ib : ia;
+        }
     }
 }
 
@@ -89,6 +145,20 @@ template <int NT> __device__ __forceinline__ double block_sum(double v, double* 
 #pragma unroll
     for (int k = 0; k < NT / 64; ++k) s += scratch[k];
     return s;
+}
+// Two sums at once (one pair of barriers); scratch holds 2 * (blockDim / 64) doubles.
+template <int NT> __device__ __forceinline__ void block_sum2(double& a, double& b, double* scratch) {
+    a = team_sum<64>(a);
+    b = team_sum<64>(b);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) { scratch[2 * w] = a; scratch[2 * w + 1] = b; }
+    __syncthreads();
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) { sa += scratch[2 * k]; sb += scratch[2 * k + 1]; }
+    a = sa;
+    b = sb;
 }
 template <int NT, typename V> __device__ __forceinline__ void block_argmax(V& v, int& i, double* scratch) {
     team_argmax<64>(v, i);

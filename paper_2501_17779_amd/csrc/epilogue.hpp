@@ -164,7 +164,7 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
         double re = 0.0, im = 0.0;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            const cf zz = zb[lpad((t + T * q - c) & (N - 1))];
+            const cf zz = zb[lpad<N>((t + T * q - c) & (N - 1))];
             const double ax = a0[q].x, ay = a0[q].y, bx = zz.x, by = zz.y;
             re = fma(ax, bx, fma(ay, by, re));
             im = fma(ay, bx, fma(-ax, by, im));

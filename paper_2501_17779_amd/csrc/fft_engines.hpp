@@ -80,6 +80,64 @@ __device__ __forceinline__ void blk_pass(cpx<T>* buf, int n, int ns, const cpx<T
     __syncthreads();
 }
 
+// The same pass on two buffers, sharing twiddles and barriers.
+template <int R, int NT, int NMAX, typename T>
+__device__ __forceinline__ void blk_pass2(cpx<T>* b1, cpx<T>* b2, int n, int ns, const cpx<T>* __restrict__ tw) {
+    constexpr int UM = (NMAX / R + NT - 1) / NT;
+    const int nb = n / R;
+    const int tstride = n / (ns * R);
+    const float inv_ns = 1.0f / (float)ns;
+    cpx<T> v[UM][R], w[UM][R];
+#pragma unroll
+    for (int u = 0; u < UM; ++u) {
+        const int j = threadIdx.x + u * NT;
+        if (j < nb) {
+            const int k = mod_small(j, ns, inv_ns);
+#pragma unroll
+            for (int r = 0; r < R; ++r) { v[u][r] = b1[j + r * nb]; w[u][r] = b2[j + r * nb]; }
+            if (ns > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    const cpx<T> f = tw[r * k * tstride];
+                    v[u][r] = mul(v[u][r], f);
+                    w[u][r] = mul(w[u][r], f);
+                }
+            }
+            dft<R>(v[u]);
+            dft<R>(w[u]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < UM; ++u) {
+        const int j = threadIdx.x + u * NT;
+        if (j < nb) {
+            const int k = mod_small(j, ns, inv_ns);
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) { b1[base + r * ns] = v[u][r]; b2[base + r * ns] = w[u][r]; }
+        }
+    }
+    __syncthreads();
+}
+
+template <int NT, int NMAX, typename T>
+__device__ void blk_fft2(cpx<T>* b1, cpx<T>* b2, const Plan& p, const cpx<T>* __restrict__ tw) {
+    int ns = 1;
+    for (int i = 0; i < p.npass; ++i) {
+        const int r = p.radix[i];
+        switch (r) {
+            case 2: blk_pass2<2, NT, NMAX>(b1, b2, p.n, ns, tw); break;
+            case 3: blk_pass2<3, NT, NMAX>(b1, b2, p.n, ns, tw); break;
+            case 4: blk_pass2<4, NT, NMAX>(b1, b2, p.n, ns, tw); break;
+            case 5: blk_pass2<5, NT, NMAX>(b1, b2, p.n, ns, tw); break;
+            case 7: blk_pass2<7, NT, NMAX>(b1, b2, p.n, ns, tw); break;
+            default: blk_pass2<8, NT, NMAX>(b1, b2, p.n, ns, tw); break;
+        }
+        ns *= r;
+    }
+}
+
 template <int NT, int NMAX, typename T>
 __device__ void blk_fft(cpx<T>* buf, const Plan& p, const cpx<T>* __restrict__ tw) {
     int ns = 1;
@@ -98,19 +156,24 @@ __device__ void blk_fft(cpx<T>* buf, const Plan& p, const cpx<T>* __restrict__ t
 }
 
 // ------------------------------------------------------------------- team engine
-// LDS exchange layout: element i lives at i + i/16 (one pad slot per 16).
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+// LDS exchange layout: element i lives at i + (i >> PS), one pad slot per 2^PS.
+template <int PS> __device__ __forceinline__ int lpadp(int i) { return i + (i >> PS); }
 
 // Radix schedules: N = T * R (T lanes, R values per lane); every radix
 // divides R.  Passes after the first multiply by w_{NS RP}^{r k}; those
 // twiddles are stored per pass as tw[TWO + (r - 1) NS + k], so a lane's
-// twiddles are one base address plus compile-time offsets.
+// twiddles are one base address plus compile-time offsets.  PS is the pad
+// shift of the exchange layout (exchanging passes need NS = 1 or a multiple
+// of 2^PS, which makes every LDS address a lane base plus a constant).  AW is
+// the minimum number of waves per SIMD the all-pairs kernel is compiled for.
 template <int N> struct TeamCfg;
-template <> struct TeamCfg<64> { static constexpr int T = 8, TW = 56; };      // 8 x 8
-template <> struct TeamCfg<128> { static constexpr int T = 8, TW = 112; };    // 16 x 8
-template <> struct TeamCfg<256> { static constexpr int T = 16, TW = 240; };   // 16 x 16
-template <> struct TeamCfg<512> { static constexpr int T = 32, TW = 496; };   // 16 x 16 x 2
-template <> struct TeamCfg<1024> { static constexpr int T = 64, TW = 1008; }; // 16 x 16 x 4
+template <> struct TeamCfg<64> { static constexpr int T = 8, TW = 56, PS = 4, AW = 2; };      // 8 x 8
+template <> struct TeamCfg<128> { static constexpr int T = 8, TW = 112, PS = 4, AW = 2; };    // 16 x 8
+template <> struct TeamCfg<256> { static constexpr int T = 16, TW = 240, PS = 4, AW = 2; };   // 16 x 16
+template <> struct TeamCfg<512> { static constexpr int T = 32, TW = 496, PS = 4, AW = 2; };   // 16 x 16 x 2
+template <> struct TeamCfg<1024> { static constexpr int T = 64, TW = 1008, PS = 4, AW = 2; }; // 16 x 16 x 4
+template <int N> __device__ __forceinline__ int lpad(int i) { return lpadp<TeamCfg<N>::PS>(i); }
+template <int N> constexpr int team_padn() { return N + (N >> TeamCfg<N>::PS); }
 
 // One Stockham pass on the team's registers.  Non-final passes scatter the
 // outputs to LDS and gather x[t + T q] back; all LDS addresses are a lane base
@@ -119,9 +182,11 @@ template <int N, int T, int RP, int NS, bool LAST, int TWO>
 __device__ __forceinline__ void team_pass(cf (&v)[N / T], cf* lds, const cf* tws, int t) {
     constexpr int R = N / T;
     constexpr int U = R / RP;
+    constexpr int PS = TeamCfg<N>::PS;
     static_assert(R % RP == 0, "radix must divide the per-lane count");
     static_assert(LAST || U == 1, "exchanging passes hold one butterfly per lane");
-    static_assert(NS == 1 || NS % 16 == 0 || LAST, "exchange layout needs NS = 1 or a multiple of 16");
+    static_assert(NS == 1 || NS % (1 << PS) == 0 || LAST, "exchange layout needs NS = 1 or a multiple of 2^PS");
+    static_assert(RP <= (1 << PS), "first-pass radix must fit a pad group");
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int j = t + u * T;
@@ -138,21 +203,21 @@ __device__ __forceinline__ void team_pass(cf (&v)[N / T], cf* lds, const cf* tws
 #pragma unroll
             for (int r = 0; r < RP; ++r) v[u + r * U] = b[r];
         } else if constexpr (NS == 1) {
-            cf* wp = lds + (RP * j + ((RP * j) >> 4));
+            cf* wp = lds + (RP * j + ((RP * j) >> PS));
 #pragma unroll
             for (int r = 0; r < RP; ++r) wp[r] = b[r];
         } else {
             const int i0 = (j - k) * RP + k;
-            cf* wp = lds + lpad(i0);
+            cf* wp = lds + lpadp<PS>(i0);
 #pragma unroll
-            for (int r = 0; r < RP; ++r) wp[r * (NS + NS / 16)] = b[r];
+            for (int r = 0; r < RP; ++r) wp[r * (NS + (NS >> PS))] = b[r];
         }
     }
     if constexpr (!LAST) {
         wave_lds_sync();
-        const cf* rp = lds + (t + (t >> 4));
+        const cf* rp = lds + (t + (t >> PS));
 #pragma unroll
-        for (int q = 0; q < R; ++q) v[q] = rp[T * q + ((T * q) >> 4)];
+        for (int q = 0; q < R; ++q) v[q] = rp[T * q + ((T * q) >> PS)];
         wave_lds_sync();
     }
 }
@@ -190,24 +255,25 @@ __device__ __forceinline__ void team_pass2(cf (&v)[N / T], cf (&w)[N / T], cf* l
         }
     }
     if constexpr (!LAST) {
+        constexpr int PS = TeamCfg<N>::PS;
         const int j = t;
         const int k = j & (NS - 1);
         cf* wp;
         int stride;
-        if constexpr (NS == 1) { wp = lds + (RP * j + ((RP * j) >> 4)); stride = 1; }
-        else { wp = lds + lpad((j - k) * RP + k); stride = NS + NS / 16; }
-        const cf* rp = lds + (t + (t >> 4));
+        if constexpr (NS == 1) { wp = lds + (RP * j + ((RP * j) >> PS)); stride = 1; }
+        else { wp = lds + lpadp<PS>((j - k) * RP + k); stride = NS + (NS >> PS); }
+        const cf* rp = lds + (t + (t >> PS));
 #pragma unroll
         for (int r = 0; r < RP; ++r) wp[r * stride] = bo[r];
         wave_lds_sync();
 #pragma unroll
-        for (int q = 0; q < R; ++q) v[q] = rp[T * q + ((T * q) >> 4)];
+        for (int q = 0; q < R; ++q) v[q] = rp[T * q + ((T * q) >> PS)];
         wave_lds_sync();
 #pragma unroll
         for (int r = 0; r < RP; ++r) wp[r * stride] = co[r];
         wave_lds_sync();
 #pragma unroll
-        for (int q = 0; q < R; ++q) w[q] = rp[T * q + ((T * q) >> 4)];
+        for (int q = 0; q < R; ++q) w[q] = rp[T * q + ((T * q) >> PS)];
         wave_lds_sync();
     }
 }

@@ -389,16 +389,30 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
     bool general = (mraw < 3 || mraw > kRsMCap || N < 1);
     const int M = general ? 0 : (int)mraw;
 
-    // pass 1: perimeter, duplicates, non-finite values
+    // pass 1: perimeter, duplicates, non-finite values (four vertices per
+    // lane per iteration, loads issued together)
     double Ls = 0.0;
     int bad = 0;
-    for (int j = lane; j < M; j += 64) {
-        const cf a = P[j];
-        const cf b = P[j + 1 < M ? j + 1 : 0];
-        const float dx = b.x - a.x, dy = b.y - a.y;
-        const float h = sqrtf(dx * dx + dy * dy);
-        if (!(h > 0.0f) || !isfinite(h)) bad = 1;
-        Ls += (double)h;
+    for (int j0 = 0; j0 < M; j0 += 256) {
+        cf a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = j0 + lane + 64 * u;
+            if (j < M) {
+                a[u] = P[j];
+                b[u] = P[j + 1 < M ? j + 1 : 0];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = j0 + lane + 64 * u;
+            if (j < M) {
+                const float dx = b[u].x - a[u].x, dy = b[u].y - a[u].y;
+                const float h = sqrtf(dx * dx + dy * dy);
+                if (!(h > 0.0f) || !isfinite(h)) bad = 1;
+                Ls += (double)h;
+            }
+        }
     }
     general = general || (__ballot(bad) != 0ull);
     if (general) {
@@ -415,11 +429,31 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
     // pass 2: tiles of kFtK knots starting at a; segments [a, a + kFtK - 1)
     double carry = 0.0;                        // arc length at knot a
     double sx = 0.0, sy = 0.0;
+    constexpr int kStage = (kFtP + 63) / 64;   // staged vertices per lane
+    cf pre[kStage];                            // next tile's vertices, loaded ahead
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+        const int i = lane + 64 * u;
+        if (i < kFtP) pre[u] = P[wrapm(i - kFtH, M)];
+    }
     for (int a = 0; a < M; a += kFtK - 1) {
         const bool last = (a + kFtK - 1 >= M);
         const int kt = last ? (M - a + 1) : kFtK;       // knots in this tile incl. the right end
-        // stage knots a - kFtH .. a + kFtK + kFtH - 1 (cyclic)
-        for (int i = lane; i < kFtP; i += 64) sP[kp(i)] = P[wrapm(a - kFtH + i, M)];
+        // stage knots a - kFtH .. a + kFtK + kFtH - 1 (cyclic), then start
+        // loading the next tile's
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int i = lane + 64 * u;
+            if (i < kFtP) sP[kp(i)] = pre[u];
+        }
+        if (!last) {
+            const int an = a + kFtK - 1;
+#pragma unroll
+            for (int u = 0; u < kStage; ++u) {
+                const int i = lane + 64 * u;
+                if (i < kFtP) pre[u] = P[wrapm(an - kFtH + i, M)];
+            }
+        }
         wave_lds_sync();
         for (int i = lane; i < kFtP - 1; i += 64) {
             const cf p = sP[kp(i)], q = sP[kp(i + 1)];
