@@ -466,6 +466,7 @@ ca_status_t resample_arclength(ca_context_t c, const void* raw, const int64_t* r
     if (num_curves == 0) return CA_OK;
     if (!raw || !raw_offsets || !out_offsets || !out)
         return fail(CA_ERR_INVALID_ARG, "raw, raw_offsets, out_offsets and out must be non-NULL");
+    if (num_curves > 0x7fffffffLL) return fail(CA_ERR_INVALID_ARG, "num_curves exceeds 2^31 - 1");
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
     if (!c->d_rs) {
@@ -474,7 +475,6 @@ ca_status_t resample_arclength(ca_context_t c, const void* raw, const int64_t* r
             return fail(CA_ERR_OOM, "resampler scratch");
         c->rs_slots = slots;
     }
-    if (num_curves > 0x7fffffffLL) return fail(CA_ERR_INVALID_ARG, "num_curves exceeds 2^31 - 1");
     if (num_curves + 1 > c->slow_cap) {
         if (c->d_slow) (void)hipFree(c->d_slow);
         c->d_slow = nullptr;

@@ -1,0 +1,195 @@
+"""Host-side checks of the C ABI (no GPU needed, no compute calls).
+
+- libcurvealign.so loads and exports every function include/curvealign.h
+  declares;
+- the record and option layouts and the enum values the header fixes are
+  the ones the Python binding marshals (checked with a C program compiled by
+  gcc against the header itself);
+- ca_n_supported is the predicate the header states (2 <= n <= CA_MAX_N,
+  no prime factor above 7), checked by trial division;
+- argument errors are reported on the host, before the context is used or
+  any device work is enqueued: NULL context, NULL data pointers, negative
+  counts, bad option values, unsupported n (the context handle passed in
+  those checks is a dummy that the library must not dereference);
+- on a machine with no GPU, ca_create reports CA_ERR_NO_DEVICE.
+"""
+import ctypes
+import json
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2501_17779_amd as ca
+from paper_2501_17779_amd import build as cabuild
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "curvealign.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(ca.LIB_PATH):
+        cabuild.build()
+    return ca.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_bound_entry_points():
+    assert set(declared_functions()) == set(ca.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol(L):
+    out = subprocess.run(["nm", "-D", "--defined-only", ca.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for name in declared_functions():
+        assert name in exported, name
+        assert getattr(L, name) is not None
+
+
+_PROBE = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "curvealign.h"
+int main(void) {
+    printf("{\"result_size\": %zu, \"result_align\": %zu, \"options_size\": %zu,\n",
+           sizeof(ca_result_t), _Alignof(ca_result_t), sizeof(ca_options_t));
+    printf("\"offsets\": [%zu, %zu, %zu, %zu, %zu, %zu],\n", offsetof(ca_result_t, shift),
+           offsetof(ca_result_t, flags), offsetof(ca_result_t, theta), offsetof(ca_result_t, e0),
+           offsetof(ca_result_t, err_est), offsetof(ca_result_t, gap));
+    printf("\"status\": [%d, %d, %d, %d, %d, %d],\n", CA_OK, CA_ERR_INVALID_ARG, CA_ERR_UNSUPPORTED_N,
+           CA_ERR_HIP, CA_ERR_OOM, CA_ERR_NO_DEVICE);
+    printf("\"flags\": [%u, %u, %u, %u, %u, %u, %u],\n", (unsigned)CA_FLAG_NEAR_TIE,
+           (unsigned)CA_FLAG_RESCORED, (unsigned)CA_FLAG_CAND_CAPPED, (unsigned)CA_FLAG_DEGENERATE,
+           (unsigned)CA_FLAG_NONFINITE, (unsigned)CA_FLAG_THETA_FP64, (unsigned)CA_FLAG_UNSUPPORTED_N);
+    printf("\"prec\": [%d, %d, %d], \"rescore\": [%d, %d], \"resample\": [%d, %d], \"max_n\": %d}\n",
+           CA_PREC_FP32, CA_PREC_SPLIT_BF16, CA_PREC_FP64, CA_RESCORE_TOP2, CA_RESCORE_WINDOW,
+           CA_RESAMPLE_SPLINE, CA_RESAMPLE_LINEAR, CA_MAX_N);
+    return 0;
+}
+"""
+
+
+def test_header_layout_matches_binding(tmp_path):
+    src = tmp_path / "probe.c"
+    src.write_text(_PROBE)
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c11", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+                    "-o", str(exe)], check=True)
+    h = json.loads(subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout)
+    dt = ca.RESULT_DTYPE
+    assert h["result_size"] == dt.itemsize == ca.RESULT_BYTES == 32
+    assert h["result_align"] == 8
+    assert h["offsets"] == [dt.fields[f][1] for f in ("shift", "flags", "theta", "e0", "err_est", "gap")]
+    assert h["options_size"] == ctypes.sizeof(ca._Options) == 16
+    assert h["status"] == [ca.OK, ca.ERR_INVALID_ARG, ca.ERR_UNSUPPORTED_N, ca.ERR_HIP, ca.ERR_OOM,
+                           ca.ERR_NO_DEVICE]
+    assert h["flags"] == [ca.FLAG_NEAR_TIE, ca.FLAG_RESCORED, ca.FLAG_CAND_CAPPED, ca.FLAG_DEGENERATE,
+                          ca.FLAG_NONFINITE, ca.FLAG_THETA_FP64, ca.FLAG_UNSUPPORTED_N]
+    assert h["prec"] == [ca.PRECISION[k] for k in ("fp32", "split_bf16", "fp64")]
+    assert h["rescore"] == [ca.RESCORE[k] for k in ("top2", "window")]
+    assert h["resample"] == [ca.RESAMPLE[k] for k in ("spline", "linear")]
+    assert h["max_n"] == ca.MAX_N
+
+
+def _smooth7(n):
+    if n < 2 or n > ca.MAX_N:
+        return False
+    for p in (2, 3, 5, 7):
+        while n % p == 0:
+            n //= p
+    return n == 1
+
+
+def test_n_supported_predicate(L):
+    for n in list(range(-3, ca.MAX_N + 40)) + [2 ** 31 - 1, -(2 ** 31)]:
+        assert L.ca_n_supported(n) == int(_smooth7(n)), n
+    explicit = {1: 0, 2: 1, 11: 0, 840: 1, 2187: 1, 4095: 0, 4096: 1, 4100: 0}   # 4095 = 3^2 5 7 13
+    for n, want in explicit.items():
+        assert L.ca_n_supported(n) == want, n
+
+
+def test_status_strings(L):
+    seen = set()
+    for st in (ca.OK, ca.ERR_INVALID_ARG, ca.ERR_UNSUPPORTED_N, ca.ERR_HIP, ca.ERR_OOM, ca.ERR_NO_DEVICE, -6):
+        s = L.ca_status_string(st).decode()
+        assert s and s not in seen
+        seen.add(s)
+    assert L.ca_status_string(12345).decode() == "unknown status"
+
+
+def _last(L):
+    return L.ca_last_error().decode()
+
+
+def test_null_context_is_rejected_on_host(L):
+    dummy = ctypes.c_void_p(16)      # never dereferenced: validation fails first
+    assert L.align_pair(None, dummy, dummy, 64, dummy, None, None) == ca.ERR_INVALID_ARG
+    assert "NULL" in _last(L)
+    assert L.align_batch(None, dummy, dummy, None, 64, 4, dummy, None, None) == ca.ERR_INVALID_ARG
+    assert L.align_all_pairs(None, dummy, 8, 64, dummy, None, None) == ca.ERR_INVALID_ARG
+    assert L.resample_arclength(None, dummy, dummy, 4, dummy, dummy, None, None, 0, None) == ca.ERR_INVALID_ARG
+    assert L.ca_create(None, 0) == ca.ERR_INVALID_ARG
+    assert L.ca_destroy(None) == ca.OK
+
+
+def test_create_without_gpu_reports_no_device(L):
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is visible; covered by the GPU tests")
+    h = ctypes.c_void_p()
+    assert L.ca_create(ctypes.byref(h), 0) == ca.ERR_NO_DEVICE
+    assert h.value is None
+    assert _last(L)
+    with pytest.raises(ca.CurveAlignError) as ei:
+        ca.Context(0)
+    assert ei.value.status == ca.ERR_NO_DEVICE
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("rescore", ctypes.c_int32),
+                ("theta_fp64", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+def test_argument_errors_before_device_work(L):
+    ctx = ctypes.c_void_p(0x1000)    # dummy handle: every case below must fail before using it
+    p = ctypes.c_void_p(0x2000)      # dummy data pointer, never dereferenced on the host
+    ok = _Opts(0, 0, 0, 0)
+    bad = {"precision": _Opts(3, 0, 0, 0), "rescore": _Opts(0, 2, 0, 0), "reserved": _Opts(0, 0, 0, 1)}
+    for what, o in bad.items():
+        assert L.align_batch(ctx, p, p, None, 64, 4, p, ctypes.byref(o), None) == ca.ERR_INVALID_ARG
+        assert what in _last(L)
+        assert L.align_all_pairs(ctx, p, 8, 64, p, ctypes.byref(o), None) == ca.ERR_INVALID_ARG
+    assert L.align_batch(ctx, p, p, None, 64, -1, p, None, None) == ca.ERR_INVALID_ARG
+    assert L.align_batch(ctx, None, p, None, 64, 4, p, None, None) == ca.ERR_INVALID_ARG
+    assert L.align_batch(ctx, p, p, None, 64, 4, None, None, None) == ca.ERR_INVALID_ARG
+    assert L.align_batch(ctx, p, p, None, 64, 2 ** 31, p, None, None) == ca.ERR_INVALID_ARG
+    for n in (0, 1, 11, 4095, 8192):
+        assert L.align_batch(ctx, p, p, None, n, 4, p, None, None) == ca.ERR_UNSUPPORTED_N, n
+        assert L.align_pair(ctx, p, p, n, p, None, None) == ca.ERR_UNSUPPORTED_N, n
+        assert L.align_all_pairs(ctx, p, 8, n, p, None, None) == ca.ERR_UNSUPPORTED_N, n
+    bf = _Opts(1, 0, 0, 0)
+    assert L.align_batch(ctx, p, p, None, 256, 4, p, ctypes.byref(bf), None) == ca.ERR_UNSUPPORTED_N
+    assert L.align_batch(ctx, p, p, p, 128, 4, p, ctypes.byref(bf), None) == ca.ERR_UNSUPPORTED_N
+    assert L.align_all_pairs(ctx, p, 8, 128, p, ctypes.byref(bf), None) == ca.ERR_INVALID_ARG
+    assert L.align_all_pairs(ctx, p, -1, 64, p, ctypes.byref(ok), None) == ca.ERR_INVALID_ARG
+    assert L.align_all_pairs(ctx, None, 8, 64, p, None, None) == ca.ERR_INVALID_ARG
+    assert L.align_all_pairs(ctx, p, 65537, 64, p, None, None) == ca.ERR_INVALID_ARG   # > 2^31 - 1 pairs
+    assert L.resample_arclength(ctx, p, p, -1, p, p, None, None, 0, None) == ca.ERR_INVALID_ARG
+    assert L.resample_arclength(ctx, p, p, 4, p, p, None, None, 2, None) == ca.ERR_INVALID_ARG
+    assert L.resample_arclength(ctx, None, p, 4, p, p, None, None, 0, None) == ca.ERR_INVALID_ARG
+    assert L.resample_arclength(ctx, p, p, 4, None, p, None, None, 0, None) == ca.ERR_INVALID_ARG
+    assert L.resample_arclength(ctx, p, p, 2 ** 31, p, p, None, None, 0, None) == ca.ERR_INVALID_ARG
+    # empty work is a no-op that touches nothing
+    assert L.align_batch(ctx, None, None, None, 64, 0, None, None, None) == ca.OK
+    assert L.align_all_pairs(ctx, None, 1, 64, None, None, None) == ca.OK
+    assert L.resample_arclength(ctx, None, None, 0, None, None, None, None, 0, None) == ca.OK
