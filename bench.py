@@ -52,6 +52,9 @@ def sources_digest(names):
     return h.hexdigest()[:16]
 
 
+ALIGN_SOURCES = ["align.hip", "epilogue.hpp", "fft_engines.hpp", "dft_small.hpp", "common.hpp"]
+
+
 def traffic_for(kernel_key: str, digest: str, per_launch_units: float):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel sources (else None)."""
@@ -102,6 +105,28 @@ def time_steps(fn, steps, warmup, torch, graph=False):
     return ev[0].elapsed_time(ev[steps]) / steps, wall
 
 
+def time_parts(fns, steps, warmup, torch, graph=False):
+    """Time a step made of several calls, with an event after each call, so
+    that every call's average duration is measured inside the timed region.
+    Each call is captured in a graph of its own when graph is set."""
+    if graph:
+        fns = [graphed(f, torch) for f in fns]
+    for _ in range(warmup):
+        for f in fns:
+            f()
+    torch.cuda.synchronize()
+    k = len(fns)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps * k + 1)]
+    ev[0].record()
+    for i in range(steps):
+        for j, f in enumerate(fns):
+            f()
+            ev[i * k + j + 1].record()
+    torch.cuda.synchronize()
+    parts = [sum(ev[i * k + j].elapsed_time(ev[i * k + j + 1]) for i in range(steps)) / steps for j in range(k)]
+    return ev[0].elapsed_time(ev[steps * k]) / steps, parts
+
+
 def cpu_baseline_batch(raw1, raw2, n, seconds):
     """The FP64 oracle (slow method, OpenMP over pairs) on a bounded sample of
     the workload's pairs; the oracle's cost does not depend on the node values,
@@ -139,8 +164,7 @@ def bench_batch(args, torch, ca):
                           graph=not args.no_graph)
     algo_bytes = B * (2 * n * 8 + RESULT_BYTES)
     achieved = algo_bytes / (ms * 1e-3) / 1e9
-    digest = sources_digest(["align.hip", "epilogue.hpp", "fft_engines.hpp", "dft_small.hpp", "common.hpp"])
-    traffic = traffic_for("k_align_team_1024", digest, B)
+    traffic = traffic_for("k_align_team_1024", sources_digest(ALIGN_SOURCES), B)
     line = {
         "metric": "curve-pair alignments/sec at N=1024, FP32 vs split-BF16, err vs FP64 oracle",
         "value": B / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
@@ -148,8 +172,8 @@ def bench_batch(args, torch, ca):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batch of 65536 curve pairs, n=1024 nodes, FP32, top-2 FP64 re-scoring",
                    "pairs": B, "n": n, "rescore": "top2"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "roofline": {"bound": "hbm", "kernel": "k_align_team<1024>", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
     }
     if not args.no_cpu_baseline:
         k = min(B, 8192)
@@ -217,8 +241,10 @@ def bench_allpairs(args, torch, ca):
     line = base_line(args, P / (ms * 1e-3), "pairs/s", ms, "f32",
                      {"workload": "all pairs of a 4096-curve gallery, n=512 nodes, FP32", "curves": M,
                       "pairs": P, "n": n})
-    line["roofline"] = {"bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS,
-                        "unit": "TFLOP/s", "frac": achieved / VALU_FP32_PEAK_TFLOPS, "traffic": None}
+    traffic = traffic_for("k_allpairs_512", sources_digest(ALIGN_SOURCES), P)
+    line["roofline"] = {"bound": "alu", "kernel": "k_allpairs<512>", "achieved": achieved,
+                        "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": achieved / VALU_FP32_PEAK_TFLOPS, "traffic": traffic}
     if not args.no_cpu_baseline:
         gh = g[:256].cpu().numpy()
         ii, jj = np.triu_indices(256, 1)
@@ -248,19 +274,26 @@ def bench_ragged(args, torch, ca):
     half = int(off[-1].item())
     out = ca.empty_results(B, dev)
 
-    def step():
+    def resample():
         ca.resample_arclength(raw, roff, ooff, out=nodes, with_norms=False, with_flags=False)
+
+    def align():
         ca.align_batch(nodes[:half], nodes[half:], offsets=off, out=out)
 
-    ms, _ = time_steps(step, args.steps, args.warmup, torch, graph=not args.no_graph)
-    algo = raw.numel() * 8 + B * RESULT_BYTES
-    achieved = algo / (ms * 1e-3) / 1e9
+    ms, (ms_rs, ms_al) = time_parts([resample, align], args.steps, args.warmup, torch, graph=not args.no_graph)
+    # dominant kernel: the resampler (reads every raw vertex and both offset
+    # arrays, writes every node)
+    algo = raw.numel() * 8 + total * 8 + 2 * (2 * B + 1) * 8
+    achieved = algo / (ms_rs * 1e-3) / 1e9
     line = base_line(args, B / (ms * 1e-3), "pairs/s", ms, "f32",
                      {"workload": "100000 ragged pairs of raw polygons, n in [64,4096], GPU resampling "
                                   "+ alignment", "pairs": B, "raw_vertices": int(raw.numel()),
                       "nodes": total})
-    line["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    line["parts_ms"] = {"resample_arclength": ms_rs, "align_batch_ragged": ms_al}
+    traffic = traffic_for("k_resample_fast", sources_digest(["resample.hip", "common.hpp"]), 1.0)
+    line["roofline"] = {"bound": "hbm", "kernel": "k_resample_fast", "achieved": achieved,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                        "traffic": traffic}
     return line
 
 
@@ -324,8 +357,9 @@ def bench_small_batch(args, torch, ca):
     line["fp32_same_inputs"] = {"value": B / (ms32 * 1e-3), "ms_per_step": ms32,
                                 "hbm_frac": B * (2 * n * 8 + RESULT_BYTES) / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS}
     line["speedup_vs_fp32"] = ms32 / ms16
-    line["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",
-                        "frac": achieved / 2500.0, "traffic": None}
+    traffic = traffic_for("k_align_bf16", sources_digest(["bf16.hip"] + ALIGN_SOURCES[1:]), B)
+    line["roofline"] = {"bound": "mfma", "kernel": "k_align_bf16", "achieved": achieved, "peak": 2500.0,
+                        "unit": "TFLOP/s", "frac": achieved / 2500.0, "traffic": traffic}
     if not args.no_cpu_baseline:
         k = 4096
         line["cpu_baseline"] = cpu_baseline_batch(r1[:k].cpu().numpy(), r2[:k].cpu().numpy(), n,

@@ -26,13 +26,15 @@ __global__ __launch_bounds__(256, 2) void k_align_team(const cf* __restrict__ z1
     constexpr int R = N / T;
     constexpr int TEAMS = 256 / T;
     constexpr int PADN = team_padn<N>();
+    // per team: the FFT exchange area, later two copies of curve 2's nodes
+    constexpr int BUF = PADN > 2 * N ? PADN : 2 * N;
     __shared__ cf tws[TeamCfg<N>::TW];
-    __shared__ cf lds_all[TEAMS * PADN];
+    __shared__ cf lds_all[TEAMS * BUF];
     __shared__ int cand_all[TEAMS * kCandCap];
     load_twiddles<TeamCfg<N>::TW>(tws, tw);
     const int team = threadIdx.x / T;
     const int t = threadIdx.x % T;
-    cf* lds = lds_all + team * PADN;
+    cf* lds = lds_all + team * BUF;
     int* cand = cand_all + team * kCandCap;
     const int64_t stride = (int64_t)gridDim.x * TEAMS;
     for (int64_t pair = (int64_t)blockIdx.x * TEAMS + team; pair < num_pairs; pair += stride) {
@@ -55,13 +57,14 @@ __global__ __launch_bounds__(256, 2) void k_align_team(const cf* __restrict__ z1
         team_fft<N, T>(v, lds, tws, t);
         const double n1 = team_sum<T>(q1) / N;
         const double n2 = team_sum<T>(q2) / N;
-        // z2 nodes for the shifted FP64 dot products
-        constexpr int PS = TeamCfg<N>::PS;
-        const int rb = t + (t >> PS);
+        // z2 nodes, twice, for the shifted FP64 dot products
 #pragma unroll
-        for (int q = 0; q < R; ++q) lds[rb + T * q + ((T * q) >> PS)] = b0[q];
+        for (int q = 0; q < R; ++q) {
+            lds[t + T * q] = b0[q];
+            lds[N + t + T * q] = b0[q];
+        }
         wave_lds_sync();
-        const ca_result_t res = team_epilogue<N, T>(v, a0, lds, cand, t, n1, n2, rescore, theta64);
+        const ca_result_t res = team_epilogue<N, T, kZTwice>(v, a0, lds, cand, t, n1, n2, rescore, theta64);
         if (t == 0) out[pair] = res;
         wave_lds_sync();
     }

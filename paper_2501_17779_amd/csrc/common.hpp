@@ -96,19 +96,29 @@ __device__ __forceinline__ double rdlane(double x, int l) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Reductions across the W lanes of an aligned team (W a power of two <= 64).
-template <int W, typename V> __device__ __forceinline__ V team_sum(V v) {
-    if constexpr (W >= 2) v += dpp<kDppXor1>(v);
-    if constexpr (W >= 4) v += dpp<kDppXor2>(v);
-    if constexpr (W >= 8) v += dpp<kDppHalfMirror>(v);
-    if constexpr (W >= 16) v += dpp<kDppMirror>(v);
+// Reductions across the W lanes of an aligned team (W a power of two <= 64)
+// with a commutative operation.
+template <int W, typename V, typename Op> __device__ __forceinline__ V team_reduce(V v, Op op) {
+    if constexpr (W >= 2) v = op(v, dpp<kDppXor1>(v));
+    if constexpr (W >= 4) v = op(v, dpp<kDppXor2>(v));
+    if constexpr (W >= 8) v = op(v, dpp<kDppHalfMirror>(v));
+    if constexpr (W >= 16) v = op(v, dpp<kDppMirror>(v));
     if constexpr (W == 32) {
-        const V a = rdlane(v, 0) + rdlane(v, 16), b = rdlane(v, 32) + rdlane(v, 48);
+        const V a = op(rdlane(v, 0), rdlane(v, 16)), b = op(rdlane(v, 32), rdlane(v, 48));
         v = (threadIdx.x & 32) ? b : a;
     } else if constexpr (W == 64) {
-        v = (rdlane(v, 0) + rdlane(v, 16)) + (rdlane(v, 32) + rdlane(v, 48));
+        v = op(op(rdlane(v, 0), rdlane(v, 16)), op(rdlane(v, 32), rdlane(v, 48)));
     }
     return v;
+}
+template <int W, typename V> __device__ __forceinline__ V team_sum(V v) {
+    return team_reduce<W>(v, [](V a, V b) { return a + b; });
+}
+template <int W> __device__ __forceinline__ float team_max(float v) {
+    return team_reduce<W>(v, [](float a, float b) { return fmaxf(a, b); });
+}
+template <int W> __device__ __forceinline__ int team_min(int v) {
+    return team_reduce<W>(v, [](int a, int b) { return min(a, b); });
 }
 template <int W, typename V> __device__ __forceinline__ void team_argmax(V& v, int& i) {
     auto step = [&](V ov, int oi) { argmax_combine(v, i, ov, oi); };

@@ -42,9 +42,14 @@ __device__ __forceinline__ void finish(ca_result_t& res, const Pick& pk, int n, 
     const double c64 = sqrt(pk.best);
     if (pk.count > 1) flags |= CA_FLAG_RESCORED;
     if (capped) flags |= CA_FLAG_CAND_CAPPED;
-    double gap;
-    if (pk.count > 1 && pk.second >= 0.0) gap = (c64 - sqrt(pk.second)) / c64;
-    else gap = (d1 - d2) / d1;
+    // relative gap (c - s) / c = (c^2 - s^2) / (c^2 + c s): the difference of
+    // the squares is formed in FP64, the rest only needs FP32
+    float gap;
+    if (pk.count > 1 && pk.second >= 0.0)
+        gap = (float)(pk.best - pk.second) *
+              __builtin_amdgcn_rcpf((float)(pk.best + c64 * (double)sqrtf((float)pk.second)));
+    else
+        gap = (float)(d1 - d2) * __builtin_amdgcn_rcpf((float)d1);
     if (gap < kNearTie) flags |= CA_FLAG_NEAR_TIE;
     double th = theta_path;
     if (theta64) {
@@ -54,9 +59,9 @@ __device__ __forceinline__ void finish(ca_result_t& res, const Pick& pk, int n, 
     res.shift = pk.shift;
     res.flags = flags;
     res.theta = th;
-    res.err_est = (float)(2.0 * epsD / d1);
-    res.gap = (float)gap;
-    res.e0 = n1 + n2 - 2.0 * c64 / (double)n;
+    res.err_est = 2.0f * (float)epsD * __builtin_amdgcn_rcpf((float)d1);
+    res.gap = gap;
+    res.e0 = n1 + n2 - c64 * (2.0 / (double)n);
 }
 
 __device__ __forceinline__ bool special_case(ca_result_t& res, double n1, double n2, double bv) {
@@ -78,38 +83,58 @@ __device__ __forceinline__ bool special_case(ca_result_t& res, double n1, double
 }
 
 // --------------------------------------------------------------- team engine
+// Layouts of the LDS copy of curve 2's nodes read by the FP64 re-scoring:
+// kZPad: node i at lpad<N>(i); kZTwice: node i at i and at N + i, so that the
+// shifted reads (t + T q - c) mod N become one base plus constant offsets.
+enum { kZPad = 0, kZTwice = 1 };
+
 // Epilogue of one pair held by a team: d[q] = D[t + T q] (D = n conj C),
 // a0[q] = z1[t + T q] (FP32 nodes of curve 1), zb = LDS copy of curve 2's
-// nodes at padded positions, cand = the team's candidate list in LDS.
+// nodes in layout ZL, cand = the team's candidate list in LDS.
 // Returns the finished result (every lane).
-template <int N, int T>
+template <int N, int T, int ZL = kZPad>
 __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const cf (&a0)[N / T],
                                                      const cf* zb, int* cand, int t, double n1, double n2,
                                                      int rescore, int theta64,
                                                      double err_u = num<float>::u) {
     constexpr int R = N / T;
+    constexpr int kNone = 0x7fffffff;
+    // |D|^2, and per lane the largest and second largest value
     float m2[R];
-    float bv = -1.0f;
-    int bi = 0;
+    float b1 = -1.0f, b2 = -1.0f;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         m2[q] = norm2(d[q]);
-        if (m2[q] > bv) { bv = m2[q]; bi = t + T * q; }
+        b2 = fmaxf(b2, fminf(b1, m2[q]));
+        b1 = fmaxf(b1, m2[q]);
     }
-    team_argmax<T>(bv, bi);
-    float cv = -1.0f;
-    int ci = 0;
+    // best value, then the smallest shift holding it
+    const float bv = team_max<T>(b1);
+    int bl = kNone;
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-        const int idx = t + T * q;
-        if (idx != bi && m2[q] > cv) { cv = m2[q]; ci = idx; }
-    }
-    team_argmax<T>(cv, ci);
+    for (int q = R - 1; q >= 0; --q)
+        if (m2[q] == bv) bl = t + T * q;
+    int bi = team_min<T>(bl);
+    if (bi == kNone) bi = 0;     // no finite maximum: flagged by special_case
+    // runner-up value over every other shift: the lane holding bi offers its
+    // second largest value, the others their largest
+    const float cv = team_max<T>((bi & (T - 1)) == t ? b2 : b1);
+    auto runner_up = [&]() {
+        int cl = kNone;
+#pragma unroll
+        for (int q = R - 1; q >= 0; --q) {
+            const int idx = t + T * q;
+            if (m2[q] == cv && idx != bi) cl = idx;
+        }
+        const int c = team_min<T>(cl);
+        return c == kNone ? ((bi + 1) & (N - 1)) : c;
+    };
 
     ca_result_t res;
     if (special_case(res, n1, n2, (double)bv)) return res;
-    const double d1 = sqrt((double)bv), d2 = sqrt(fmax((double)cv, 0.0));
-    const double epsD = kErrScale * err_u * (double)ilog2_ceil(N) * N * N * sqrt(n1 * n2);
+    const double d1 = (double)sqrtf(bv), d2 = (double)sqrtf(fmaxf(cv, 0.0f));
+    const double epsD =
+        (double)((float)(kErrScale * err_u * (double)ilog2_ceil(N) * N * N) * sqrtf((float)(n1 * n2)));
     const bool two = d1 - d2 < 2.0 * epsD;
 
     // candidate list (team-uniform order: by register, then by lane)
@@ -151,6 +176,7 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
         }
     }
     if (rescore != CA_RESCORE_WINDOW || cnt == 0) {
+        const int ci = two ? runner_up() : bi;
         if (t == 0) {
             cand[0] = bi;
             cand[1] = ci;
@@ -162,9 +188,10 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
     for (int k = 0; k < cnt; ++k) {
         const int c = cand[k];
         double re = 0.0, im = 0.0;
+        const cf* zs = zb + ((t - c) & (N - 1));
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            const cf zz = zb[lpad<N>((t + T * q - c) & (N - 1))];
+            const cf zz = (ZL == kZTwice) ? zs[T * q] : zb[lpad<N>((t + T * q - c) & (N - 1))];
             const double ax = a0[q].x, ay = a0[q].y, bx = zz.x, by = zz.y;
             re = fma(ax, bx, fma(ay, by, re));
             im = fma(ay, bx, fma(-ax, by, im));
