@@ -182,6 +182,27 @@ ca_status_t resample_arclength(ca_context_t ctx, const void* raw, const int64_t*
                                double* norms_out, uint32_t* flags_out, int32_t mode,
                                void* stream);
 
+/*
+ * to_initializer -- hand-off to an elastic shape-distance solver (section 4:
+ * the iterative solver is started from the rigid optimum (t0*, R*) with
+ * gamma(t) = t).  Converts alignment records into the paper's notation.
+ *   results : count records written by align_pair / align_batch /
+ *             align_all_pairs (device)
+ *   n       : node count of every pair, or 0 when offsets is given
+ *   offsets : int64 [count+1] node offsets of a ragged batch (device, the
+ *             same array passed to align_batch), or NULL
+ *   t0_out  : FP64 [count] (device): t0* = ((n - shift) mod n) / n in [0, 1),
+ *             the start parameter at which curve 2 is read, beta2(t + t0*)
+ *   rot_out : FP64 [count][4] (device), row-major R* = R(theta_p) of section 2,
+ *             [[cos theta_p, sin theta_p], [-sin theta_p, cos theta_p]] with
+ *             theta_p = -theta, so that R* beta2(t + t0*) is aligned to beta1(t)
+ * Records flagged DEGENERATE, NONFINITE or UNSUPPORTED_N carry shift 0 and
+ * theta 0 and convert to t0* = 0, R* = identity.  count = 0 is a no-op.
+ */
+ca_status_t to_initializer(ca_context_t ctx, const ca_result_t* results, int32_t n,
+                           const int64_t* offsets, int64_t count, double* t0_out, double* rot_out,
+                           void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -164,3 +164,19 @@ def per_shift_arrays(z1, z2):
     s = np.arange(n)
     m = (n - s) % n
     return T[m], wrap_angle(-H[m]), m, H[m]
+
+
+def R_paper(theta_paper: float) -> np.ndarray:
+    """R(theta) of section 2: [[cos, sin], [-sin, cos]] (clockwise by theta)."""
+    c, s = np.cos(theta_paper), np.sin(theta_paper)
+    return np.array([[c, s], [-s, c]])
+
+
+def initializer(z1, z2):
+    """The rigid optimum handed to an elastic solver (section 4): the start
+    parameter t0 = m / n at which curve 2 is read and R(theta_paper), the
+    slow method's minimiser of Eq. disc-energy.  Returns (t0, R, align_pair dict)."""
+    res = align_pair(z1, z2)
+    n = _as_xy(z1).shape[0]
+    return res["m"] / n, R_paper(res["theta_paper"]), res
+

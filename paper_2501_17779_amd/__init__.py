@@ -45,7 +45,7 @@ RESAMPLE = {"spline": 0, "linear": 1}
 MAX_N = 4096
 
 EXPORTED = ("ca_create", "ca_destroy", "ca_status_string", "ca_last_error", "ca_n_supported",
-            "align_pair", "align_batch", "align_all_pairs", "resample_arclength")
+            "align_pair", "align_batch", "align_all_pairs", "resample_arclength", "to_initializer")
 
 
 class CurveAlignError(RuntimeError):
@@ -87,8 +87,9 @@ def lib():
             L.align_batch.argtypes = [vp, vp, vp, vp, i32, i64, vp, vp, vp]
             L.align_all_pairs.argtypes = [vp, vp, i32, i32, vp, vp, vp]
             L.resample_arclength.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, i32, vp]
+            L.to_initializer.argtypes = [vp, vp, i32, vp, i64, vp, vp, vp]
             for name in ("ca_create", "ca_destroy", "align_pair", "align_batch",
-                         "align_all_pairs", "resample_arclength"):
+                         "align_all_pairs", "resample_arclength", "to_initializer"):
                 getattr(L, name).restype = i32
             _lib = L
     return _lib
@@ -240,6 +241,31 @@ def align_all_pairs(curves, *, rescore="top2", theta_fp64=False, out=None, strea
     _check(lib().align_all_pairs(ctx.handle, curves.data_ptr(), m, n, out.data_ptr(),
                                  ctypes.byref(opt), _stream_ptr(stream)))
     return out
+
+
+def to_initializer(results, n=None, offsets=None, *, stream=None, ctx=None):
+    """Alignment records -> the paper's (t0*, R*) for an elastic solver.
+
+    `results` is the uint8 [count, 32] tensor from align_*; give the uniform
+    node count `n` or the ragged `offsets` used for the alignment.  Returns
+    (t0 FP64 [count], R FP64 [count, 2, 2]).
+    """
+    import torch
+    _require(results, "results", (torch.uint8,), 2)
+    count = results.shape[0]
+    if (n is None) == (offsets is None):
+        raise ValueError("give exactly one of n and offsets")
+    if offsets is not None:
+        _require(offsets, "offsets", (torch.int64,), 1)
+        if offsets.shape[0] != count + 1:
+            raise ValueError("offsets must have count + 1 entries")
+    ctx = ctx or default_context(results.device.index)
+    t0 = torch.empty(count, dtype=torch.float64, device=results.device)
+    rot = torch.empty(count, 2, 2, dtype=torch.float64, device=results.device)
+    _check(lib().to_initializer(ctx.handle, results.data_ptr(), 0 if n is None else int(n),
+                                None if offsets is None else offsets.data_ptr(), count,
+                                t0.data_ptr(), rot.data_ptr(), _stream_ptr(stream)))
+    return t0, rot
 
 
 def resample_arclength(raw, raw_offsets, out_offsets, *, mode="spline", with_norms=True,

@@ -490,4 +490,20 @@ ca_status_t resample_arclength(ca_context_t c, const void* raw, const int64_t* r
     return CA_OK;
 }
 
+ca_status_t to_initializer(ca_context_t c, const ca_result_t* results, int32_t n, const int64_t* offsets,
+                           int64_t count, double* t0_out, double* rot_out, void* stream) {
+    if (!c) return fail(CA_ERR_INVALID_ARG, "context is NULL");
+    if (count < 0) return fail(CA_ERR_INVALID_ARG, "count < 0");
+    if (!offsets && n < 1) return fail(CA_ERR_INVALID_ARG, "n must be >= 1 without offsets");
+    if (offsets && n != 0) return fail(CA_ERR_INVALID_ARG, "n must be 0 when offsets are given");
+    if (count == 0) return CA_OK;
+    if (!results || !t0_out || !rot_out)
+        return fail(CA_ERR_INVALID_ARG, "results, t0_out and rot_out must be non-NULL");
+    DeviceGuard g(c->device);
+    const hipError_t e =
+        ca::launch_initializer(results, n, offsets, count, t0_out, rot_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "initializer kernel launch");
+    return CA_OK;
+}
+
 }  // extern "C"

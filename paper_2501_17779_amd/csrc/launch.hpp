@@ -58,6 +58,8 @@ bool allpairs_supported(int n);
 // than 3 vertices, duplicates, non-finite values, above the vertex cap) are
 // listed in slow_list (count in *slow_count, device) and resampled by the
 // general workgroup-per-curve kernel with `slots` scratch slots.
+hipError_t launch_initializer(const ca_result_t* res, int n, const int64_t* offsets, int64_t count,
+                              double* t0, double* rot, hipStream_t s);
 hipError_t launch_resample(const void* raw, const int64_t* raw_off, int64_t num_curves,
                            const int64_t* out_off, void* out, double* norms, uint32_t* flags,
                            int mode, void* scratch, int64_t slot_bytes, int64_t slots,

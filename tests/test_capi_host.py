@@ -138,6 +138,7 @@ def test_null_context_is_rejected_on_host(L):
     assert L.align_batch(None, dummy, dummy, None, 64, 4, dummy, None, None) == ca.ERR_INVALID_ARG
     assert L.align_all_pairs(None, dummy, 8, 64, dummy, None, None) == ca.ERR_INVALID_ARG
     assert L.resample_arclength(None, dummy, dummy, 4, dummy, dummy, None, None, 0, None) == ca.ERR_INVALID_ARG
+    assert L.to_initializer(None, dummy, 64, None, 4, dummy, dummy, None) == ca.ERR_INVALID_ARG
     assert L.ca_create(None, 0) == ca.ERR_INVALID_ARG
     assert L.ca_destroy(None) == ca.OK
 
@@ -189,7 +190,13 @@ def test_argument_errors_before_device_work(L):
     assert L.resample_arclength(ctx, None, p, 4, p, p, None, None, 0, None) == ca.ERR_INVALID_ARG
     assert L.resample_arclength(ctx, p, p, 4, None, p, None, None, 0, None) == ca.ERR_INVALID_ARG
     assert L.resample_arclength(ctx, p, p, 2 ** 31, p, p, None, None, 0, None) == ca.ERR_INVALID_ARG
+    assert L.to_initializer(ctx, p, 64, None, -1, p, p, None) == ca.ERR_INVALID_ARG
+    assert L.to_initializer(ctx, p, 0, None, 4, p, p, None) == ca.ERR_INVALID_ARG
+    assert L.to_initializer(ctx, p, 64, p, 4, p, p, None) == ca.ERR_INVALID_ARG
+    assert L.to_initializer(ctx, p, 64, None, 4, None, p, None) == ca.ERR_INVALID_ARG
+    assert L.to_initializer(ctx, p, 64, None, 4, p, None, None) == ca.ERR_INVALID_ARG
     # empty work is a no-op that touches nothing
+    assert L.to_initializer(ctx, None, 64, None, 0, None, None, None) == ca.OK
     assert L.align_batch(ctx, None, None, None, 64, 0, None, None, None) == ca.OK
     assert L.align_all_pairs(ctx, None, 1, 64, None, None, None) == ca.OK
     assert L.resample_arclength(ctx, None, None, 0, None, None, None, None, 0, None) == ca.OK

@@ -287,3 +287,24 @@ def test_generator_template_truth():
     s, th = oracle.to_library_convention(res["m"], res["theta_paper"], 200)
     assert s == truth["s0"]
     assert abs(oracle.wrap_angle(th + truth["theta0"])) < 1e-6
+
+
+@pytest.mark.parametrize("n,m0,theta0", [(64, 16, 1.0), (200, 150, -2.2), (257, 1, 0.4)])
+def test_initializer_reproduces_curve_in_matrix_form(n, m0, theta0):
+    """Hand-off of section 4 in the matrix notation of section 2: with
+    beta2 built so that R(theta0) beta2(t + t0) = beta1(t) at t0 = m0 / n,
+    the oracle returns exactly that t0 and R, and applying them to the nodes
+    of beta2 reproduces beta1."""
+    rng = np.random.default_rng(n + m0)
+    z1 = random_curve(rng, n)
+    b1 = np.stack([z1.real, z1.imag], 1)
+    R0 = R_paper(theta0)
+    b2 = np.empty_like(b1)
+    for l in range(n):
+        b2[(l + m0) % n] = R0.T @ b1[l]
+    t0, R, res = oracle.initializer(b1, b2)
+    assert t0 == m0 / n
+    assert np.max(np.abs(R - R0)) < 1e-12
+    back = np.stack([R @ b2[(l + round(t0 * n)) % n] for l in range(n)])
+    assert np.max(np.abs(back - b1)) < 1e-12
+    assert res["E"] < 1e-24
