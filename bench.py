@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="batch",
-                    choices=["batch", "pair", "allpairs", "ragged", "bf16", "copy"])
+                    choices=["batch", "pair", "allpairs", "ragged", "ragged_any", "bf16", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every step from Python instead of replaying a captured HIP graph")
@@ -256,13 +256,14 @@ def bench_allpairs(args, torch, ca):
     return line
 
 
-def bench_ragged(args, torch, ca):
-    """100,000 pairs of raw polygons, n log-uniform in [64, 4096] (7-smooth),
-    1.2-5x more raw vertices than n: GPU resampling + ragged alignment per step."""
+def bench_ragged(args, torch, ca, snap=True):
+    """100,000 pairs of raw polygons, n log-uniform in [64, 4096] (7-smooth,
+    or any integer with snap=False), 1.2-5x more raw vertices than n: GPU
+    resampling + ragged alignment per step."""
     from synth import curves
     B = 100000
     dev = torch.device("cuda:0")
-    d = curves.ragged_pairs_torch(17782, B, dev)
+    d = curves.ragged_pairs_torch(17782, B, dev, snap=snap)
     raw = torch.cat([d["raw1"], d["raw2"]])
     roff = torch.cat([d["off1"], d["off2"][1:] + d["off1"][-1]])
     n = d["n"].long()
@@ -285,10 +286,12 @@ def bench_ragged(args, torch, ca):
     # arrays, writes every node)
     algo = raw.numel() * 8 + total * 8 + 2 * (2 * B + 1) * 8
     achieved = algo / (ms_rs * 1e-3) / 1e9
+    wl = ("100000 ragged pairs of raw polygons, n in [64,4096], GPU resampling + alignment" if snap else
+          "100000 ragged pairs of raw polygons, any integer n in [64,4096] (zero-padded transforms for n "
+          "with a prime factor above 7), GPU resampling + alignment")
     line = base_line(args, B / (ms * 1e-3), "pairs/s", ms, "f32",
-                     {"workload": "100000 ragged pairs of raw polygons, n in [64,4096], GPU resampling "
-                                  "+ alignment", "pairs": B, "raw_vertices": int(raw.numel()),
-                      "nodes": total})
+                     {"workload": wl, "pairs": B, "raw_vertices": int(raw.numel()), "nodes": total,
+                      "n_7smooth": bool(snap)})
     line["parts_ms"] = {"resample_arclength": ms_rs, "align_batch_ragged": ms_al}
     traffic = traffic_for("k_resample_fast", sources_digest(["resample.hip", "common.hpp"]), 1.0)
     line["roofline"] = {"bound": "hbm", "kernel": "k_resample_fast", "achieved": achieved,
@@ -396,7 +399,8 @@ def main():
         sys.exit(1)
     ca.default_context(0)
     fn = {"batch": bench_batch, "copy": bench_copy, "pair": bench_pair, "allpairs": bench_allpairs,
-          "ragged": bench_ragged, "bf16": bench_small_batch}[args.config]
+          "ragged": bench_ragged, "ragged_any": lambda a, t, c: bench_ragged(a, t, c, snap=False),
+          "bf16": bench_small_batch}[args.config]
     line = fn(args, torch, ca)
     print(json.dumps(line), flush=True)
 

@@ -113,8 +113,15 @@ const char* ca_status_string(ca_status_t status);
 /* Text of the last error raised on this thread (empty if none). */
 const char* ca_last_error(void);
 
-/* Largest n accepted by align_* (uniform and ragged), and the predicate for
- * a single n: 2 <= n <= CA_MAX_N and n has no prime factor above 7. */
+/* Largest n accepted by align_pair / align_batch (uniform and ragged), and
+ * how a single n is handled:
+ *   1 -- 2 <= n <= CA_MAX_N with no prime factor above 7: transforms of size n;
+ *   2 -- any other n in [2, CA_MAX_N]: the correlation is evaluated exactly
+ *        through zero-padded transforms of the smallest size M >= 2n with no
+ *        prime factor above 7 (curve 1 followed by zeros, curve 2 repeated
+ *        twice; no wrap-around at the lags that hold C(s)).  FP32 takes every
+ *        such n, FP64 those with M <= 4096 (n <= 2048);
+ *   0 -- n outside [2, CA_MAX_N]. */
 #define CA_MAX_N 4096
 int32_t ca_n_supported(int32_t n);
 
@@ -130,7 +137,8 @@ ca_status_t align_pair(ca_context_t ctx, const void* z1, const void* z2, int32_t
 /*
  * align_batch -- Algorithm 2 for many independent pairs.
  *   Uniform batch (offsets == NULL): pair p uses z1 + p*n and z2 + p*n
- *     (n nodes each); n must satisfy ca_n_supported, else CA_ERR_UNSUPPORTED_N.
+ *     (n nodes each); ca_n_supported(n) must be nonzero (and, for FP64 with
+ *     ca_n_supported(n) == 2, n <= 2048), else CA_ERR_UNSUPPORTED_N.
  *   Ragged batch (offsets != NULL): offsets is a device array of num_pairs+1
  *     int64 node offsets, nondecreasing, offsets[0] = 0; pair p uses nodes
  *     [offsets[p], offsets[p+1]) of both z1 and z2; `n` is ignored.  A pair
@@ -150,8 +158,8 @@ ca_status_t align_batch(ca_context_t ctx, const void* z1, const void* z2,
  * curves with n nodes each (complex64, curve-contiguous [m][n]).  Per-curve
  * spectra and norms are computed once.  Results are packed in row-major
  * upper-triangle order: pair (i, j) is at k = i*m - i*(i+1)/2 + (j - i - 1),
- * m*(m-1)/2 results in total.  FP32 precision only; n in {64,...,1024}
- * powers of two or any supported n.
+ * m*(m-1)/2 results in total.  FP32 precision only; n must be a power of
+ * two in [64, 1024], else CA_ERR_UNSUPPORTED_N.
  */
 ca_status_t align_all_pairs(ca_context_t ctx, const void* curves, int32_t m, int32_t n,
                             ca_result_t* out_upper, const ca_options_t* opt, void* stream);

@@ -285,35 +285,42 @@ hipError_t launch_allpairs(const void* curves, const void* spec, const double* n
 
 // -------------------------------------------------------------- block engine
 // Persistent kernels, one pair per workgroup at a time; each launch serves
-// the pairs whose size lies in [nlo, nhi] (a size class) with NT threads and
-// LDS for NMAX nodes per signal.  Unsupported sizes are flagged by the class
-// that has nlo == 0.
-template <typename T, int NT, int NMAX>
+// the pairs whose transform size lies in [mlo, mhi] (a size class) with NT
+// threads and LDS for MMAX values per signal.  Pairs that no class can take
+// (n outside [2, kMaxN], transform larger than mcap) are flagged by the class
+// that has mlo == 0.
+//
+// A 7-smooth n is transformed at size M = n.  Any other n uses the plan's
+// 7-smooth M >= 2n: with a = z1 followed by zeros and b = (z2, z2, zeros),
+// the cyclic correlation of length M has no wrap-around at the lags
+// M - n + s, 0 <= s < n, where it equals C(s) = sum_k z1[k] conj(z2[k - s])
+// (indices mod n).  The forward transform of conj(A) B then gives
+// D[M - n + s] = M conj(C(s)).
+template <typename T, int NT, int MMAX>
 __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1, const cpx<T>* __restrict__ z2,
                                                   const int64_t* __restrict__ offsets, int n_uniform,
                                                   int64_t num_pairs, ca_result_t* __restrict__ out,
                                                   const Plan* __restrict__ plans,
                                                   const cpx<T>* __restrict__ arena, int rescore, int theta64,
-                                                  int nlo, int nhi) {
-    __shared__ cpx<T> A[NMAX];
-    __shared__ cpx<T> B[NMAX];
+                                                  int mlo, int mhi, int mcap) {
+    __shared__ cpx<T> A[MMAX];
+    __shared__ cpx<T> B[MMAX];
     __shared__ double red[2 * (NT / 64)];
     __shared__ int clist[kCandCap + 1];
     for (int64_t pair = blockIdx.x; pair < num_pairs; pair += gridDim.x) {
         int64_t off;
         int n;
-        bool bad = false;
         if (offsets) {
             off = offsets[pair];
             const int64_t len = offsets[pair + 1] - off;
             n = (len >= 2 && len <= kMaxN) ? (int)len : 0;
-            bad = n == 0 || plans[n].n != n;
         } else {
             off = pair * (int64_t)n_uniform;
             n = n_uniform;
         }
-        if (bad) {
-            if (nlo == 0 && threadIdx.x == 0) {
+        const int M = n ? plans[n].n : 0;
+        if (M == 0 || M > mcap) {
+            if (mlo == 0 && threadIdx.x == 0) {
                 ca_result_t r;
                 r.shift = 0; r.flags = CA_FLAG_UNSUPPORTED_N; r.theta = 0.0; r.err_est = 0.0f; r.gap = 0.0f;
                 r.e0 = __builtin_nan("");
@@ -321,39 +328,46 @@ __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1,
             }
             continue;
         }
-        if (n < nlo || n > nhi) continue;
+        if (M < mlo || M > mhi) continue;
         const Plan& p = plans[n];
         const cpx<T>* tw = arena + p.tw_off;
         const cpx<T>* pa = z1 + off;
         const cpx<T>* pb = z2 + off;
+        const bool padded = M != n;
+        const int base = M - n;              // D index of shift 0
+        const int nb = padded ? 2 * n : n;   // extent of b
 
         double q1 = 0.0, q2 = 0.0;
-        for (int k = threadIdx.x; k < n; k += NT) {
-            const cpx<T> a = pa[k], b = pb[k];
+        for (int k = threadIdx.x; k < M; k += NT) {
+            const cpx<T> zero = {T(0), T(0)};
+            const cpx<T> a = k < n ? pa[k] : zero;
+            const cpx<T> b = k < nb ? pb[k < n ? k : k - n] : zero;
             A[k] = a;
             B[k] = b;
-            q1 = fma((double)a.x, (double)a.x, fma((double)a.y, (double)a.y, q1));
-            q2 = fma((double)b.x, (double)b.x, fma((double)b.y, (double)b.y, q2));
+            if (k < n) {
+                q1 = fma((double)a.x, (double)a.x, fma((double)a.y, (double)a.y, q1));
+                q2 = fma((double)b.x, (double)b.x, fma((double)b.y, (double)b.y, q2));
+            }
         }
         block_sum2<NT>(q1, q2, red);                    // synchronises
         const double n1 = q1 / n, n2 = q2 / n;
-        blk_fft2<NT, NMAX>(A, B, p, tw);
-        for (int k = threadIdx.x; k < n; k += NT) A[k] = cjmul(A[k], B[k]);
+        blk_fft2<NT, MMAX>(A, B, p, tw);
+        for (int k = threadIdx.x; k < M; k += NT) A[k] = cjmul(A[k], B[k]);
         __syncthreads();
-        blk_fft<NT, NMAX>(A, p, tw);
+        blk_fft<NT, MMAX>(A, p, tw);
         for (int k = threadIdx.x; k < n; k += NT) B[k] = pb[k];   // z2 again, for re-scoring
 
         T bv = T(-1);
         int bi = 0;
         for (int k = threadIdx.x; k < n; k += NT) {
-            const T m = norm2(A[k]);
+            const T m = norm2(A[base + k]);
             if (m > bv) { bv = m; bi = k; }
         }
         block_argmax<NT>(bv, bi, red);
         T cv = T(-1);
         int ci = 0;
         for (int k = threadIdx.x; k < n; k += NT) {
-            const T m = norm2(A[k]);
+            const T m = norm2(A[base + k]);
             if (k != bi && m > cv) { cv = m; ci = k; }
         }
         block_argmax<NT>(cv, ci, red);
@@ -362,8 +376,11 @@ __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1,
         if (!special_case(res, n1, n2, (double)bv)) {
             const double d1 = sqrt((double)bv), d2 = sqrt(fmax((double)cv, 0.0));
             double lg = 0.0;
-            for (int m = 1; m < n; m <<= 1) lg += 1.0;
-            const double epsD = kErrScale * num<T>::u * lg * (double)n * (double)n * sqrt(n1 * n2);
+            for (int m = 1; m < M; m <<= 1) lg += 1.0;
+            // |D| error bound: transform size M, |a| |b| = n sqrt(n1 n2) (times
+            // sqrt 2 when curve 2 is repeated)
+            const double epsD = kErrScale * num<T>::u * lg * (double)M * (double)n * sqrt(n1 * n2) *
+                                (padded ? 1.4142135623730951 : 1.0);
             Pick pk;
             auto rescore_one = [&](int c) {
                 double re = 0.0, im = 0.0;
@@ -385,7 +402,7 @@ __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1,
                 if (threadIdx.x == 0) clist[0] = 0;
                 __syncthreads();
                 for (int k = threadIdx.x; k < n; k += NT) {
-                    if ((double)norm2(A[k]) >= thr2) {
+                    if ((double)norm2(A[base + k]) >= thr2) {
                         const int pos = atomicAdd(&clist[0], 1);
                         if (pos < kCandCap) clist[1 + pos] = k;
                     }
@@ -402,7 +419,7 @@ __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1,
                 rescore_one(bi);
                 if (d1 - d2 < 2.0 * epsD) rescore_one(ci);
             }
-            const cpx<T> sel = A[pk.shift];
+            const cpx<T> sel = A[base + pk.shift];
             const double thp = wrap_pi(atan2(-(double)sel.y, (double)sel.x));
             finish(res, pk, n, n1, n2, d1, d2, epsD, capped, thp, theta64);
         }
@@ -412,33 +429,37 @@ __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1,
 }
 
 
-template <typename T, int NT, int NMAX>
-static hipError_t launch_blk_class(const BlkArgs& a, int nlo, int nhi, hipStream_t s) {
+template <typename T, int NT, int MMAX>
+static hipError_t launch_blk_class(const BlkArgs& a, int mlo, int mhi, hipStream_t s) {
     static int per_cu = -1;
     if (per_cu < 0) {
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_align_blk<T, NT, NMAX>, NT, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_align_blk<T, NT, MMAX>, NT, 0) != hipSuccess ||
             nb < 1)
             nb = 1;
         per_cu = nb;
     }
     int64_t grid = (int64_t)a.num_cus * per_cu;
     if (grid > a.num_pairs) grid = a.num_pairs;
-    hipLaunchKernelGGL((k_align_blk<T, NT, NMAX>), dim3((unsigned)grid), dim3(NT), 0, s,
+    hipLaunchKernelGGL((k_align_blk<T, NT, MMAX>), dim3((unsigned)grid), dim3(NT), 0, s,
                        (const cpx<T>*)a.z1, (const cpx<T>*)a.z2, a.offsets, a.n_uniform, a.num_pairs, a.out,
-                       a.plans, (const cpx<T>*)a.tw_arena, a.rescore, a.theta64, nlo, nhi);
+                       a.plans, (const cpx<T>*)a.tw_arena, a.rescore, a.theta64, mlo, mhi, a.m_cap);
     return hipGetLastError();
 }
 
-// Size classes: (64 threads, n <= 512), (128, <= 1024), (256, <= 2048), (256, <= 4096).
+// Size classes by transform size: (64 threads, M <= 512), (128, <= 1024),
+// (256, <= 2048), (256, <= 4096) and, FP32 only, (256, <= 8192).
 template <typename T>
 static hipError_t launch_blk(const BlkArgs& a, hipStream_t s) {
-    const int lo = a.offsets ? 0 : a.n_uniform, hi = a.offsets ? kMaxN : a.n_uniform;
+    const int lo = a.offsets ? 0 : a.m_uniform, hi = a.offsets ? a.m_cap : a.m_uniform;
     hipError_t e = hipSuccess;
-    if (lo <= 512 && e == hipSuccess) e = launch_blk_class<T, 64, 512>(a, a.offsets ? 0 : lo, 512, s);
+    if (lo <= 512 && e == hipSuccess) e = launch_blk_class<T, 64, 512>(a, lo, 512, s);
     if (hi > 512 && lo <= 1024 && e == hipSuccess) e = launch_blk_class<T, 128, 1024>(a, 513, 1024, s);
     if (hi > 1024 && lo <= 2048 && e == hipSuccess) e = launch_blk_class<T, 256, 2048>(a, 1025, 2048, s);
-    if (hi > 2048 && e == hipSuccess) e = launch_blk_class<T, 256, 4096>(a, 2049, 4096, s);
+    if (hi > 2048 && lo <= 4096 && e == hipSuccess) e = launch_blk_class<T, 256, 4096>(a, 2049, 4096, s);
+    if constexpr (sizeof(T) == 4) {
+        if (hi > 4096 && e == hipSuccess) e = launch_blk_class<T, 256, 8192>(a, 4097, 8192, s);
+    }
     return e;
 }
 

@@ -32,12 +32,26 @@ ca_status_t hip_fail(hipError_t e, const char* what) {
     return CA_ERR_HIP;
 }
 
-bool smooth7(int n) {
-    if (n < 2 || n > CA_MAX_N) return false;
+bool smooth7_size(int m) {
+    if (m < 1) return false;
     for (int p : {2, 3, 5, 7})
-        while (n % p == 0) n /= p;
-    return n == 1;
+        while (m % p == 0) m /= p;
+    return m == 1;
 }
+
+bool smooth7(int n) { return n >= 2 && n <= CA_MAX_N && smooth7_size(n); }
+
+// Transform size of the block engine for n in [2, CA_MAX_N]: n itself when it
+// is 7-smooth, else the smallest 7-smooth M >= 2n (zero-padded correlation).
+int transform_size(int n) {
+    if (smooth7(n)) return n;
+    int m = 2 * n;
+    while (!smooth7_size(m)) ++m;
+    return m;
+}
+
+constexpr int kMaxM = 2 * CA_MAX_N;
+constexpr int kFp64MaxM = CA_MAX_N;   // LDS of the FP64 block engine
 
 // Radix schedule of the block engine: eights, then a four or two, then the
 // odd primes.
@@ -111,18 +125,23 @@ ca_status_t ensure_tables(ca_context* c, bool need64) {
     if (!c->d_plans) {
         c->h_plans.assign(CA_MAX_N + 1, Plan{});
         std::vector<float> arena32;
+        std::vector<int64_t> tw_off(kMaxM + 1, -1);
         int64_t off = 0;
         std::vector<double> re, im;
-        for (int n = 2; n <= CA_MAX_N; ++n) {
-            if (!smooth7(n)) continue;
-            make_plan(n, c->h_plans[n]);
-            c->h_plans[n].tw_off = off;
-            twiddles(n, re, im);
-            for (int m = 0; m < n; ++m) {
-                arena32.push_back((float)re[m]);
-                arena32.push_back((float)im[m]);
+        for (int m = 2; m <= kMaxM; ++m) {
+            if (!smooth7_size(m)) continue;
+            tw_off[m] = off;
+            twiddles(m, re, im);
+            for (int k = 0; k < m; ++k) {
+                arena32.push_back((float)re[k]);
+                arena32.push_back((float)im[k]);
             }
-            off += n;
+            off += m;
+        }
+        for (int n = 2; n <= CA_MAX_N; ++n) {
+            const int M = transform_size(n);
+            make_plan(M, c->h_plans[n]);
+            c->h_plans[n].tw_off = tw_off[M];
         }
         hipError_t e;
         if ((e = hipMalloc(&c->d_plans, sizeof(Plan) * (CA_MAX_N + 1))) != hipSuccess)
@@ -138,12 +157,12 @@ ca_status_t ensure_tables(ca_context* c, bool need64) {
     }
     if (need64 && !c->d_tw64) {
         std::vector<double> arena64, re, im;
-        for (int n = 2; n <= CA_MAX_N; ++n) {
-            if (!smooth7(n)) continue;
-            twiddles(n, re, im);
-            for (int m = 0; m < n; ++m) {
-                arena64.push_back(re[m]);
-                arena64.push_back(im[m]);
+        for (int m = 2; m <= kMaxM; ++m) {      // same order and offsets as the FP32 arena
+            if (!smooth7_size(m)) continue;
+            twiddles(m, re, im);
+            for (int k = 0; k < m; ++k) {
+                arena64.push_back(re[k]);
+                arena64.push_back(im[k]);
             }
         }
         hipError_t e;
@@ -154,10 +173,6 @@ ca_status_t ensure_tables(ca_context* c, bool need64) {
             return hip_fail(e, "FP64 twiddle upload");
     }
     return CA_OK;
-}
-
-const void* tw32_for(ca_context* c, int n) {
-    return (const char*)c->d_tw32 + c->h_plans[n].tw_off * 2 * sizeof(float);
 }
 
 // Team-engine twiddles per pass after the first: (radix RP, stride NS, table offset).
@@ -300,7 +315,10 @@ const char* ca_status_string(ca_status_t s) {
 
 const char* ca_last_error(void) { return g_err.c_str(); }
 
-int32_t ca_n_supported(int32_t n) { return smooth7(n) ? 1 : 0; }
+int32_t ca_n_supported(int32_t n) {
+    if (smooth7(n)) return 1;
+    return (n >= 2 && n <= CA_MAX_N) ? 2 : 0;
+}
 
 ca_status_t ca_create(ca_context_t* ctx, int device) {
     if (!ctx) return fail(CA_ERR_INVALID_ARG, "ctx is NULL");
@@ -359,8 +377,9 @@ ca_status_t align_batch(ca_context_t c, const void* z1, const void* z2, const in
     if (num_pairs == 0) return CA_OK;
     if (!z1 || !z2 || !out) return fail(CA_ERR_INVALID_ARG, "z1, z2 and out must be non-NULL");
     if (num_pairs > 0x7fffffffLL) return fail(CA_ERR_INVALID_ARG, "num_pairs exceeds 2^31 - 1");
-    if (!offsets && !smooth7(n))
-        return fail(CA_ERR_UNSUPPORTED_N, "n must be in [2, 4096] with prime factors 2, 3, 5, 7");
+    if (!offsets && (n < 2 || n > CA_MAX_N)) return fail(CA_ERR_UNSUPPORTED_N, "n must be in [2, 4096]");
+    if (!offsets && o.precision == CA_PREC_FP64 && transform_size(n) > kFp64MaxM)
+        return fail(CA_ERR_UNSUPPORTED_N, "FP64 precision takes n with prime factors above 7 only up to 2048");
     if (o.precision == CA_PREC_SPLIT_BF16 && (offsets || n != 128))
         return fail(CA_ERR_UNSUPPORTED_N, "split-BF16 precision needs a uniform batch with n = 128");
     std::lock_guard<std::mutex> lk(c->mu);
@@ -384,7 +403,8 @@ ca_status_t align_batch(ca_context_t c, const void* z1, const void* z2, const in
         a.z2 = z2;
         a.offsets = offsets;
         a.n_uniform = offsets ? 0 : n;
-        a.n_max = offsets ? CA_MAX_N : n;
+        a.m_uniform = offsets ? 0 : transform_size(n);
+        a.m_cap = o.precision == CA_PREC_FP64 ? kFp64MaxM : kMaxM;
         a.num_pairs = num_pairs;
         a.out = out;
         a.plans = c->d_plans;
@@ -418,7 +438,8 @@ ca_status_t align_all_pairs(ca_context_t c, const void* curves, int32_t m, int32
     if (m < 2) return CA_OK;
     if (!curves || !out_upper) return fail(CA_ERR_INVALID_ARG, "curves and out_upper must be non-NULL");
     if (o.precision != CA_PREC_FP32) return fail(CA_ERR_INVALID_ARG, "align_all_pairs is FP32 only");
-    if (!smooth7(n)) return fail(CA_ERR_UNSUPPORTED_N, "unsupported n");
+    if (!ca::allpairs_supported(n))
+        return fail(CA_ERR_UNSUPPORTED_N, "align_all_pairs supports n in {64, 128, 256, 512, 1024}");
     const int64_t npairs = (int64_t)m * (m - 1) / 2;
     if (npairs > 0x7fffffffLL) return fail(CA_ERR_INVALID_ARG, "m*(m-1)/2 exceeds 2^31 - 1");
     std::lock_guard<std::mutex> lk(c->mu);

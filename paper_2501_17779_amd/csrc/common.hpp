@@ -10,6 +10,7 @@
 namespace ca {
 
 constexpr int kMaxN = CA_MAX_N;
+constexpr int kMaxM = 2 * CA_MAX_N;   // largest transform size (zero-padded correlation)
 constexpr int kCandCap = 32;           // FP64 re-scoring candidates per pair
 constexpr double kNearTie = 1e-6;      // relative gap that counts as a near-tie
 // Multiplier of u * log2(n) in the FP32 error bound of |C|:

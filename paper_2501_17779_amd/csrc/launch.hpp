@@ -15,10 +15,11 @@ struct BlkArgs {
     const void* z2;
     const int64_t* offsets;   // device, or nullptr for a uniform batch
     int n_uniform;
-    int n_max;                // largest n the launch must hold in LDS
+    int m_uniform;            // transform size of a uniform batch (n, or the padded size)
+    int m_cap;                // largest transform size this precision supports
     int64_t num_pairs;
     ca_result_t* out;
-    const Plan* plans;        // device table indexed by n
+    const Plan* plans;        // device table indexed by n: the plan of n's transform
     const void* tw_arena;     // device twiddle arena (float2 or double2)
     int rescore;
     int theta64;
@@ -26,7 +27,9 @@ struct BlkArgs {
 };
 
 // Persistent size-class kernels, one pair per workgroup at a time,
-// LDS-resident Stockham FFT, any supported n.
+// LDS-resident Stockham FFT.  A 7-smooth n is transformed at size n; any
+// other n uses the zero-padded correlation at the 7-smooth size M >= 2n of
+// its plan (curve 1 padded with zeros, curve 2 repeated twice).
 hipError_t launch_align_blk_f32(const BlkArgs& a, hipStream_t s);
 hipError_t launch_align_blk_f64(const BlkArgs& a, hipStream_t s);
 
@@ -53,13 +56,15 @@ hipError_t launch_allpairs(const void* curves, const void* spectra, const double
                            hipStream_t s);
 bool allpairs_supported(int n);
 
+// Hand-off records -> (t0*, R*) in the paper's notation.
+hipError_t launch_initializer(const ca_result_t* res, int n, const int64_t* offsets, int64_t count,
+                              double* t0, double* rot, hipStream_t s);
+
 // Arc-length resampling, one workgroup per curve.
 // A wave-per-curve fast kernel handles every curve it can; the others (fewer
 // than 3 vertices, duplicates, non-finite values, above the vertex cap) are
 // listed in slow_list (count in *slow_count, device) and resampled by the
 // general workgroup-per-curve kernel with `slots` scratch slots.
-hipError_t launch_initializer(const ca_result_t* res, int n, const int64_t* offsets, int64_t count,
-                              double* t0, double* rot, hipStream_t s);
 hipError_t launch_resample(const void* raw, const int64_t* raw_off, int64_t num_curves,
                            const int64_t* out_off, void* out, double* norms, uint32_t* flags,
                            int mode, void* scratch, int64_t slot_bytes, int64_t slots,

@@ -289,9 +289,10 @@ def gallery_torch(seed: int, M: int, n_raw: int, device, K: int = 16, A: float =
 
 def ragged_pairs_torch(seed: int, B: int, device, nmin: int = 64, nmax: int = 4096,
                        ratio=(1.2, 5.0), A: float = 0.1, sigma_max: float = 1e-2,
-                       jitter: float = 0.4, chunk: int = 8192):
+                       jitter: float = 0.4, chunk: int = 8192, snap: bool = True):
     """Device version of ragged_pairs.  Returns dict of device tensors:
-    raw1, raw2 complex64 flat; off1, off2 int64 (B+1); n int32 (B)."""
+    raw1, raw2 complex64 flat; off1, off2 int64 (B+1); n int32 (B).
+    snap=False keeps the rounded log-uniform draw (any integer size)."""
     import torch
     gen = torch.Generator(device=device)
     gen.manual_seed(seed)
@@ -299,7 +300,10 @@ def ragged_pairs_torch(seed: int, B: int, device, nmin: int = 64, nmax: int = 40
     logc = torch.log(cand.double())
     draw = torch.rand(B, generator=gen, device=device, dtype=torch.float64)
     draw = math.log(nmin) + draw * (math.log(nmax) - math.log(nmin))
-    N = cand[(logc[None, :] - draw[:, None]).abs().argmin(dim=1)]
+    if snap:
+        N = cand[(logc[None, :] - draw[:, None]).abs().argmin(dim=1)]
+    else:
+        N = torch.clamp(torch.round(torch.exp(draw)), nmin, nmax).long()
     out = {"n": N.to(torch.int32)}
     for which in (1, 2):
         rr = torch.rand(B, generator=gen, device=device, dtype=torch.float64)

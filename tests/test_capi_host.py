@@ -101,19 +101,20 @@ def test_header_layout_matches_binding(tmp_path):
     assert h["max_n"] == ca.MAX_N
 
 
-def _smooth7(n):
+def _expected_support(n):
     if n < 2 or n > ca.MAX_N:
-        return False
+        return 0
+    m = n
     for p in (2, 3, 5, 7):
-        while n % p == 0:
-            n //= p
-    return n == 1
+        while m % p == 0:
+            m //= p
+    return 1 if m == 1 else 2
 
 
 def test_n_supported_predicate(L):
     for n in list(range(-3, ca.MAX_N + 40)) + [2 ** 31 - 1, -(2 ** 31)]:
-        assert L.ca_n_supported(n) == int(_smooth7(n)), n
-    explicit = {1: 0, 2: 1, 11: 0, 840: 1, 2187: 1, 4095: 0, 4096: 1, 4100: 0}   # 4095 = 3^2 5 7 13
+        assert L.ca_n_supported(n) == _expected_support(n), n
+    explicit = {1: 0, 2: 1, 11: 2, 840: 1, 2187: 1, 4093: 2, 4095: 2, 4096: 1, 4100: 0}   # 4095 = 3^2 5 7 13
     for n, want in explicit.items():
         assert L.ca_n_supported(n) == want, n
 
@@ -174,10 +175,14 @@ def test_argument_errors_before_device_work(L):
     assert L.align_batch(ctx, None, p, None, 64, 4, p, None, None) == ca.ERR_INVALID_ARG
     assert L.align_batch(ctx, p, p, None, 64, 4, None, None, None) == ca.ERR_INVALID_ARG
     assert L.align_batch(ctx, p, p, None, 64, 2 ** 31, p, None, None) == ca.ERR_INVALID_ARG
-    for n in (0, 1, 11, 4095, 8192):
+    for n in (0, 1, 4097, 8192):
         assert L.align_batch(ctx, p, p, None, n, 4, p, None, None) == ca.ERR_UNSUPPORTED_N, n
         assert L.align_pair(ctx, p, p, n, p, None, None) == ca.ERR_UNSUPPORTED_N, n
+    for n in (0, 1, 11, 96, 2048, 4095, 8192):
         assert L.align_all_pairs(ctx, p, 8, n, p, None, None) == ca.ERR_UNSUPPORTED_N, n
+    fp64 = _Opts(2, 0, 0, 0)
+    for n in (2053, 4093, 4095):                  # padded size above the FP64 block engine's LDS
+        assert L.align_batch(ctx, p, p, None, n, 4, p, ctypes.byref(fp64), None) == ca.ERR_UNSUPPORTED_N, n
     bf = _Opts(1, 0, 0, 0)
     assert L.align_batch(ctx, p, p, None, 256, 4, p, ctypes.byref(bf), None) == ca.ERR_UNSUPPORTED_N
     assert L.align_batch(ctx, p, p, p, 128, 4, p, ctypes.byref(bf), None) == ca.ERR_UNSUPPORTED_N

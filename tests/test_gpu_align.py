@@ -68,6 +68,37 @@ def test_block_engine_parity(ca, n):
         note(f"n={n} {rescore}: {st}")
 
 
+@pytest.mark.parametrize("n", [11, 13, 97, 143, 1009, 2053, 4093])
+def test_padded_transform_parity(ca, n):
+    """n with a prime factor above 7: zero-padded correlation at M >= 2n."""
+    B = 16 if n >= 2048 else 40
+    if n < 16:
+        rng = np.random.default_rng(n)
+        z1 = (rng.normal(size=(B, n)) + 1j * rng.normal(size=(B, n))).astype(np.complex64)
+        z2 = (rng.normal(size=(B, n)) + 1j * rng.normal(size=(B, n))).astype(np.complex64)
+    else:
+        z1, z2 = inputs.batch(700 + n, B, n)
+    for rescore in ("top2", "window"):
+        res = run_batch(ca, z1, z2, rescore=rescore)
+        st = acc.check_batch(res, z1, z2)
+        note(f"padded n={n} {rescore}: {st}")
+        if rescore == "window":
+            assert st["shift_mismatch"] == 0
+
+
+@pytest.mark.parametrize("n", [11, 97, 1009, 2039])
+def test_padded_transform_fp64(ca, n):
+    z1, z2 = inputs.batch(800 + n, 12, max(n, 16)) if n >= 16 else (None, None)
+    if z1 is None:
+        rng = np.random.default_rng(n)
+        z1 = rng.normal(size=(12, n)) + 1j * rng.normal(size=(12, n))
+        z2 = rng.normal(size=(12, n)) + 1j * rng.normal(size=(12, n))
+    z1, z2 = z1.astype(np.complex128), z2.astype(np.complex128)
+    note(f"align_batch fp64 padded n={n}")
+    res = ca.to_numpy(ca.align_batch(gpu(z1), gpu(z2), precision="fp64"))
+    acc.check_batch(res, z1, z2, theta_tol=1e-10, e_rtol=1e-10)
+
+
 def test_fp64_single_pair(ca):
     """The one-pair workload in FP64 (n = 256)."""
     z1, z2, truth = inputs.single(17779, 256)
@@ -103,7 +134,7 @@ def test_ragged_batch(ca):
 
 def test_ragged_unsupported_sizes_are_flagged(ca):
     rng = np.random.default_rng(3)
-    sizes = [64, 11, 1, 5000, 128]        # 11: prime > 7; 1: too small; 5000: too large
+    sizes = [64, 11, 1, 5000, 128, 4093]   # 11, 4093: padded; 1: too small; 5000: too large
     off = np.zeros(len(sizes) + 1, dtype=np.int64)
     off[1:] = np.cumsum(sizes)
     z1 = (rng.normal(size=off[-1]) + 1j * rng.normal(size=off[-1])).astype(np.complex64)
@@ -111,9 +142,18 @@ def test_ragged_unsupported_sizes_are_flagged(ca):
     note("ragged unsupported sizes")
     res = ca.to_numpy(ca.align_batch(gpu(z1), gpu(z2), offsets=gpu(off)))
     bad = (res["flags"] & ca.FLAG_UNSUPPORTED_N) != 0
-    assert list(bad) == [False, True, True, True, False]
-    for b in (0, 4):
+    assert list(bad) == [False, False, True, True, False, False]
+    for b in (0, 1, 4, 5):
         acc.check_pair(res[b], z1[off[b]:off[b + 1]], z2[off[b]:off[b + 1]])
+    # FP64: a padded transform above 4096 does not fit the block engine's LDS
+    note("ragged fp64 sizes")
+    r64 = ca.to_numpy(ca.align_batch(gpu(z1.astype(np.complex128)), gpu(z2.astype(np.complex128)),
+                                     offsets=gpu(off), precision="fp64"))
+    bad = (r64["flags"] & ca.FLAG_UNSUPPORTED_N) != 0
+    assert list(bad) == [False, False, True, True, False, True]
+    for b in (0, 1, 4):
+        acc.check_pair(r64[b], z1[off[b]:off[b + 1]].astype(np.complex128),
+                       z2[off[b]:off[b + 1]].astype(np.complex128), theta_tol=1e-10, e_rtol=1e-10)
 
 
 @pytest.mark.parametrize("n", [64, 256, 1000, 1024])
@@ -154,9 +194,13 @@ def test_degenerate_and_nonfinite(ca):
 
 
 def test_invalid_arguments(ca):
-    z = gpu(np.zeros((2, 11), np.complex64))
+    z = gpu(np.zeros((2, 4097), np.complex64))
     with pytest.raises(ca.CurveAlignError) as e:
         ca.align_batch(z, z)
+    assert e.value.status == ca.ERR_UNSUPPORTED_N
+    z = gpu(np.zeros((2, 2053), np.complex128))
+    with pytest.raises(ca.CurveAlignError) as e:
+        ca.align_batch(z, z, precision="fp64")
     assert e.value.status == ca.ERR_UNSUPPORTED_N
     z = gpu(np.zeros((0, 64), np.complex64))
     out = ca.align_batch(z, z)        # empty batch: no-op
