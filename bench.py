@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="batch",
-                    choices=["batch", "pair", "allpairs", "ragged", "ragged_any", "bf16", "copy"])
+                    choices=["batch", "pair", "allpairs", "ragged", "ragged_any", "bf16", "srv", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every step from Python instead of replaying a captured HIP graph")
@@ -372,6 +372,43 @@ def bench_small_batch(args, torch, ca):
     return line
 
 
+def bench_srv(args, torch, ca):
+    """The (t0, R) step of the elastic solver on SRV functions (section 4) at
+    the batch workload's size: SRV transform of both curves of 65,536 pairs
+    (n = 1024), then the alignment of (q2, q1), every step."""
+    from synth import curves
+    B, n = 65536, 1024
+    dev = torch.device("cuda:0")
+    r1, r2 = curves.batch_pairs_torch(17780, B, n, dev)
+    raw = torch.view_as_complex(torch.cat([r1, r2]).reshape(-1, 2)).contiguous()
+    roff = torch.arange(0, 2 * B + 1, dtype=torch.int64, device=dev) * n
+    nodes, _, _ = ca.resample_arclength(raw, roff, roff)
+    nodes = nodes.view(2 * B, n)
+    q = torch.empty_like(nodes)
+    out = ca.empty_results(B, dev)
+
+    def srv():
+        ca.srv_transform(nodes, out=q)
+
+    def align():
+        ca.align_batch(q[B:], q[:B], out=out)
+
+    ms, (ms_srv, ms_al) = time_parts([srv, align], args.steps, args.warmup, torch, graph=not args.no_graph)
+    line = base_line(args, B / (ms * 1e-3), "pairs/s", ms, "f32",
+                     {"workload": "SRV (t0, R) step: SRV transform of 65536 curve pairs, n=1024, then "
+                                  "alignment of (q2, q1), FP32, top-2 FP64 re-scoring", "pairs": B, "n": n})
+    line["parts_ms"] = {"srv_transform": ms_srv, "align_batch": ms_al}
+    algo = B * (2 * n * 8 + RESULT_BYTES)
+    achieved = algo / (ms_al * 1e-3) / 1e9
+    line["roofline"] = {"bound": "hbm", "kernel": "k_align_team<1024>", "achieved": achieved,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                        "traffic": traffic_for("k_align_team_1024", sources_digest(ALIGN_SOURCES), B)}
+    srv_gbs = 2 * B * n * 16 / (ms_srv * 1e-3) / 1e9
+    line["srv_roofline"] = {"bound": "hbm", "kernel": "k_srv", "achieved": srv_gbs, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": srv_gbs / HBM_PEAK_GBS}
+    return line
+
+
 def bench_copy(args, torch, ca):
     """A plain device-to-device copy of 1 GiB: the reference reading for the
     rocprofv3 FETCH_SIZE / WRITE_SIZE counters (bytes moved are known)."""
@@ -400,7 +437,7 @@ def main():
     ca.default_context(0)
     fn = {"batch": bench_batch, "copy": bench_copy, "pair": bench_pair, "allpairs": bench_allpairs,
           "ragged": bench_ragged, "ragged_any": lambda a, t, c: bench_ragged(a, t, c, snap=False),
-          "bf16": bench_small_batch}[args.config]
+          "bf16": bench_small_batch, "srv": bench_srv}[args.config]
     line = fn(args, torch, ca)
     print(json.dumps(line), flush=True)
 

@@ -211,6 +211,26 @@ ca_status_t to_initializer(ca_context_t ctx, const ca_result_t* results, int32_t
                            const int64_t* offsets, int64_t count, double* t0_out, double* rot_out,
                            void* stream);
 
+/*
+ * srv_transform -- square-root-velocity function of section 4,
+ * q = beta' / |beta'|^(1/2), for curves given as n nodes at the uniform
+ * parameters t_k = k / n.  The curve is read as the closed polygon through
+ * its nodes, so q is piecewise constant on the segments:
+ *     q_k = d_k / |d_k|^(1/2),  d_k = n (z[k+1 mod n] - z[k]),
+ * and q_k = 0 on a segment of zero length.  (1/n) sum |q_k|^2 is the
+ * polygon's length.  FP32 (complex64) in and out.
+ *   curves  : nodes, complex64 (device); uniform [count][n] or ragged flat
+ *   offsets : int64 [count+1] node offsets of a ragged set (device), or NULL
+ *   n       : nodes per curve (>= 2) when offsets is NULL, else 0
+ *   q_out   : complex64, same layout and size as curves (device)
+ * With the SRV functions of two curves on the same grid, the (t0, R) step of
+ * Eq. (dist2-energy), the integral of |R q1(t + t0) - q2*(t)|^2, is
+ * align_batch on (z1 = q2*, z2 = q1) followed by to_initializer.
+ * count = 0 is a no-op.
+ */
+ca_status_t srv_transform(ca_context_t ctx, const void* curves, const int64_t* offsets, int32_t n,
+                          int64_t count, void* q_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -45,7 +45,8 @@ RESAMPLE = {"spline": 0, "linear": 1}
 MAX_N = 4096
 
 EXPORTED = ("ca_create", "ca_destroy", "ca_status_string", "ca_last_error", "ca_n_supported",
-            "align_pair", "align_batch", "align_all_pairs", "resample_arclength", "to_initializer")
+            "align_pair", "align_batch", "align_all_pairs", "resample_arclength", "to_initializer",
+            "srv_transform")
 
 
 class CurveAlignError(RuntimeError):
@@ -88,8 +89,9 @@ def lib():
             L.align_all_pairs.argtypes = [vp, vp, i32, i32, vp, vp, vp]
             L.resample_arclength.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, i32, vp]
             L.to_initializer.argtypes = [vp, vp, i32, vp, i64, vp, vp, vp]
+            L.srv_transform.argtypes = [vp, vp, vp, i32, i64, vp, vp]
             for name in ("ca_create", "ca_destroy", "align_pair", "align_batch",
-                         "align_all_pairs", "resample_arclength", "to_initializer"):
+                         "align_all_pairs", "resample_arclength", "to_initializer", "srv_transform"):
                 getattr(L, name).restype = i32
             _lib = L
     return _lib
@@ -266,6 +268,29 @@ def to_initializer(results, n=None, offsets=None, *, stream=None, ctx=None):
                                 None if offsets is None else offsets.data_ptr(), count,
                                 t0.data_ptr(), rot.data_ptr(), _stream_ptr(stream)))
     return t0, rot
+
+
+def srv_transform(curves, offsets=None, *, out=None, stream=None, ctx=None):
+    """Square-root-velocity values q_k of closed polygons (section 4).
+
+    Uniform: curves complex64 [count, n].  Ragged: curves flat complex64 with
+    int64 `offsets` [count+1].  Returns q with the layout of `curves`."""
+    import torch
+    _require(curves, "curves", (torch.complex64,))
+    if offsets is None:
+        if curves.dim() != 2:
+            raise ValueError("uniform curves are [count, n]")
+        count, n, off_ptr = curves.shape[0], curves.shape[1], None
+    else:
+        _require(offsets, "offsets", (torch.int64,), 1)
+        if curves.dim() != 1:
+            raise ValueError("ragged curves are flat")
+        count, n, off_ptr = offsets.shape[0] - 1, 0, offsets.data_ptr()
+    ctx = ctx or default_context(curves.device.index)
+    out = torch.empty_like(curves) if out is None else out
+    _check(lib().srv_transform(ctx.handle, curves.data_ptr(), off_ptr, n, count, out.data_ptr(),
+                               _stream_ptr(stream)))
+    return out
 
 
 def resample_arclength(raw, raw_offsets, out_offsets, *, mode="spline", with_norms=True,

@@ -527,4 +527,18 @@ ca_status_t to_initializer(ca_context_t c, const ca_result_t* results, int32_t n
     return CA_OK;
 }
 
+ca_status_t srv_transform(ca_context_t c, const void* curves, const int64_t* offsets, int32_t n,
+                          int64_t count, void* q_out, void* stream) {
+    if (!c) return fail(CA_ERR_INVALID_ARG, "context is NULL");
+    if (count < 0) return fail(CA_ERR_INVALID_ARG, "count < 0");
+    if (!offsets && n < 2) return fail(CA_ERR_INVALID_ARG, "n must be >= 2 without offsets");
+    if (offsets && n != 0) return fail(CA_ERR_INVALID_ARG, "n must be 0 when offsets are given");
+    if (count == 0) return CA_OK;
+    if (!curves || !q_out) return fail(CA_ERR_INVALID_ARG, "curves and q_out must be non-NULL");
+    DeviceGuard g(c->device);
+    const hipError_t e = ca::launch_srv(curves, offsets, n, count, q_out, c->num_cus, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "SRV kernel launch");
+    return CA_OK;
+}
+
 }  // extern "C"

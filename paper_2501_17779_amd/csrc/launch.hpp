@@ -60,6 +60,10 @@ bool allpairs_supported(int n);
 hipError_t launch_initializer(const ca_result_t* res, int n, const int64_t* offsets, int64_t count,
                               double* t0, double* rot, hipStream_t s);
 
+// Square-root-velocity transform (section 4), one wave per curve.
+hipError_t launch_srv(const void* z, const int64_t* offsets, int n, int64_t count, void* q, int num_cus,
+                      hipStream_t s);
+
 // Arc-length resampling, one workgroup per curve.
 // A wave-per-curve fast kernel handles every curve it can; the others (fewer
 // than 3 vertices, duplicates, non-finite values, above the vertex cap) are

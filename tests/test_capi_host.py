@@ -140,6 +140,7 @@ def test_null_context_is_rejected_on_host(L):
     assert L.align_all_pairs(None, dummy, 8, 64, dummy, None, None) == ca.ERR_INVALID_ARG
     assert L.resample_arclength(None, dummy, dummy, 4, dummy, dummy, None, None, 0, None) == ca.ERR_INVALID_ARG
     assert L.to_initializer(None, dummy, 64, None, 4, dummy, dummy, None) == ca.ERR_INVALID_ARG
+    assert L.srv_transform(None, dummy, None, 64, 4, dummy, None) == ca.ERR_INVALID_ARG
     assert L.ca_create(None, 0) == ca.ERR_INVALID_ARG
     assert L.ca_destroy(None) == ca.OK
 
@@ -200,7 +201,13 @@ def test_argument_errors_before_device_work(L):
     assert L.to_initializer(ctx, p, 64, p, 4, p, p, None) == ca.ERR_INVALID_ARG
     assert L.to_initializer(ctx, p, 64, None, 4, None, p, None) == ca.ERR_INVALID_ARG
     assert L.to_initializer(ctx, p, 64, None, 4, p, None, None) == ca.ERR_INVALID_ARG
+    assert L.srv_transform(ctx, p, None, 64, -1, p, None) == ca.ERR_INVALID_ARG
+    assert L.srv_transform(ctx, p, None, 1, 4, p, None) == ca.ERR_INVALID_ARG
+    assert L.srv_transform(ctx, p, p, 64, 4, p, None) == ca.ERR_INVALID_ARG
+    assert L.srv_transform(ctx, None, None, 64, 4, p, None) == ca.ERR_INVALID_ARG
+    assert L.srv_transform(ctx, p, None, 64, 4, None, None) == ca.ERR_INVALID_ARG
     # empty work is a no-op that touches nothing
+    assert L.srv_transform(ctx, None, None, 64, 0, None, None) == ca.OK
     assert L.to_initializer(ctx, None, 64, None, 0, None, None, None) == ca.OK
     assert L.align_batch(ctx, None, None, None, 64, 0, None, None, None) == ca.OK
     assert L.align_all_pairs(ctx, None, 1, 64, None, None, None) == ca.OK
