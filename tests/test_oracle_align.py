@@ -308,3 +308,23 @@ def test_initializer_reproduces_curve_in_matrix_form(n, m0, theta0):
     back = np.stack([R @ b2[(l + round(t0 * n)) % n] for l in range(n)])
     assert np.max(np.abs(back - b1)) < 1e-12
     assert res["E"] < 1e-24
+
+
+@pytest.mark.parametrize("n", [11, 97, 250, 1009])
+def test_zero_padded_correlation_identity(n):
+    """The identity behind sizes with a prime factor above 7: for M >= 2n,
+    a = z1 then zeros, b = (z2, z2) then zeros, the length-M transform of
+    conj(A) B holds M conj(C(s)) at index M - n + s, with C the correlation
+    whose magnitude and angle the slow method reports at every shift."""
+    rng = np.random.default_rng(n)
+    z1, z2 = random_curve(rng, n), random_curve(rng, n)
+    M = 2 * n + 3                              # any length >= 2n works
+    a = np.zeros(M, complex)
+    b = np.zeros(M, complex)
+    a[:n] = z1
+    b[:2 * n] = np.concatenate([z2, z2])
+    D = np.fft.fft(np.conj(np.fft.fft(a)) * np.fft.fft(b))
+    C = np.conj(D[M - n:]) / M
+    T, th, _, _ = oracle.per_shift_arrays(z1, z2)
+    assert np.max(np.abs(np.abs(C) - T)) < 1e-12 * np.max(T)
+    assert np.max(np.abs(oracle.wrap_angle(np.angle(C) - th))) < 1e-9
