@@ -285,10 +285,9 @@ hipError_t launch_allpairs(const void* curves, const void* spec, const double* n
 
 // -------------------------------------------------------------- block engine
 // Persistent kernels, one pair per workgroup at a time; each launch serves
-// the pairs whose transform size lies in [mlo, mhi] (a size class) with NT
-// threads and LDS for MMAX values per signal.  Pairs that no class can take
-// (n outside [2, kMaxN], transform larger than mcap) are flagged by the class
-// that has mlo == 0.
+// one size class of transform sizes with NT threads and LDS for MMAX values
+// per signal: a whole uniform batch, or the list that k_blk_bin built for the
+// class in a ragged batch.
 //
 // A 7-smooth n is transformed at size M = n.  Any other n uses the plan's
 // 7-smooth M >= 2n: with a = z1 followed by zeros and b = (z2, z2, zeros),
@@ -296,39 +295,74 @@ hipError_t launch_allpairs(const void* curves, const void* spec, const double* n
 // M - n + s, 0 <= s < n, where it equals C(s) = sum_k z1[k] conj(z2[k - s])
 // (indices mod n).  The forward transform of conj(A) B then gives
 // D[M - n + s] = M conj(C(s)).
+// Size class of a transform size (the launch order of launch_blk).
+__device__ __forceinline__ int blk_class(int M) {
+    return M <= 512 ? 0 : M <= 1024 ? 1 : M <= 2048 ? 2 : M <= 4096 ? 3 : 4;
+}
+
+__global__ void k_zero_ints(int* p, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+
+// Ragged batches: every pair goes to the list of its size class (wave-
+// aggregated atomics; the order inside a list does not affect any result);
+// pairs that no class can take get their CA_FLAG_UNSUPPORTED_N record here.
+__global__ __launch_bounds__(256) void k_blk_bin(const int64_t* __restrict__ offsets, int64_t num_pairs,
+                                                 const Plan* __restrict__ plans, int mcap, int* __restrict__ bins,
+                                                 ca_result_t* __restrict__ out) {
+    const int64_t pair = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int cls = -1;
+    if (pair < num_pairs) {
+        const int64_t len = offsets[pair + 1] - offsets[pair];
+        const int n = (len >= 2 && len <= kMaxN) ? (int)len : 0;
+        const int M = n ? plans[n].n : 0;
+        if (M == 0 || M > mcap) {
+            ca_result_t r;
+            r.shift = 0; r.flags = CA_FLAG_UNSUPPORTED_N; r.theta = 0.0; r.err_est = 0.0f; r.gap = 0.0f;
+            r.e0 = __builtin_nan("");
+            out[pair] = r;
+        } else {
+            cls = blk_class(M);
+        }
+    }
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int c = 0; c < kBlkClasses; ++c) {
+        const uint64_t mask = __ballot(cls == c);
+        if (mask == 0ull) continue;
+        const int leader = __ffsll((long long)mask) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&bins[c], __popcll(mask));
+        base = __shfl(base, leader, 64);
+        if (cls == c) bins[kBlkClasses + c * num_pairs + base + __popcll(mask & below)] = (int)pair;
+    }
+}
+
 template <typename T, int NT, int MMAX>
 __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1, const cpx<T>* __restrict__ z2,
                                                   const int64_t* __restrict__ offsets, int n_uniform,
                                                   int64_t num_pairs, ca_result_t* __restrict__ out,
                                                   const Plan* __restrict__ plans,
                                                   const cpx<T>* __restrict__ arena, int rescore, int theta64,
-                                                  int mlo, int mhi, int mcap) {
+                                                  const int* __restrict__ list_count, const int* __restrict__ list) {
     __shared__ cpx<T> A[MMAX];
     __shared__ cpx<T> B[MMAX];
     __shared__ double red[2 * (NT / 64)];
     __shared__ int clist[kCandCap + 1];
-    for (int64_t pair = blockIdx.x; pair < num_pairs; pair += gridDim.x) {
+    const int64_t todo = list ? (int64_t)*list_count : num_pairs;
+    for (int64_t it = blockIdx.x; it < todo; it += gridDim.x) {
+        const int64_t pair = list ? (int64_t)list[it] : it;
         int64_t off;
         int n;
         if (offsets) {
             off = offsets[pair];
-            const int64_t len = offsets[pair + 1] - off;
-            n = (len >= 2 && len <= kMaxN) ? (int)len : 0;
+            n = (int)(offsets[pair + 1] - off);
         } else {
             off = pair * (int64_t)n_uniform;
             n = n_uniform;
         }
-        const int M = n ? plans[n].n : 0;
-        if (M == 0 || M > mcap) {
-            if (mlo == 0 && threadIdx.x == 0) {
-                ca_result_t r;
-                r.shift = 0; r.flags = CA_FLAG_UNSUPPORTED_N; r.theta = 0.0; r.err_est = 0.0f; r.gap = 0.0f;
-                r.e0 = __builtin_nan("");
-                out[pair] = r;
-            }
-            continue;
-        }
-        if (M < mlo || M > mhi) continue;
+        const int M = plans[n].n;
         const Plan& p = plans[n];
         const cpx<T>* tw = arena + p.tw_off;
         const cpx<T>* pa = z1 + off;
@@ -430,7 +464,7 @@ __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1,
 
 
 template <typename T, int NT, int MMAX>
-static hipError_t launch_blk_class(const BlkArgs& a, int mlo, int mhi, hipStream_t s) {
+static hipError_t launch_blk_class(const BlkArgs& a, int cls, hipStream_t s) {
     static int per_cu = -1;
     if (per_cu < 0) {
         int nb = 0;
@@ -441,24 +475,33 @@ static hipError_t launch_blk_class(const BlkArgs& a, int mlo, int mhi, hipStream
     }
     int64_t grid = (int64_t)a.num_cus * per_cu;
     if (grid > a.num_pairs) grid = a.num_pairs;
+    const int* count = a.offsets ? a.bins + cls : nullptr;
+    const int* list = a.offsets ? a.bins + kBlkClasses + cls * a.num_pairs : nullptr;
     hipLaunchKernelGGL((k_align_blk<T, NT, MMAX>), dim3((unsigned)grid), dim3(NT), 0, s,
                        (const cpx<T>*)a.z1, (const cpx<T>*)a.z2, a.offsets, a.n_uniform, a.num_pairs, a.out,
-                       a.plans, (const cpx<T>*)a.tw_arena, a.rescore, a.theta64, mlo, mhi, a.m_cap);
+                       a.plans, (const cpx<T>*)a.tw_arena, a.rescore, a.theta64, count, list);
     return hipGetLastError();
 }
 
 // Size classes by transform size: (64 threads, M <= 512), (128, <= 1024),
-// (256, <= 2048), (256, <= 4096) and, FP32 only, (256, <= 8192).
+// (256, <= 2048), (256, <= 4096) and, FP32 only, (256, <= 8192).  A uniform
+// batch launches its one class; a ragged batch is binned on the device first.
 template <typename T>
 static hipError_t launch_blk(const BlkArgs& a, hipStream_t s) {
     const int lo = a.offsets ? 0 : a.m_uniform, hi = a.offsets ? a.m_cap : a.m_uniform;
     hipError_t e = hipSuccess;
-    if (lo <= 512 && e == hipSuccess) e = launch_blk_class<T, 64, 512>(a, lo, 512, s);
-    if (hi > 512 && lo <= 1024 && e == hipSuccess) e = launch_blk_class<T, 128, 1024>(a, 513, 1024, s);
-    if (hi > 1024 && lo <= 2048 && e == hipSuccess) e = launch_blk_class<T, 256, 2048>(a, 1025, 2048, s);
-    if (hi > 2048 && lo <= 4096 && e == hipSuccess) e = launch_blk_class<T, 256, 4096>(a, 2049, 4096, s);
+    if (a.offsets) {
+        hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, s, a.bins, kBlkClasses);
+        hipLaunchKernelGGL(k_blk_bin, dim3((unsigned)((a.num_pairs + 255) / 256)), dim3(256), 0, s, a.offsets,
+                           a.num_pairs, a.plans, a.m_cap, a.bins, a.out);
+        e = hipGetLastError();
+    }
+    if (lo <= 512 && e == hipSuccess) e = launch_blk_class<T, 64, 512>(a, 0, s);
+    if (hi > 512 && lo <= 1024 && e == hipSuccess) e = launch_blk_class<T, 128, 1024>(a, 1, s);
+    if (hi > 1024 && lo <= 2048 && e == hipSuccess) e = launch_blk_class<T, 256, 2048>(a, 2, s);
+    if (hi > 2048 && lo <= 4096 && e == hipSuccess) e = launch_blk_class<T, 256, 4096>(a, 3, s);
     if constexpr (sizeof(T) == 4) {
-        if (hi > 4096 && e == hipSuccess) e = launch_blk_class<T, 256, 8192>(a, 4097, 8192, s);
+        if (hi > 4096 && e == hipSuccess) e = launch_blk_class<T, 256, 8192>(a, 4, s);
     }
     return e;
 }

@@ -101,6 +101,9 @@ struct ca_context {
     int64_t rs_slots = 0;
     int* d_slow = nullptr;          // [0] = count, [1..] = curve indices
     int64_t slow_cap = 0;
+    // block-engine size-class lists of ragged batches
+    int* d_bins = nullptr;
+    int64_t bins_cap = 0;           // pairs
     // all-pairs spectra workspace
     void* d_spec = nullptr;
     size_t spec_bytes = 0;
@@ -359,6 +362,7 @@ ca_status_t ca_destroy(ca_context_t c) {
         if (c->d_bf16) (void)hipFree(c->d_bf16);
         if (c->d_rs) (void)hipFree(c->d_rs);
         if (c->d_slow) (void)hipFree(c->d_slow);
+        if (c->d_bins) (void)hipFree(c->d_bins);
         if (c->d_spec) (void)hipFree(c->d_spec);
         if (c->d_norms) (void)hipFree(c->d_norms);
     }
@@ -411,6 +415,18 @@ ca_status_t align_batch(ca_context_t c, const void* z1, const void* z2, const in
         a.rescore = o.rescore;
         a.theta64 = o.theta_fp64;
         a.num_cus = c->num_cus;
+        a.bins = nullptr;
+        if (offsets) {
+            if (num_pairs > c->bins_cap) {
+                if (c->d_bins) (void)hipFree(c->d_bins);
+                c->d_bins = nullptr;
+                c->bins_cap = 0;
+                if (hipMalloc(&c->d_bins, (size_t)ca::blk_bin_ints(num_pairs) * sizeof(int)) != hipSuccess)
+                    return fail(CA_ERR_OOM, "size-class lists");
+                c->bins_cap = num_pairs;
+            }
+            a.bins = c->d_bins;
+        }
         if (o.precision == CA_PREC_FP64) {
             a.tw_arena = c->d_tw64;
             e = ca::launch_align_blk_f64(a, s);

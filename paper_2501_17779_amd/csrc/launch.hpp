@@ -24,7 +24,13 @@ struct BlkArgs {
     int rescore;
     int theta64;
     int num_cus;
+    // ragged batches: device workspace of kBlkClasses counters followed by
+    // kBlkClasses lists of num_pairs pair indices (blk_bin_ints(num_pairs) ints)
+    int* bins;
 };
+
+constexpr int kBlkClasses = 5;
+inline int64_t blk_bin_ints(int64_t num_pairs) { return kBlkClasses + kBlkClasses * num_pairs; }
 
 // Persistent size-class kernels, one pair per workgroup at a time,
 // LDS-resident Stockham FFT.  A 7-smooth n is transformed at size n; any
