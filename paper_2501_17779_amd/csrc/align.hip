@@ -118,8 +118,12 @@ __global__ __launch_bounds__(256, TeamCfg<N>::AW) void k_allpairs(const cf* __re
     constexpr int PADN = team_padn<N>();
     constexpr int PER = (N + 255) / 256;
     __shared__ cf tws[TeamCfg<N>::TW];
+    // column nodes: twice (shifted reads at constant offsets) where two
+    // blocks per CU still fit in LDS, else once in the padded layout
+    constexpr int ZL = N <= 512 ? kZTwice : kZPad;
+    constexpr int ZS = ZL == kZTwice ? 2 * N : PADN;
     __shared__ cf sZ[2][N];
-    __shared__ cf sz[2][PADN];
+    __shared__ cf sz[2][ZS];
     __shared__ cf xbuf[TEAMS * PADN];
     __shared__ int cand_all[TEAMS * kCandCap];
     const int i0 = blockIdx.y * TEAMS;
@@ -161,7 +165,12 @@ __global__ __launch_bounds__(256, TeamCfg<N>::AW) void k_allpairs(const cf* __re
             const int k = threadIdx.x + 256 * p;
             if (k < N) {
                 sZ[b][k] = gZ[p];
-                sz[b][lpad<N>(k)] = gz[p];
+                if constexpr (ZL == kZTwice) {
+                    sz[b][k] = gz[p];
+                    sz[b][N + k] = gz[p];
+                } else {
+                    sz[b][lpad<N>(k)] = gz[p];
+                }
             }
         }
     };
@@ -178,7 +187,8 @@ __global__ __launch_bounds__(256, TeamCfg<N>::AW) void k_allpairs(const cf* __re
 #pragma unroll
             for (int q = 0; q < R; ++q) v[q] = cjmul(Zi[q], sZ[cur][t + T * q]);
             team_fft<N, T>(v, lds, tws, t);
-            const ca_result_t res = team_epilogue<N, T>(v, zi, sz[cur], cand, t, ni, norms[j], rescore, theta64);
+            const ca_result_t res =
+                team_epilogue<N, T, ZL>(v, zi, sz[cur], cand, t, ni, norms[j], rescore, theta64);
             if (t == 0) {
                 const int64_t k = (int64_t)i * m - (int64_t)i * (i + 1) / 2 + (j - i - 1);
                 out[k] = res;
