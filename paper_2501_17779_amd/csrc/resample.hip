@@ -389,25 +389,37 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
     bool general = (mraw < 3 || mraw > kRsMCap || N < 1);
     const int M = general ? 0 : (int)mraw;
 
-    // pass 1: perimeter, duplicates, non-finite values (four vertices per
-    // lane per iteration, loads issued together)
+    // pass 1: perimeter, duplicates, non-finite values.  Eight vertices per
+    // lane per iteration, loads issued together; the successor of vertex j
+    // comes from the next lane (lane 63: the first lane of the next group),
+    // so only the vertex after the 512-vertex window is loaded twice.  The
+    // per-lane order of the chord sum is j = lane, lane + 64, ...
     double Ls = 0.0;
     int bad = 0;
-    for (int j0 = 0; j0 < M; j0 += 256) {
-        cf a[4], b[4];
+    constexpr int kP1 = 8;
+    const cf p0 = M > 0 ? P[0] : cf{0.0f, 0.0f};
+    for (int j0 = 0; j0 < M; j0 += 64 * kP1) {
+        cf a[kP1 + 1];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kP1; ++u) {
             const int j = j0 + lane + 64 * u;
-            if (j < M) {
-                a[u] = P[j];
-                b[u] = P[j + 1 < M ? j + 1 : 0];
-            }
+            a[u] = P[j < M ? j : 0];
         }
+        a[kP1] = P[j0 + 64 * kP1 < M ? j0 + 64 * kP1 : 0];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kP1; ++u) {
             const int j = j0 + lane + 64 * u;
+            cf b;
+            b.x = __shfl(a[u].x, (lane + 1) & 63, 64);
+            b.y = __shfl(a[u].y, (lane + 1) & 63, 64);
+            const float nx = rdlane(a[u + 1].x, 0), ny = rdlane(a[u + 1].y, 0);
+            if (lane == 63) {
+                b.x = nx;
+                b.y = ny;
+            }
+            if (j + 1 == M) b = p0;            // closing chord back to vertex 0
             if (j < M) {
-                const float dx = b[u].x - a[u].x, dy = b[u].y - a[u].y;
+                const float dx = b.x - a[u].x, dy = b.y - a[u].y;
                 const float h = sqrtf(dx * dx + dy * dy);
                 if (!(h > 0.0f) || !isfinite(h)) bad = 1;
                 Ls += (double)h;
