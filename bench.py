@@ -405,7 +405,8 @@ def bench_srv(args, torch, ca):
                         "traffic": traffic_for("k_align_team_1024", sources_digest(ALIGN_SOURCES), B)}
     srv_gbs = 2 * B * n * 16 / (ms_srv * 1e-3) / 1e9
     line["srv_roofline"] = {"bound": "hbm", "kernel": "k_srv", "achieved": srv_gbs, "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": srv_gbs / HBM_PEAK_GBS}
+                            "unit": "GB/s", "frac": srv_gbs / HBM_PEAK_GBS,
+                            "traffic": traffic_for("k_srv", sources_digest(["srv.hip", "common.hpp"]), 2 * B * n)}
     return line
 
 

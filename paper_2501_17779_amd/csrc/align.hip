@@ -464,7 +464,7 @@ __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1,
                 if (d1 - d2 < 2.0 * epsD) rescore_one(ci);
             }
             const cpx<T> sel = A[base + pk.shift];
-            const double thp = wrap_pi(atan2(-(double)sel.y, (double)sel.x));
+            const double thp = wrap_pi(atan2_fp64(-(double)sel.y, (double)sel.x));
             finish(res, pk, n, n1, n2, d1, d2, epsD, capped, thp, theta64);
         }
         if (threadIdx.x == 0) out[pair] = res;

@@ -35,6 +35,11 @@ __device__ __forceinline__ double wrap_pi(double a) {
     return (a <= -pi) ? pi : a;
 }
 
+// FP64 arc tangent for the opt-in FP64 theta, kept out of line: inlined, its
+// polynomial constants are hoisted into registers for the whole persistent
+// loop (and spilled), although only pairs with theta_fp64 set use them.
+__device__ __attribute__((noinline)) double atan2_fp64(double y, double x) { return atan2(y, x); }
+
 __device__ __forceinline__ void finish(ca_result_t& res, const Pick& pk, int n, double n1, double n2,
                                        double d1, double d2, double epsD, bool capped,
                                        double theta_path, int theta64) {
@@ -53,7 +58,7 @@ __device__ __forceinline__ void finish(ca_result_t& res, const Pick& pk, int n, 
     if (gap < kNearTie) flags |= CA_FLAG_NEAR_TIE;
     double th = theta_path;
     if (theta64) {
-        th = wrap_pi(atan2(pk.im, pk.re));
+        th = wrap_pi(atan2_fp64(pk.im, pk.re));
         flags |= CA_FLAG_THETA_FP64;
     }
     res.shift = pk.shift;
