@@ -127,24 +127,30 @@ def time_parts(fns, steps, warmup, torch, graph=False):
     return ev[0].elapsed_time(ev[steps * k]) / steps, parts
 
 
-def cpu_baseline_batch(raw1, raw2, n, seconds):
+def cpu_baseline_batch(get_pairs, total, n, seconds, what="first {k} of the workload's pairs"):
     """The FP64 oracle (slow method, OpenMP over pairs) on a bounded sample of
-    the workload's pairs; the oracle's cost does not depend on the node values,
-    so the sample uses the raw n-vertex node lists of the first pairs."""
+    the workload's pairs: the sample grows until one run takes `seconds` (or
+    covers all `total` pairs), and that run is reported.  get_pairs(k) returns
+    the first k pairs as float32 (k, n, 2) arrays; the oracle's cost does not
+    depend on the node values."""
     import oracle
-    z1 = (raw1[..., 0] + 1j * raw1[..., 1]).astype(np.complex64)
-    z2 = (raw2[..., 0] + 1j * raw2[..., 1]).astype(np.complex64)
-    probe = min(64, len(z1))
-    t0 = time.perf_counter()
-    _, _, _, _, used = oracle.align_batch_f32(z1[:probe], z2[:probe])
-    dt = time.perf_counter() - t0
-    k = int(min(len(z1), max(probe, probe * seconds / max(dt, 1e-6))))
-    t0 = time.perf_counter()
-    _, _, _, _, used = oracle.align_batch_f32(z1[:k], z2[:k])
-    dt = time.perf_counter() - t0
+
+    def zs(k):
+        a, b = get_pairs(k)
+        return ((a[..., 0] + 1j * a[..., 1]).astype(np.complex64),
+                (b[..., 0] + 1j * b[..., 1]).astype(np.complex64))
+
+    k = min(64, total)
+    while True:
+        z1, z2 = zs(k)
+        t0 = time.perf_counter()
+        _, _, _, _, used = oracle.align_batch_f32(z1, z2)
+        dt = time.perf_counter() - t0
+        if dt >= seconds or k >= total:
+            break
+        k = int(min(total, max(2 * k, 1.1 * k * seconds / max(dt, 1e-6))))
     return {"value": k / dt, "unit": "pairs/s", "cores": int(used), "kind": "oracle",
-            "sample": f"first {k} of the workload's pairs (n={n}), FP64 slow method, "
-                      f"{dt:.1f} s wall on {used} threads"}
+            "sample": what.format(k=k) + f" (n={n}), FP64 slow method, {dt:.1f} s wall on {used} threads"}
 
 
 def bench_batch(args, torch, ca):
@@ -176,8 +182,7 @@ def bench_batch(args, torch, ca):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
     }
     if not args.no_cpu_baseline:
-        k = min(B, 8192)
-        line["cpu_baseline"] = cpu_baseline_batch(r1[:k].cpu().numpy(), r2[:k].cpu().numpy(), n,
+        line["cpu_baseline"] = cpu_baseline_batch(lambda k: (r1[:k].cpu().numpy(), r2[:k].cpu().numpy()), B, n,
                                                   args.cpu_seconds)
         line["accuracy"] = accuracy_sample(torch, ca, r1[:128].cpu().numpy(), r2[:128].cpu().numpy(), n,
                                            ["fp32"], k=128)
@@ -246,13 +251,15 @@ def bench_allpairs(args, torch, ca):
                         "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": achieved / VALU_FP32_PEAK_TFLOPS, "traffic": traffic}
     if not args.no_cpu_baseline:
-        gh = g[:256].cpu().numpy()
-        ii, jj = np.triu_indices(256, 1)
-        k = min(len(ii), 8192)
-        cb = cpu_baseline_batch(np.stack([gh[ii[:k]].real, gh[ii[:k]].imag], -1),
-                                np.stack([gh[jj[:k]].real, gh[jj[:k]].imag], -1), n, args.cpu_seconds)
-        cb["sample"] = "pairs among the first 256 gallery curves; " + cb["sample"]
-        line["cpu_baseline"] = cb
+        gh = g.cpu().numpy()
+        ii, jj = np.triu_indices(M, 1)
+
+        def pairs(k):
+            return (np.stack([gh[ii[:k]].real, gh[ii[:k]].imag], -1),
+                    np.stack([gh[jj[:k]].real, gh[jj[:k]].imag], -1))
+
+        line["cpu_baseline"] = cpu_baseline_batch(pairs, P, n, args.cpu_seconds,
+                                                  "first {k} pairs of the gallery in upper-triangle order")
     return line
 
 
@@ -364,8 +371,7 @@ def bench_small_batch(args, torch, ca):
     line["roofline"] = {"bound": "mfma", "kernel": "k_align_bf16", "achieved": achieved, "peak": 2500.0,
                         "unit": "TFLOP/s", "frac": achieved / 2500.0, "traffic": traffic}
     if not args.no_cpu_baseline:
-        k = 4096
-        line["cpu_baseline"] = cpu_baseline_batch(r1[:k].cpu().numpy(), r2[:k].cpu().numpy(), n,
+        line["cpu_baseline"] = cpu_baseline_batch(lambda k: (r1[:k].cpu().numpy(), r2[:k].cpu().numpy()), B, n,
                                                   args.cpu_seconds)
         line["accuracy"] = accuracy_sample(torch, ca, r1[:256].cpu().numpy(), r2[:256].cpu().numpy(), n,
                                            ["fp32", "split_bf16"])
