@@ -67,6 +67,25 @@ void make_plan(int n, Plan& p) {
     p.npass = k;
 }
 
+// Per-pass twiddles of the block-engine plan p (layout in fft_engines.hpp):
+// pass i, radix R, stride ns: w_{ns R}^{r k} = w_n^{r k n / (ns R)}.
+void plan_twiddles(const Plan& p, const std::vector<double>& re, const std::vector<double>& im,
+                   std::vector<double>& pre, std::vector<double>& pim) {
+    pre.clear();
+    pim.clear();
+    int ns = 1;
+    for (int i = 0; i < p.npass; ++i) {
+        const int R = p.radix[i];
+        const int stride = p.n / (ns * R);
+        for (int r = 1; r < R; ++r)
+            for (int k = 0; k < ns; ++k) {
+                pre.push_back(re[(size_t)r * k * stride]);
+                pim.push_back(im[(size_t)r * k * stride]);
+            }
+        ns *= R;
+    }
+}
+
 // w_n^m = exp(-2 pi i m / n), computed in long double and rounded once.
 void twiddles(int n, std::vector<double>& re, std::vector<double>& im) {
     re.resize(n);
@@ -130,16 +149,19 @@ ca_status_t ensure_tables(ca_context* c, bool need64) {
         std::vector<float> arena32;
         std::vector<int64_t> tw_off(kMaxM + 1, -1);
         int64_t off = 0;
-        std::vector<double> re, im;
+        std::vector<double> re, im, pre, pim;
+        Plan pm;
         for (int m = 2; m <= kMaxM; ++m) {
             if (!smooth7_size(m)) continue;
             tw_off[m] = off;
             twiddles(m, re, im);
-            for (int k = 0; k < m; ++k) {
-                arena32.push_back((float)re[k]);
-                arena32.push_back((float)im[k]);
+            make_plan(m, pm);
+            plan_twiddles(pm, re, im, pre, pim);
+            for (size_t k = 0; k < pre.size(); ++k) {
+                arena32.push_back((float)pre[k]);
+                arena32.push_back((float)pim[k]);
             }
-            off += m;
+            off += (int64_t)pre.size();
         }
         for (int n = 2; n <= CA_MAX_N; ++n) {
             const int M = transform_size(n);
@@ -159,13 +181,16 @@ ca_status_t ensure_tables(ca_context* c, bool need64) {
             return hip_fail(e, "twiddle upload");
     }
     if (need64 && !c->d_tw64) {
-        std::vector<double> arena64, re, im;
+        std::vector<double> arena64, re, im, pre, pim;
+        Plan pm;
         for (int m = 2; m <= kMaxM; ++m) {      // same order and offsets as the FP32 arena
             if (!smooth7_size(m)) continue;
             twiddles(m, re, im);
-            for (int k = 0; k < m; ++k) {
-                arena64.push_back(re[k]);
-                arena64.push_back(im[k]);
+            make_plan(m, pm);
+            plan_twiddles(pm, re, im, pre, pim);
+            for (size_t k = 0; k < pre.size(); ++k) {
+                arena64.push_back(pre[k]);
+                arena64.push_back(pim[k]);
             }
         }
         hipError_t e;

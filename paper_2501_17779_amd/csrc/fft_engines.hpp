@@ -32,8 +32,12 @@ struct Plan {
     int32_t n;
     int32_t npass;
     int32_t radix[16];
-    int64_t tw_off;      // offset of the w_n^m table in the twiddle arena
+    int64_t tw_off;      // offset of the plan's per-pass twiddles in the arena
 };
+// Per-pass twiddle layout of a plan: pass i (radix R, stride ns = product of
+// the earlier radices) owns the (R - 1) ns entries w_{ns R}^{r k}, r = 1..R-1,
+// k = 0..ns-1, at (r - 1) ns + k after the entries of the earlier passes (n - 1
+// entries in all).  Lanes with consecutive k read consecutive entries.
 
 // j mod ns for 0 <= j < 2^13 and ns >= 1 through a float reciprocal and one
 // correction step (the quotient estimate is off by at most one).
@@ -49,7 +53,6 @@ template <int R, int NT, int NMAX, typename T>
 __device__ __forceinline__ void blk_pass(cpx<T>* buf, int n, int ns, const cpx<T>* __restrict__ tw) {
     constexpr int UM = (NMAX / R + NT - 1) / NT;
     const int nb = n / R;
-    const int tstride = n / (ns * R);
     const float inv_ns = 1.0f / (float)ns;
     cpx<T> v[UM][R];
 #pragma unroll
@@ -61,7 +64,7 @@ __device__ __forceinline__ void blk_pass(cpx<T>* buf, int n, int ns, const cpx<T
             for (int r = 0; r < R; ++r) v[u][r] = buf[j + r * nb];
             if (ns > 1) {
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[u][r] = mul(v[u][r], tw[r * k * tstride]);
+                for (int r = 1; r < R; ++r) v[u][r] = mul(v[u][r], tw[(r - 1) * ns + k]);
             }
             dft<R>(v[u]);
         }
@@ -85,7 +88,6 @@ template <int R, int NT, int NMAX, typename T>
 __device__ __forceinline__ void blk_pass2(cpx<T>* b1, cpx<T>* b2, int n, int ns, const cpx<T>* __restrict__ tw) {
     constexpr int UM = (NMAX / R + NT - 1) / NT;
     const int nb = n / R;
-    const int tstride = n / (ns * R);
     const float inv_ns = 1.0f / (float)ns;
     cpx<T> v[UM][R], w[UM][R];
 #pragma unroll
@@ -98,7 +100,7 @@ __device__ __forceinline__ void blk_pass2(cpx<T>* b1, cpx<T>* b2, int n, int ns,
             if (ns > 1) {
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    const cpx<T> f = tw[r * k * tstride];
+                    const cpx<T> f = tw[(r - 1) * ns + k];
                     v[u][r] = mul(v[u][r], f);
                     w[u][r] = mul(w[u][r], f);
                 }
@@ -134,6 +136,7 @@ __device__ void blk_fft2(cpx<T>* b1, cpx<T>* b2, const Plan& p, const cpx<T>* __
             case 7: blk_pass2<7, NT, NMAX>(b1, b2, p.n, ns, tw); break;
             default: blk_pass2<8, NT, NMAX>(b1, b2, p.n, ns, tw); break;
         }
+        tw += (r - 1) * ns;
         ns *= r;
     }
 }
@@ -151,6 +154,7 @@ __device__ void blk_fft(cpx<T>* buf, const Plan& p, const cpx<T>* __restrict__ t
             case 7: blk_pass<7, NT, NMAX>(buf, p.n, ns, tw); break;
             default: blk_pass<8, NT, NMAX>(buf, p.n, ns, tw); break;
         }
+        tw += (r - 1) * ns;
         ns *= r;
     }
 }
