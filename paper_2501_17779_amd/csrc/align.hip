@@ -356,8 +356,11 @@ __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1,
                                                   const Plan* __restrict__ plans,
                                                   const cpx<T>* __restrict__ arena, int rescore, int theta64,
                                                   const int* __restrict__ list_count, const int* __restrict__ list) {
+    // the plan's twiddles are staged in LDS where the table is small
+    constexpr bool kTwLds = MMAX * sizeof(cpx<T>) <= 16384;
     __shared__ cpx<T> A[MMAX];
     __shared__ cpx<T> B[MMAX];
+    __shared__ cpx<T> TWL[kTwLds ? MMAX : 1];
     __shared__ double red[2 * (NT / 64)];
     __shared__ int clist[kCandCap + 1];
     const int64_t todo = list ? (int64_t)*list_count : num_pairs;
@@ -375,6 +378,10 @@ __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1,
         const int M = plans[n].n;
         const Plan& p = plans[n];
         const cpx<T>* tw = arena + p.tw_off;
+        if constexpr (kTwLds) {
+            for (int k = threadIdx.x; k < M - 1; k += NT) TWL[k] = tw[k];
+            tw = TWL;                        // visible after the barrier of block_sum2 below
+        }
         const cpx<T>* pa = z1 + off;
         const cpx<T>* pb = z2 + off;
         const bool padded = M != n;
