@@ -1,0 +1,26 @@
+"""bench.py command line (no GPU needed): more than one GPU is refused with a
+message, and the workload list is the documented one."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def run(*args):
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args], capture_output=True,
+                          text=True, timeout=120)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = run("--gpus", "2")
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_workloads_listed_in_help():
+    r = run("--help")
+    assert r.returncode == 0
+    for c in ("batch", "pair", "allpairs", "ragged", "ragged_any", "bf16", "srv", "copy"):
+        assert c in r.stdout
