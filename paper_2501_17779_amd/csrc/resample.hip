@@ -443,11 +443,18 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
     double sx = 0.0, sy = 0.0;
     constexpr int kStage = (kFtP + 63) / 64;   // staged vertices per lane
     cf pre[kStage];                            // next tile's vertices, loaded ahead
+    // staged knot j of the tile at a reads vertex a - kFtH + j (cyclic); with
+    // M >= kFtP one correction by M suffices
+    const bool wide = M >= kFtP;
+    auto vert = [&](int j) { return wide ? (j < 0 ? j + M : (j >= M ? j - M : j)) : wrapm(j, M); };
 #pragma unroll
     for (int u = 0; u < kStage; ++u) {
         const int i = lane + 64 * u;
-        if (i < kFtP) pre[u] = P[wrapm(i - kFtH, M)];
+        if (i < kFtP) pre[u] = P[vert(i - kFtH)];
     }
+    // LDS index of staged knot lane + 64 u is kpl + 72 u (kp adds one slot per
+    // eight), of knots lane + 1 + 64 u and lane + 2 + 64 u kp1 + 72 u, kp2 + 72 u
+    const int kpl = kp(lane), kp1 = kp(lane + 1), kp2 = kp(lane + 2);
     for (int a = 0; a < M; a += kFtK - 1) {
         const bool last = (a + kFtK - 1 >= M);
         const int kt = last ? (M - a + 1) : kFtK;       // knots in this tile incl. the right end
@@ -455,31 +462,36 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
         // loading the next tile's
 #pragma unroll
         for (int u = 0; u < kStage; ++u) {
-            const int i = lane + 64 * u;
-            if (i < kFtP) sP[kp(i)] = pre[u];
+            if (lane + 64 * u < kFtP) sP[kpl + 72 * u] = pre[u];
         }
         if (!last) {
             const int an = a + kFtK - 1;
 #pragma unroll
             for (int u = 0; u < kStage; ++u) {
                 const int i = lane + 64 * u;
-                if (i < kFtP) pre[u] = P[wrapm(an - kFtH + i, M)];
+                if (i < kFtP) pre[u] = P[vert(an - kFtH + i)];
             }
         }
         wave_lds_sync();
-        for (int i = lane; i < kFtP - 1; i += 64) {
-            const cf p = sP[kp(i)], q = sP[kp(i + 1)];
-            const float dx = q.x - p.x, dy = q.y - p.y;
-            sH[kp(i)] = sqrtf(dx * dx + dy * dy);
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            if (lane + 64 * u < kFtP - 1) {
+                const cf p = sP[kpl + 72 * u], q = sP[kp1 + 72 * u];
+                const float dx = q.x - p.x, dy = q.y - p.y;
+                sH[kpl + 72 * u] = sqrtf(dx * dx + dy * dy);
+            }
         }
         wave_lds_sync();
         if (mode == CA_RESAMPLE_SPLINE) {
-            for (int i = lane + 1; i < kFtP - 1; i += 64) {
-                const cf pm = sP[kp(i - 1)], p = sP[kp(i)], q = sP[kp(i + 1)];
-                const float hm = sH[kp(i - 1)], h = sH[kp(i)];
-                const float ih = frcp(h), ihm = frcp(hm);
-                sR[kp(i)] = {6.0f * ((q.x - p.x) * ih - (p.x - pm.x) * ihm),
-                         6.0f * ((q.y - p.y) * ih - (p.y - pm.y) * ihm)};
+#pragma unroll
+            for (int u = 0; u < kStage; ++u) {
+                if (lane + 1 + 64 * u < kFtP - 1) {
+                    const cf pm = sP[kpl + 72 * u], p = sP[kp1 + 72 * u], q = sP[kp2 + 72 * u];
+                    const float hm = sH[kpl + 72 * u], h = sH[kp1 + 72 * u];
+                    const float ih = frcp(h), ihm = frcp(hm);
+                    sR[kp1 + 72 * u] = {6.0f * ((q.x - p.x) * ih - (p.x - pm.x) * ihm),
+                                        6.0f * ((q.y - p.y) * ih - (p.y - pm.y) * ihm)};
+                }
             }
         }
         // tile-relative arc length: lane owns local knots [8 lane, 8 lane + 8)
