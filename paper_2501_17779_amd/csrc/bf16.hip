@@ -55,8 +55,9 @@ __device__ __forceinline__ f32x4 mma(bf16x8 a, bf16x8 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// DFT of length 128 of two pairs' signals.  src(p, n) reads element n of pair
-// p; the result is written with dst(p, k, comp, value) in natural order k.
+// DFT of length 128 of two pairs' signals.  src(p, n, comp) reads component
+// comp (0 real, 1 imaginary) of element n of pair p; the result is written
+// with dst(p, k, comp, value) in natural order k.
 template <class Src, class Dst>
 __device__ __forceinline__ void dft128x2(Src src, Dst dst, cf* ys, const Bf16Lane& c, int l) {
     // stage 1: B rows = (Re n1 0..15, Im n1 0..15), columns = (pair, n2)
@@ -65,10 +66,7 @@ __device__ __forceinline__ void dft128x2(Src src, Dst dst, cf* ys, const Bf16Lan
         const int comp = l >> 5, n1b = 8 * ((l >> 4) & 1);
         float v[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const cf x = src(p, 8 * (n1b + e) + n2);
-            v[e] = comp ? x.y : x.x;
-        }
+        for (int e = 0; e < 8; ++e) v[e] = src(p, 8 * (n1b + e) + n2, comp);
         bf16x8 bh, bl;
         split8(v, bh, bl);
         f32x4 yr = {0.0f, 0.0f, 0.0f, 0.0f}, yi = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -89,12 +87,10 @@ __device__ __forceinline__ void dft128x2(Src src, Dst dst, cf* ys, const Bf16Lan
 #pragma unroll
     for (int pp = 0; pp < 2; ++pp) {
         const int k1 = l & 15, comp = (l >> 4) & 1, half = l >> 5;
+        const float* yc = reinterpret_cast<const float*>(ys + pp * kBN + k1 * 8) + comp;
         float u[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const cf y = ys[pp * kBN + k1 * 8 + e];
-            u[e] = comp ? y.y : y.x;
-        }
+        for (int e = 0; e < 8; ++e) u[e] = yc[2 * e];
         bf16x8 bh, bl;
         split8(u, bh, bl);
         const bf16x8 b = half ? bl : bh;
@@ -146,7 +142,9 @@ __global__ __launch_bounds__(256, 2) void k_align_bf16(const cf* __restrict__ z1
         }
         const double n1 = team_sum<32>(q1) / kBN, n2 = team_sum<32>(q2) / kBN;
         for (int cv = 0; cv < 2; ++cv) {
-            dft128x2([&](int pp, int n) { return s_z[wv][pp][cv][lpad<kBN>(n)]; },
+            dft128x2([&](int pp, int n, int comp) {
+                         return reinterpret_cast<const float*>(&s_z[wv][pp][cv][lpad<kBN>(n)])[comp];
+                     },
                      [&](int pp, int k, int comp, float v) {
                          float* w = reinterpret_cast<float*>(&s_w[wv][pp][cv][k]);
                          w[comp] = v;
@@ -159,7 +157,7 @@ __global__ __launch_bounds__(256, 2) void k_align_bf16(const cf* __restrict__ z1
             s_w[wv][pp][0][k] = cjmul(s_w[wv][pp][0][k], s_w[wv][pp][1][k]);
         }
         wave_lds_sync();
-        dft128x2([&](int pp, int n) { return s_w[wv][pp][0][n]; },
+        dft128x2([&](int pp, int n, int comp) { return reinterpret_cast<const float*>(&s_w[wv][pp][0][n])[comp]; },
                  [&](int pp, int k, int comp, float v) {
                      float* w = reinterpret_cast<float*>(&s_w[wv][pp][1][k]);
                      w[comp] = v;
@@ -168,8 +166,19 @@ __global__ __launch_bounds__(256, 2) void k_align_bf16(const cf* __restrict__ z1
         cf d[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) d[q] = s_w[wv][p][1][t + 32 * q];
-        const ca_result_t res = team_epilogue<kBN, 32>(d, a0, s_z[wv][p][1], s_cand[wv][p], t, n1, n2,
-                                                       CA_RESCORE_WINDOW, theta64, kBf16U);
+        wave_lds_sync();
+        // curve 2's nodes twice over the pair's spectra area (read into d
+        // above), so the re-scoring reads them at constant offsets
+        cf* zt = &s_w[wv][p][0][0];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const cf b = s_z[wv][p][1][lpad<kBN>(t + 32 * q)];
+            zt[t + 32 * q] = b;
+            zt[kBN + t + 32 * q] = b;
+        }
+        wave_lds_sync();
+        const ca_result_t res = team_epilogue<kBN, 32, kZTwice>(d, a0, zt, s_cand[wv][p], t, n1, n2,
+                                                                CA_RESCORE_WINDOW, theta64, kBf16U);
         if (t == 0 && (p == 0 || has1)) out[p0 + p] = res;
         wave_lds_sync();
     }
