@@ -33,10 +33,39 @@ def capture(fn):
     return g
 
 
-@pytest.mark.parametrize("kind", ["team", "block", "bf16", "allpairs", "ragged"])
+@pytest.mark.parametrize("kind", ["team", "block", "bf16", "allpairs", "ragged", "ragged_any", "srv", "handoff"])
 def test_graph_replays_match_eager(ca, kind):
     print(f"[gpu] graph replay {kind}", flush=True)
-    if kind == "allpairs":
+    if kind == "ragged_any":
+        # padded sizes, a size above the limit (flagged by the binning kernel)
+        rng = np.random.default_rng(12)
+        sizes = [97, 5000, 64, 1009, 11, 256]
+        offn = np.zeros(len(sizes) + 1, dtype=np.int64)
+        offn[1:] = np.cumsum(sizes)
+        a = (rng.normal(size=offn[-1]) + 1j * rng.normal(size=offn[-1])).astype(np.complex64)
+        b = (rng.normal(size=offn[-1]) + 1j * rng.normal(size=offn[-1])).astype(np.complex64)
+        z1, z2, off = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), torch.from_numpy(offn).cuda()
+        out = ca.empty_results(len(sizes), "cuda")
+        fn = lambda: ca.align_batch(z1, z2, offsets=off, out=out)  # noqa: E731
+    elif kind == "srv":
+        a, _ = inputs.batch(13, 9, 512)
+        z = torch.from_numpy(a).cuda()
+        q = torch.empty_like(z)
+        out = q.view(torch.uint8)
+        fn = lambda: ca.srv_transform(z, out=q)  # noqa: E731
+    elif kind == "handoff":
+        a, b = inputs.batch(14, 21, 256)
+        rec = ca.align_batch(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda())
+        t0 = torch.empty(21, dtype=torch.float64, device="cuda")
+        rot = torch.empty(21, 2, 2, dtype=torch.float64, device="cuda")
+        out = torch.empty(21 * 40, dtype=torch.uint8, device="cuda")
+
+        def fn():
+            t, r = ca.to_initializer(rec, n=256)
+            t0.copy_(t)
+            rot.copy_(r)
+            out.copy_(torch.cat([t0.view(torch.uint8), rot.view(torch.uint8).reshape(-1)]))
+    elif kind == "allpairs":
         g_in = torch.from_numpy(inputs.gallery(8, 24, 256)).cuda()
         out = ca.empty_results(24 * 23 // 2, "cuda")
         fn = lambda: ca.align_all_pairs(g_in, out=out)          # noqa: E731
