@@ -441,11 +441,15 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
-    ca.default_context(0)
+    ctx = ca.default_context(0)
     fn = {"batch": bench_batch, "copy": bench_copy, "pair": bench_pair, "allpairs": bench_allpairs,
           "ragged": bench_ragged, "ragged_any": lambda a, t, c: bench_ragged(a, t, c, snap=False),
           "bf16": bench_small_batch, "srv": bench_srv}[args.config]
     line = fn(args, torch, ca)
+    # launch choices in force: the tuning cache default_context loaded (if any)
+    src = os.environ.get("CURVEALIGN_TUNE_FILE", ca.TUNE_CACHE)
+    line["tuning"] = {"cache": os.path.relpath(src, ROOT) if src and os.path.exists(src) else None,
+                      "entries_applied": getattr(ctx, "tune_applied", 0)}
     print(json.dumps(line), flush=True)
 
 

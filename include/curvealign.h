@@ -231,6 +231,80 @@ ca_status_t to_initializer(ca_context_t ctx, const ca_result_t* results, int32_t
 ca_status_t srv_transform(ca_context_t ctx, const void* curves, const int64_t* offsets, int32_t n,
                           int64_t count, void* q_out, void* stream);
 
+/*
+ * Launch tuning.  The kernels above take a few launch choices at run time;
+ * each context holds one value per (knob, key), starting from defaults that
+ * need no tuning.  A choice changes how work is scheduled, never what is
+ * computed: grid and tile knobs give bit-identical results, and a radix
+ * schedule changes only the rounding order of the FFT (results stay within
+ * the error bound every record reports).
+ *
+ *   knob                    key                          values (count)
+ *   CA_TUNE_TEAM_GRID       n in {64,...,1024}           1: persistent blocks per CU of
+ *                           (uniform FP32 batches)          the team kernel, in multiples of
+ *                                                           its occupancy limit, 1..8, or 0
+ *                                                           for one block per group of pairs
+ *                                                           (default 1)
+ *   CA_TUNE_ALLPAIRS_COLS   n in {64,...,1024}           1: columns per all-pairs tile,
+ *                                                           1..256 (default 64)
+ *   CA_TUNE_BLOCK_PLAN      M, a transform size with no  1..16: radix schedule of the block
+ *                           prime factor above 7,           engine's FFT of size M, radices
+ *                           2 <= M <= 2 * CA_MAX_N          2, 3, 4, 5, 7, 8 whose product
+ *                                                           is M (default: eights, then a four
+ *                                                           or two, then 3, 5, 7)
+ *   CA_TUNE_BLOCK_GRID      size class 0..4 of the block 1: persistent blocks per CU,
+ *                           engine (M <= 512, 1024, 2048,   multiples of the occupancy limit,
+ *                           4096, 8192)                     1..8, or 0 for one block per pair
+ *                                                           (default 1)
+ *
+ * ca_tune_set and ca_tune_load change the tables the kernels read: they
+ * synchronise the device first and must not be called while work of this
+ * context is in flight on another stream or during stream capture.
+ */
+enum { CA_TUNE_TEAM_GRID = 0, CA_TUNE_ALLPAIRS_COLS = 1, CA_TUNE_BLOCK_PLAN = 2, CA_TUNE_BLOCK_GRID = 3 };
+
+/*
+ * ca_autotune -- measure every candidate of one (knob, key) on a synthetic
+ * batch that the library generates on the device (smooth star-shaped curves
+ * with rotated, shifted templates; about 2^25 nodes per side), install the
+ * fastest and report its time per launch in *best_ms (optional).  Candidates:
+ * grid knobs 1, 2, 4 and 0; all-pairs columns 2, 4, 8, 16, 32, 64; radix
+ * schedules: the orderings of the power-of-two part as eights, fours or
+ * mixed, each with the odd radices first or last.  Each candidate is timed
+ * with HIP events over three launches after one warm-up launch on `stream`.
+ * Allocates and frees its own device buffers and synchronises the stream.
+ * CA_ERR_UNSUPPORTED_N: the key names no size the knob serves (a transform
+ * size that no n in [2, CA_MAX_N] uses).
+ */
+ca_status_t ca_autotune(ca_context_t ctx, int32_t knob, int32_t key, float* best_ms, void* stream);
+
+/*
+ * ca_tune_get -- current values of (knob, key) into values[0..*count) (host
+ * memory); on entry *count is the capacity of values (16 is always enough),
+ * on return the number of values.  ca_tune_set -- install values[0..count)
+ * (host memory), validated as in the table above.
+ */
+ca_status_t ca_tune_get(ca_context_t ctx, int32_t knob, int32_t key, int32_t* values, int32_t* count);
+ca_status_t ca_tune_set(ca_context_t ctx, int32_t knob, int32_t key, const int32_t* values,
+                        int32_t count);
+
+/*
+ * ca_tune_save -- write every non-default choice of the context to a JSON
+ * file (host path):
+ *   {"format": "curvealign-tune/1", "arch": "gfx950", "num_cus": 256,
+ *    "entries": [{"knob": "team_grid", "key": 1024, "values": [2], "ms": 0.41}, ...]}
+ * knob names: team_grid, allpairs_cols, block_plan, block_grid; "ms" is the
+ * time ca_autotune measured (-1 for values set by hand).
+ * ca_tune_load -- read such a file and install its entries.  The whole file
+ * is validated before anything is installed: a file that cannot be read or
+ * parsed, or holds an invalid entry, returns CA_ERR_INVALID_ARG and leaves the
+ * context's choices unchanged.  A file written for another architecture or
+ * CU count installs nothing and returns CA_OK.  *applied (optional) receives
+ * the number of entries installed.
+ */
+ca_status_t ca_tune_save(ca_context_t ctx, const char* path);
+ca_status_t ca_tune_load(ca_context_t ctx, const char* path, int32_t* applied);
+
 #ifdef __cplusplus
 }
 #endif

@@ -46,7 +46,13 @@ MAX_N = 4096
 
 EXPORTED = ("ca_create", "ca_destroy", "ca_status_string", "ca_last_error", "ca_n_supported",
             "align_pair", "align_batch", "align_all_pairs", "resample_arclength", "to_initializer",
-            "srv_transform")
+            "srv_transform", "ca_autotune", "ca_tune_get", "ca_tune_set", "ca_tune_save", "ca_tune_load")
+
+# launch-tuning knobs (ca_autotune / ca_tune_*)
+TUNE_KNOBS = {"team_grid": 0, "allpairs_cols": 1, "block_plan": 2, "block_grid": 3}
+# tuning cache shipped with the package, loaded by default_context when it
+# matches the device; CURVEALIGN_TUNE_FILE names another file ("" = none)
+TUNE_CACHE = os.path.join(_HERE, "tune_cache.json")
 
 
 class CurveAlignError(RuntimeError):
@@ -90,8 +96,15 @@ def lib():
             L.resample_arclength.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, i32, vp]
             L.to_initializer.argtypes = [vp, vp, i32, vp, i64, vp, vp, vp]
             L.srv_transform.argtypes = [vp, vp, vp, i32, i64, vp, vp]
+            pi32 = ctypes.POINTER(i32)
+            L.ca_autotune.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_float), vp]
+            L.ca_tune_get.argtypes = [vp, i32, i32, pi32, pi32]
+            L.ca_tune_set.argtypes = [vp, i32, i32, pi32, i32]
+            L.ca_tune_save.argtypes = [vp, ctypes.c_char_p]
+            L.ca_tune_load.argtypes = [vp, ctypes.c_char_p, pi32]
             for name in ("ca_create", "ca_destroy", "align_pair", "align_batch",
-                         "align_all_pairs", "resample_arclength", "to_initializer", "srv_transform"):
+                         "align_all_pairs", "resample_arclength", "to_initializer", "srv_transform",
+                         "ca_autotune", "ca_tune_get", "ca_tune_set", "ca_tune_save", "ca_tune_load"):
                 getattr(L, name).restype = i32
             _lib = L
     return _lib
@@ -133,11 +146,61 @@ _contexts: dict[int, Context] = {}
 
 
 def default_context(device: int | None = None) -> Context:
+    """The per-device context of this process, created on first use with the
+    tuning cache (CURVEALIGN_TUNE_FILE, else the packaged one) loaded."""
     import torch
     dev = torch.cuda.current_device() if device is None else int(device)
     if dev not in _contexts:
-        _contexts[dev] = Context(dev)
+        ctx = Context(dev)
+        path = os.environ.get("CURVEALIGN_TUNE_FILE", TUNE_CACHE)
+        if path and os.path.exists(path):
+            ctx.tune_applied = tune_load(path, ctx=ctx)
+        _contexts[dev] = ctx
     return _contexts[dev]
+
+
+def _knob(knob) -> int:
+    if knob not in TUNE_KNOBS:
+        raise ValueError(f"knob must be one of {sorted(TUNE_KNOBS)}")
+    return TUNE_KNOBS[knob]
+
+
+def autotune(knob: str, key: int, *, stream=None, ctx=None) -> float:
+    """Time every candidate of (knob, key) on a synthetic batch, install the
+    fastest; returns its milliseconds per launch."""
+    ctx = ctx or default_context()
+    ms = ctypes.c_float()
+    _check(lib().ca_autotune(ctx.handle, _knob(knob), int(key), ctypes.byref(ms), _stream_ptr(stream)))
+    return float(ms.value)
+
+
+def tune_get(knob: str, key: int, *, ctx=None) -> list[int]:
+    ctx = ctx or default_context()
+    vals = (ctypes.c_int32 * 16)()
+    cnt = ctypes.c_int32(16)
+    _check(lib().ca_tune_get(ctx.handle, _knob(knob), int(key), vals, ctypes.byref(cnt)))
+    return [int(vals[i]) for i in range(cnt.value)]
+
+
+def tune_set(knob: str, key: int, values, *, ctx=None):
+    ctx = ctx or default_context()
+    vals = [int(v) for v in (values if hasattr(values, "__len__") else [values])]
+    arr = (ctypes.c_int32 * max(1, len(vals)))(*vals)
+    _check(lib().ca_tune_set(ctx.handle, _knob(knob), int(key), arr, len(vals)))
+
+
+def tune_save(path: str, *, ctx=None):
+    ctx = ctx or default_context()
+    _check(lib().ca_tune_save(ctx.handle, os.fsencode(path)))
+
+
+def tune_load(path: str, *, ctx=None) -> int:
+    """Install the entries of a tuning file; returns how many applied (0 for
+    a file written for another device)."""
+    ctx = ctx or default_context()
+    applied = ctypes.c_int32(0)
+    _check(lib().ca_tune_load(ctx.handle, os.fsencode(path), ctypes.byref(applied)))
+    return int(applied.value)
 
 
 def _stream_ptr(stream):

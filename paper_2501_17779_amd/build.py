@@ -12,7 +12,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcurvealign.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["align.hip", "resample.hip", "bf16.hip", "handoff.hip", "srv.hip", "capi.cpp"]
+SOURCES = ["align.hip", "resample.hip", "bf16.hip", "handoff.hip", "srv.hip", "tune.hip", "capi.cpp"]
 FLAGS = [
     "-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 VALU instructions are kept out of the generated code

@@ -103,13 +103,13 @@ __global__ __launch_bounds__(256) void k_spectra(const cf* __restrict__ curves, 
 }
 
 // Upper-triangle tiles: blockIdx.y picks TEAMS rows i, blockIdx.x a block of
-// JB columns j.  Each row's spectrum and nodes stay in registers; every
+// `cols` columns j.  Each row's spectrum and nodes stay in registers; every
 // column's spectrum and nodes are staged once in LDS (double-buffered: the
 // next column is loaded while the current one is aligned) and shared by the
 // rows.
-template <int N, int JB>
+template <int N>
 __global__ __launch_bounds__(256, TeamCfg<N>::AW) void k_allpairs(const cf* __restrict__ curves, const cf* __restrict__ spec,
-                                                  const double* __restrict__ norms, int m,
+                                                  const double* __restrict__ norms, int m, int cols,
                                                   ca_result_t* __restrict__ out, const cf* __restrict__ tw,
                                                   int rescore, int theta64) {
     constexpr int T = TeamCfg<N>::T;
@@ -127,8 +127,8 @@ __global__ __launch_bounds__(256, TeamCfg<N>::AW) void k_allpairs(const cf* __re
     __shared__ cf xbuf[TEAMS * PADN];
     __shared__ int cand_all[TEAMS * kCandCap];
     const int i0 = blockIdx.y * TEAMS;
-    const int j0 = blockIdx.x * JB;
-    if (j0 + JB - 1 <= i0) return;     // no j > i in this tile
+    const int j0 = blockIdx.x * cols;
+    if (j0 + cols - 1 <= i0) return;   // no j > i in this tile
     load_twiddles<TeamCfg<N>::TW>(tws, tw);
     const int team = threadIdx.x / T;
     const int t = threadIdx.x % T;
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256, TeamCfg<N>::AW) void k_allpairs(const cf* __re
         ni = norms[i];
     }
     const int jbeg = max(j0, i0 + 1);
-    const int jend = min(j0 + JB, m);
+    const int jend = min(j0 + cols, m);
     cf gZ[PER], gz[PER];
     auto fetch = [&](int j) {
 #pragma unroll
@@ -226,13 +226,15 @@ static int team_blocks_per_cu() {
 }
 
 hipError_t launch_align_team(const void* z1, const void* z2, int n, int64_t np, ca_result_t* out,
-                             const void* tw, int rescore, int theta64, int num_cus, hipStream_t s) {
+                             const void* tw, int rescore, int theta64, int num_cus, int grid_mult,
+                             hipStream_t s) {
+    if (grid_mult < 0) return hipErrorInvalidValue;
     switch (n) {
-        case 64: return launch_team_n<64>(z1, z2, np, out, tw, rescore, theta64, num_cus * team_blocks_per_cu<64>(), s);
-        case 128: return launch_team_n<128>(z1, z2, np, out, tw, rescore, theta64, num_cus * team_blocks_per_cu<128>(), s);
-        case 256: return launch_team_n<256>(z1, z2, np, out, tw, rescore, theta64, num_cus * team_blocks_per_cu<256>(), s);
-        case 512: return launch_team_n<512>(z1, z2, np, out, tw, rescore, theta64, num_cus * team_blocks_per_cu<512>(), s);
-        case 1024: return launch_team_n<1024>(z1, z2, np, out, tw, rescore, theta64, num_cus * team_blocks_per_cu<1024>(), s);
+        case 64: return launch_team_n<64>(z1, z2, np, out, tw, rescore, theta64, num_cus * team_blocks_per_cu<64>() * grid_mult, s);
+        case 128: return launch_team_n<128>(z1, z2, np, out, tw, rescore, theta64, num_cus * team_blocks_per_cu<128>() * grid_mult, s);
+        case 256: return launch_team_n<256>(z1, z2, np, out, tw, rescore, theta64, num_cus * team_blocks_per_cu<256>() * grid_mult, s);
+        case 512: return launch_team_n<512>(z1, z2, np, out, tw, rescore, theta64, num_cus * team_blocks_per_cu<512>() * grid_mult, s);
+        case 1024: return launch_team_n<1024>(z1, z2, np, out, tw, rescore, theta64, num_cus * team_blocks_per_cu<1024>() * grid_mult, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -259,13 +261,13 @@ static hipError_t launch_spectra_n(const void* curves, int m, void* spec, double
 
 template <int N>
 static hipError_t launch_allpairs_n(const void* curves, const void* spec, const double* norms, int m,
-                                    ca_result_t* out, const void* tw, int rescore, int theta64,
+                                    ca_result_t* out, const void* tw, int rescore, int theta64, int cols,
                                     hipStream_t s) {
     constexpr int TEAMS = 256 / TeamCfg<N>::T;
-    constexpr int JB = 64;
-    dim3 grid((unsigned)((m + JB - 1) / JB), (unsigned)((m + TEAMS - 1) / TEAMS));
-    hipLaunchKernelGGL((k_allpairs<N, JB>), grid, dim3(256), 0, s, (const cf*)curves, (const cf*)spec,
-                       norms, m, out, (const cf*)tw, rescore, theta64);
+    if (cols < 1) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((m + cols - 1) / cols), (unsigned)((m + TEAMS - 1) / TEAMS));
+    hipLaunchKernelGGL((k_allpairs<N>), grid, dim3(256), 0, s, (const cf*)curves, (const cf*)spec,
+                       norms, m, cols, out, (const cf*)tw, rescore, theta64);
     return hipGetLastError();
 }
 
@@ -282,13 +284,14 @@ hipError_t launch_spectra(const void* curves, int m, int n, void* spec, double* 
 }
 
 hipError_t launch_allpairs(const void* curves, const void* spec, const double* norms, int m, int n,
-                           ca_result_t* out, const void* tw, int rescore, int theta64, hipStream_t s) {
+                           ca_result_t* out, const void* tw, int rescore, int theta64, int cols,
+                           hipStream_t s) {
     switch (n) {
-        case 64: return launch_allpairs_n<64>(curves, spec, norms, m, out, tw, rescore, theta64, s);
-        case 128: return launch_allpairs_n<128>(curves, spec, norms, m, out, tw, rescore, theta64, s);
-        case 256: return launch_allpairs_n<256>(curves, spec, norms, m, out, tw, rescore, theta64, s);
-        case 512: return launch_allpairs_n<512>(curves, spec, norms, m, out, tw, rescore, theta64, s);
-        case 1024: return launch_allpairs_n<1024>(curves, spec, norms, m, out, tw, rescore, theta64, s);
+        case 64: return launch_allpairs_n<64>(curves, spec, norms, m, out, tw, rescore, theta64, cols, s);
+        case 128: return launch_allpairs_n<128>(curves, spec, norms, m, out, tw, rescore, theta64, cols, s);
+        case 256: return launch_allpairs_n<256>(curves, spec, norms, m, out, tw, rescore, theta64, cols, s);
+        case 512: return launch_allpairs_n<512>(curves, spec, norms, m, out, tw, rescore, theta64, cols, s);
+        case 1024: return launch_allpairs_n<1024>(curves, spec, norms, m, out, tw, rescore, theta64, cols, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -490,7 +493,9 @@ static hipError_t launch_blk_class(const BlkArgs& a, int cls, hipStream_t s) {
             nb = 1;
         per_cu = nb;
     }
-    int64_t grid = (int64_t)a.num_cus * per_cu;
+    const int g = a.grid_mult[cls];
+    if (g < 0) return hipErrorInvalidValue;
+    int64_t grid = g == 0 ? a.num_pairs : (int64_t)a.num_cus * per_cu * g;
     if (grid > a.num_pairs) grid = a.num_pairs;
     const int* count = a.offsets ? a.bins + cls : nullptr;
     const int* list = a.offsets ? a.bins + kBlkClasses + cls * a.num_pairs : nullptr;

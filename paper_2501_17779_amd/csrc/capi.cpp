@@ -10,7 +10,7 @@
 
 #include "../../include/curvealign.h"
 #include "fft_engines.hpp"
-#include "launch.hpp"
+#include "context.hpp"
 
 namespace ca {
 int64_t resample_slot_bytes();
@@ -20,8 +20,11 @@ int resample_max_raw();
 using ca::Plan;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+namespace ca {
+namespace host {
 
 ca_status_t fail(ca_status_t st, const std::string& msg) {
     g_err = msg;
@@ -50,22 +53,50 @@ int transform_size(int n) {
     return m;
 }
 
-constexpr int kMaxM = 2 * CA_MAX_N;
-constexpr int kFp64MaxM = CA_MAX_N;   // LDS of the FP64 block engine
+// Default radix schedule of the block engine: eights, then a four or two,
+// then the odd primes.
+std::vector<int> default_radices(int n) {
+    std::vector<int> r;
+    int m = n;
+    while (m % 8 == 0) { r.push_back(8); m /= 8; }
+    if (m % 4 == 0) { r.push_back(4); m /= 4; }
+    if (m % 2 == 0) { r.push_back(2); m /= 2; }
+    for (int p : {3, 5, 7})
+        while (m % p == 0) { r.push_back(p); m /= p; }
+    return r;
+}
 
-// Radix schedule of the block engine: eights, then a four or two, then the
-// odd primes.
-void make_plan(int n, Plan& p) {
+bool valid_radices(int m, const std::vector<int>& r) {
+    if (r.empty() || r.size() > 16) return false;
+    int64_t prod = 1;
+    for (int x : r) {
+        if (x != 2 && x != 3 && x != 4 && x != 5 && x != 7 && x != 8) return false;
+        prod *= x;
+        if (prod > m) return false;
+    }
+    return prod == m;
+}
+
+Plan plan_from(int n, const std::vector<int>& r) {
+    Plan p;
     memset(&p, 0, sizeof(p));
     p.n = n;
-    int m = n, k = 0;
-    while (m % 8 == 0) { p.radix[k++] = 8; m /= 8; }
-    if (m % 4 == 0) { p.radix[k++] = 4; m /= 4; }
-    if (m % 2 == 0) { p.radix[k++] = 2; m /= 2; }
-    for (int r : {3, 5, 7})
-        while (m % r == 0) { p.radix[k++] = r; m /= r; }
-    p.npass = k;
+    p.npass = (int32_t)r.size();
+    for (size_t i = 0; i < r.size(); ++i) p.radix[i] = r[i];
+    return p;
 }
+
+std::vector<int> radices_for(const ca_context* c, int m) {
+    auto it = c->tune.blk_plan.find(m);
+    return it != c->tune.blk_plan.end() ? it->second : default_radices(m);
+}
+
+}  // namespace host
+}  // namespace ca
+
+using namespace ca::host;
+
+namespace {
 
 // Per-pass twiddles of the block-engine plan p (layout in fft_engines.hpp):
 // pass i, radix R, stride ns: w_{ns R}^{r k} = w_n^{r k n / (ns R)}.
@@ -103,60 +134,30 @@ void twiddles(int n, std::vector<double>& re, std::vector<double>& im) {
 
 }  // namespace
 
-struct ca_context {
-    int device = 0;
-    int num_cus = 0;
-    size_t lds_per_block = 0;
-    std::mutex mu;
-    // block-engine plans for every n in [0, CA_MAX_N] and the twiddle arenas
-    Plan* d_plans = nullptr;
-    std::vector<Plan> h_plans;
-    void* d_tw32 = nullptr;   // float2 arena
-    void* d_tw64 = nullptr;   // double2 arena
-    void* d_team_tw[11] = {};  // per-pass team-engine twiddles, index log2(n)
-    void* d_bf16 = nullptr;    // split-BF16 per-lane constants (64 x 128 bytes)
-    // resampler scratch and the list of curves for the general kernel
-    void* d_rs = nullptr;
-    int64_t rs_slots = 0;
-    int* d_slow = nullptr;          // [0] = count, [1..] = curve indices
-    int64_t slow_cap = 0;
-    // block-engine size-class lists of ragged batches
-    int* d_bins = nullptr;
-    int64_t bins_cap = 0;           // pairs
-    // all-pairs spectra workspace
-    void* d_spec = nullptr;
-    size_t spec_bytes = 0;
-    double* d_norms = nullptr;
-    size_t norms_count = 0;
-};
+namespace ca {
+namespace host {
 
-namespace {
+// Per-pass twiddles of transform size m under the context's radix schedule.
+void block_twiddles(const ca_context* c, int m, std::vector<double>& pre, std::vector<double>& pim) {
+    std::vector<double> re, im;
+    twiddles(m, re, im);
+    plan_twiddles(plan_from(m, radices_for(c, m)), re, im, pre, pim);
+}
 
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
+// Plans for every n and the twiddle arenas (one segment of m - 1 entries per
+// 7-smooth transform size m; the segment length does not depend on the radix
+// schedule, so the offsets are fixed).
 ca_status_t ensure_tables(ca_context* c, bool need64) {
     if (!c->d_plans) {
         c->h_plans.assign(CA_MAX_N + 1, Plan{});
+        c->tw_off.assign(kMaxM + 1, -1);
         std::vector<float> arena32;
-        std::vector<int64_t> tw_off(kMaxM + 1, -1);
         int64_t off = 0;
-        std::vector<double> re, im, pre, pim;
-        Plan pm;
+        std::vector<double> pre, pim;
         for (int m = 2; m <= kMaxM; ++m) {
             if (!smooth7_size(m)) continue;
-            tw_off[m] = off;
-            twiddles(m, re, im);
-            make_plan(m, pm);
-            plan_twiddles(pm, re, im, pre, pim);
+            c->tw_off[m] = off;
+            block_twiddles(c, m, pre, pim);
             for (size_t k = 0; k < pre.size(); ++k) {
                 arena32.push_back((float)pre[k]);
                 arena32.push_back((float)pim[k]);
@@ -165,8 +166,8 @@ ca_status_t ensure_tables(ca_context* c, bool need64) {
         }
         for (int n = 2; n <= CA_MAX_N; ++n) {
             const int M = transform_size(n);
-            make_plan(M, c->h_plans[n]);
-            c->h_plans[n].tw_off = tw_off[M];
+            c->h_plans[n] = plan_from(M, radices_for(c, M));
+            c->h_plans[n].tw_off = c->tw_off[M];
         }
         hipError_t e;
         if ((e = hipMalloc(&c->d_plans, sizeof(Plan) * (CA_MAX_N + 1))) != hipSuccess)
@@ -181,13 +182,10 @@ ca_status_t ensure_tables(ca_context* c, bool need64) {
             return hip_fail(e, "twiddle upload");
     }
     if (need64 && !c->d_tw64) {
-        std::vector<double> arena64, re, im, pre, pim;
-        Plan pm;
+        std::vector<double> arena64, pre, pim;
         for (int m = 2; m <= kMaxM; ++m) {      // same order and offsets as the FP32 arena
             if (!smooth7_size(m)) continue;
-            twiddles(m, re, im);
-            make_plan(m, pm);
-            plan_twiddles(pm, re, im, pre, pim);
+            block_twiddles(c, m, pre, pim);
             for (size_t k = 0; k < pre.size(); ++k) {
                 arena64.push_back(pre[k]);
                 arena64.push_back(pim[k]);
@@ -200,6 +198,41 @@ ca_status_t ensure_tables(ca_context* c, bool need64) {
                            hipMemcpyHostToDevice)) != hipSuccess)
             return hip_fail(e, "FP64 twiddle upload");
     }
+    return CA_OK;
+}
+
+ca_status_t upload_block_plan(ca_context* c, int m) {
+    if (!c->d_plans) return CA_OK;             // the tables are built later with the new schedule
+    hipError_t e = hipDeviceSynchronize();     // no kernel may read the tables while they change
+    if (e != hipSuccess) return hip_fail(e, "synchronise before the plan update");
+    const std::vector<int> r = radices_for(c, m);
+    for (int n = 2; n <= CA_MAX_N; ++n) {
+        if (c->h_plans[n].n != m) continue;
+        const int64_t off = c->h_plans[n].tw_off;
+        c->h_plans[n] = plan_from(m, r);
+        c->h_plans[n].tw_off = off;
+    }
+    if ((e = hipMemcpy(c->d_plans, c->h_plans.data(), sizeof(Plan) * (CA_MAX_N + 1),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "plan upload");
+    std::vector<double> pre, pim;
+    block_twiddles(c, m, pre, pim);
+    const size_t cnt = pre.size();
+    std::vector<float> t32(2 * cnt);
+    std::vector<double> t64(2 * cnt);
+    for (size_t k = 0; k < cnt; ++k) {
+        t32[2 * k] = (float)pre[k];
+        t32[2 * k + 1] = (float)pim[k];
+        t64[2 * k] = pre[k];
+        t64[2 * k + 1] = pim[k];
+    }
+    const int64_t off = c->tw_off[m];
+    if ((e = hipMemcpy((float*)c->d_tw32 + 2 * off, t32.data(), t32.size() * sizeof(float),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "twiddle upload");
+    if (c->d_tw64 && (e = hipMemcpy((double*)c->d_tw64 + 2 * off, t64.data(), t64.size() * sizeof(double),
+                                    hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "FP64 twiddle upload");
     return CA_OK;
 }
 
@@ -324,7 +357,8 @@ ca_status_t parse_opts(const ca_options_t* opt, ca_options_t& o) {
     return CA_OK;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace ca
 
 extern "C" {
 
@@ -364,6 +398,9 @@ ca_status_t ca_create(ca_context_t* ctx, int device) {
     c->device = device;
     c->num_cus = prop.multiProcessorCount;
     c->lds_per_block = prop.sharedMemPerBlock;
+    c->arch = prop.gcnArchName;
+    const size_t colon = c->arch.find(':');
+    if (colon != std::string::npos) c->arch.resize(colon);
     DeviceGuard g(device);
     ca_status_t st = ensure_tables(c, false);
     if (st != CA_OK) {
@@ -425,7 +462,7 @@ ca_status_t align_batch(ca_context_t c, const void* z1, const void* z2, const in
         st = ensure_team_tables(c);
         if (st != CA_OK) return st;
         e = ca::launch_align_team(z1, z2, n, num_pairs, out, team_tw_for(c, n), o.rescore, o.theta_fp64,
-                                  c->num_cus, s);
+                                  c->num_cus, c->tune.team_grid[team_key(n)], s);
     } else {
         ca::BlkArgs a;
         a.z1 = z1;
@@ -440,6 +477,7 @@ ca_status_t align_batch(ca_context_t c, const void* z1, const void* z2, const in
         a.rescore = o.rescore;
         a.theta64 = o.theta_fp64;
         a.num_cus = c->num_cus;
+        for (int k = 0; k < ca::kBlkClasses; ++k) a.grid_mult[k] = c->tune.blk_grid[k];
         a.bins = nullptr;
         if (offsets) {
             if (num_pairs > c->bins_cap) {
@@ -511,7 +549,7 @@ ca_status_t align_all_pairs(ca_context_t c, const void* curves, int32_t m, int32
         e = ca::launch_spectra(curves, m, n, c->d_spec, c->d_norms, team_tw_for(c, n), s);
         if (e != hipSuccess) return hip_fail(e, "spectra kernel launch");
         e = ca::launch_allpairs(curves, c->d_spec, c->d_norms, m, n, out_upper, team_tw_for(c, n),
-                                o.rescore, o.theta_fp64, s);
+                                o.rescore, o.theta_fp64, c->tune.allpairs_cols[team_key(n)], s);
         if (e != hipSuccess) return hip_fail(e, "all-pairs kernel launch");
         return CA_OK;
     }

@@ -10,6 +10,8 @@ namespace ca {
 
 struct Plan;
 
+constexpr int kBlkClasses = 5;
+
 struct BlkArgs {
     const void* z1;
     const void* z2;
@@ -24,12 +26,14 @@ struct BlkArgs {
     int rescore;
     int theta64;
     int num_cus;
+    // persistent blocks per CU of each size class, in multiples of the
+    // kernel's occupancy limit; 0 = one block per pair
+    int grid_mult[kBlkClasses];
     // ragged batches: device workspace of kBlkClasses counters followed by
     // kBlkClasses lists of num_pairs pair indices (blk_bin_ints(num_pairs) ints)
     int* bins;
 };
 
-constexpr int kBlkClasses = 5;
 inline int64_t blk_bin_ints(int64_t num_pairs) { return kBlkClasses + kBlkClasses * num_pairs; }
 
 // Persistent size-class kernels, one pair per workgroup at a time,
@@ -44,9 +48,11 @@ hipError_t launch_align_blk_f64(const BlkArgs& a, hipStream_t s);
 // (see TeamCfg): entry TWO + (r - 1) NS + k = w_{NS RP}^{r k}.
 bool team_supported(int n);
 int team_twiddle_count(int n);
+// The persistent grid is grid_mult times the occupancy limit per CU
+// (grid_mult = 0: one block per group of pairs).
 hipError_t launch_align_team(const void* z1, const void* z2, int n, int64_t num_pairs,
                              ca_result_t* out, const void* tw, int rescore, int theta64,
-                             int num_cus, hipStream_t s);
+                             int num_cus, int grid_mult, hipStream_t s);
 
 // Split-BF16 MFMA path, n = 128.  lane_consts: 64 per-lane blocks of 128
 // bytes (stage-1 and stage-2 DFT matrices as BF16 hi/lo operands in the
@@ -54,12 +60,13 @@ hipError_t launch_align_team(const void* z1, const void* z2, int n, int64_t num_
 hipError_t launch_align_bf16(const void* z1, const void* z2, int64_t num_pairs, ca_result_t* out,
                              const void* lane_consts, int theta64, int num_cus, hipStream_t s);
 
-// All-pairs: per-curve spectra, then the upper-triangle tile kernel.
+// All-pairs: per-curve spectra, then the upper-triangle tile kernel with
+// tiles of (pairs per block) rows x `cols` columns.
 hipError_t launch_spectra(const void* curves, int m, int n, void* spectra, double* norms,
                           const void* tw, hipStream_t s);
 hipError_t launch_allpairs(const void* curves, const void* spectra, const double* norms, int m,
                            int n, ca_result_t* out, const void* tw, int rescore, int theta64,
-                           hipStream_t s);
+                           int cols, hipStream_t s);
 bool allpairs_supported(int n);
 
 // Hand-off records -> (t0*, R*) in the paper's notation.

@@ -212,3 +212,88 @@ def test_argument_errors_before_device_work(L):
     assert L.align_batch(ctx, None, None, None, 64, 0, None, None, None) == ca.OK
     assert L.align_all_pairs(ctx, None, 1, 64, None, None, None) == ca.OK
     assert L.resample_arclength(ctx, None, None, 0, None, None, None, None, 0, None) == ca.OK
+
+
+def _tune_file(tmp_path, name, text):
+    p = tmp_path / name
+    p.write_text(text)
+    return str(p).encode()
+
+
+def test_tuning_arguments_rejected_on_host(L):
+    ctx = ctypes.c_void_p(0x1000)    # dummy handle: every case below must fail before using it
+    i32 = ctypes.c_int32
+    vals = (i32 * 16)(*([8] * 16))
+    cnt = i32(16)
+    assert L.ca_autotune(None, 0, 1024, None, None) == ca.ERR_INVALID_ARG
+    assert L.ca_tune_get(None, 0, 1024, vals, ctypes.byref(cnt)) == ca.ERR_INVALID_ARG
+    assert L.ca_tune_set(None, 0, 1024, vals, 1) == ca.ERR_INVALID_ARG
+    assert L.ca_tune_save(None, b"/tmp/x.json") == ca.ERR_INVALID_ARG
+    assert L.ca_tune_load(None, b"/tmp/x.json", None) == ca.ERR_INVALID_ARG
+    for knob in (-1, 4):
+        assert L.ca_autotune(ctx, knob, 1024, None, None) == ca.ERR_INVALID_ARG
+        assert L.ca_tune_get(ctx, knob, 1024, vals, ctypes.byref(cnt)) == ca.ERR_INVALID_ARG
+        assert L.ca_tune_set(ctx, knob, 1024, vals, 1) == ca.ERR_INVALID_ARG
+    # keys the knobs do not serve
+    for knob, key in ((0, 96), (1, 2048), (2, 11), (2, 16384), (2, 1)):
+        assert L.ca_autotune(ctx, knob, key, None, None) == ca.ERR_UNSUPPORTED_N, (knob, key)
+    assert L.ca_autotune(ctx, 3, 5, None, None) == ca.ERR_INVALID_ARG
+    for knob, key in ((0, 96), (1, 2048), (2, 11), (3, 5), (3, -1)):
+        assert L.ca_tune_get(ctx, knob, key, vals, ctypes.byref(cnt)) == ca.ERR_INVALID_ARG, (knob, key)
+    # values outside the header's ranges
+    def setv(knob, key, *v):
+        arr = (i32 * max(1, len(v)))(*v)
+        return L.ca_tune_set(ctx, knob, key, arr, len(v))
+    assert setv(0, 1024, 9) == ca.ERR_INVALID_ARG
+    assert setv(0, 1024, -1) == ca.ERR_INVALID_ARG
+    assert setv(0, 1024, 1, 2) == ca.ERR_INVALID_ARG
+    assert setv(1, 512, 0) == ca.ERR_INVALID_ARG
+    assert setv(1, 512, 257) == ca.ERR_INVALID_ARG
+    assert setv(2, 4096, 8, 8, 8) == ca.ERR_INVALID_ARG          # product 512
+    assert setv(2, 4096, 16, 16, 16) == ca.ERR_INVALID_ARG       # radix 16 is not a block-engine radix
+    assert setv(2, 3000, 8, 3, 5, 5) == ca.ERR_INVALID_ARG       # product 600
+    assert setv(3, 0, 9) == ca.ERR_INVALID_ARG
+    assert L.ca_tune_set(ctx, 0, 1024, vals, 0) == ca.ERR_INVALID_ARG
+    assert L.ca_tune_set(ctx, 2, 4096, vals, 17) == ca.ERR_INVALID_ARG
+    assert L.ca_tune_set(ctx, 0, 1024, None, 1) == ca.ERR_INVALID_ARG
+    assert L.ca_tune_get(ctx, 0, 1024, None, ctypes.byref(cnt)) == ca.ERR_INVALID_ARG
+    assert L.ca_tune_save(ctx, None) == ca.ERR_INVALID_ARG
+    assert L.ca_tune_load(ctx, None, None) == ca.ERR_INVALID_ARG
+
+
+def test_tuning_file_rejections_on_host(L, tmp_path):
+    """Every malformed cache is refused while reading, before the context is
+    used (the handle is a dummy)."""
+    ctx = ctypes.c_void_p(0x1000)
+    applied = ctypes.c_int32(-7)
+    assert L.ca_tune_load(ctx, str(tmp_path / "missing.json").encode(), ctypes.byref(applied)) == \
+        ca.ERR_INVALID_ARG
+    assert applied.value == 0
+    head = '{"format": "curvealign-tune/1", "arch": "gfx950", "num_cus": 256, "entries": %s}'
+    bad = {
+        "not_json": "{format: 1}",
+        "truncated": head[:40],
+        "trailing": head % "[]" + " x",
+        "array_root": "[]",
+        "format": '{"format": "other/1", "arch": "gfx950", "num_cus": 256, "entries": []}',
+        "no_arch": '{"format": "curvealign-tune/1", "num_cus": 256, "entries": []}',
+        "no_entries": '{"format": "curvealign-tune/1", "arch": "gfx950", "num_cus": 256}',
+        "knob": head % '[{"knob": "warp_size", "key": 64, "values": [1]}]',
+        "key": head % '[{"knob": "team_grid", "key": 1.5, "values": [1]}]',
+        "team_key": head % '[{"knob": "team_grid", "key": 96, "values": [1]}]',
+        "value": head % '[{"knob": "team_grid", "key": 1024, "values": [9]}]',
+        "cols": head % '[{"knob": "allpairs_cols", "key": 512, "values": [0]}]',
+        "plan_product": head % '[{"knob": "block_plan", "key": 4096, "values": [8, 8, 8]}]',
+        "plan_radix": head % '[{"knob": "block_plan", "key": 4096, "values": [16, 16, 16]}]',
+        "plan_key": head % '[{"knob": "block_plan", "key": 4099, "values": [4099]}]',
+        "class": head % '[{"knob": "block_grid", "key": 5, "values": [1]}]',
+        "values_type": head % '[{"knob": "block_grid", "key": 1, "values": ["2"]}]',
+        "one_bad_of_two": head % ('[{"knob": "block_grid", "key": 1, "values": [2]}, '
+                                  '{"knob": "block_grid", "key": 2, "values": [-2]}]'),
+    }
+    for name, text in bad.items():
+        applied.value = -7
+        st = L.ca_tune_load(ctx, _tune_file(tmp_path, name + ".json", text), ctypes.byref(applied))
+        assert st == ca.ERR_INVALID_ARG, name
+        assert applied.value == 0, name
+        assert _last(L), name

@@ -1,0 +1,200 @@
+"""Launch tuning on the GPU: ca_autotune installs one of its candidates,
+choices survive a save/load round trip, and no choice changes what is
+computed -- grid and tile choices give bit-identical records, radix schedules
+give records that pass the oracle's acceptance rule (FP32 and FP64).
+
+Tuning runs on contexts of its own, so the default context that the other
+GPU tests share keeps its choices.
+"""
+import numpy as np
+import pytest
+
+import acceptance as acc
+import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ca():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2501_17779_amd as m
+    m.default_context(0)
+    return m
+
+
+@pytest.fixture
+def ctx(ca):
+    c = ca.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def note(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def smooth7(m):
+    for p in (2, 3, 5, 7):
+        while m % p == 0:
+            m //= p
+    return m == 1
+
+
+def transform_size(n):
+    if smooth7(n):
+        return n
+    m = 2 * n
+    while not smooth7(m):
+        m += 1
+    return m
+
+
+@pytest.mark.parametrize("knob,key,allowed", [
+    ("team_grid", 256, {(1,), (2,), (4,), (0,)}),
+    ("team_grid", 1024, {(1,), (2,), (4,), (0,)}),
+    ("allpairs_cols", 128, {(2,), (4,), (8,), (16,), (32,), (64,)}),
+    ("block_grid", 1, {(1,), (2,), (4,), (0,)}),
+    ("block_grid", 4, {(1,), (2,), (4,), (0,)}),
+])
+def test_autotune_installs_a_candidate(ca, ctx, knob, key, allowed):
+    note(f"autotune {knob} key={key}")
+    ms = ca.autotune(knob, key, ctx=ctx)
+    got = tuple(ca.tune_get(knob, key, ctx=ctx))
+    note(f"{knob}[{key}] -> {got} at {ms:.4f} ms")
+    assert ms > 0.0
+    assert got in allowed
+
+
+@pytest.mark.parametrize("M", [2048, 3000, 4096, 8192, 210])
+def test_autotune_radix_schedule(ca, ctx, M):
+    note(f"autotune block_plan M={M}")
+    ms = ca.autotune("block_plan", M, ctx=ctx)
+    r = ca.tune_get("block_plan", M, ctx=ctx)
+    note(f"block_plan[{M}] -> {r} at {ms:.4f} ms")
+    assert ms > 0.0
+    assert int(np.prod(r)) == M and set(r) <= {2, 3, 4, 5, 7, 8}
+
+
+def test_autotune_rejects_unused_transform_size(ca, ctx):
+    # 7-smooth but above the zero-padded size of every n <= 4096 that maps near it
+    used = {transform_size(n) for n in range(2049, 4097) if not smooth7(n)}
+    bad = [m for m in range(4097, 8193) if smooth7(m) and m not in used][:1]
+    if not bad:
+        pytest.skip("every 7-smooth size in (4096, 8192] is used")
+    with pytest.raises(ca.CurveAlignError) as ei:
+        ca.autotune("block_plan", bad[0], ctx=ctx)
+    assert ei.value.status == ca.ERR_UNSUPPORTED_N
+
+
+def test_grid_and_tile_choices_are_bit_identical(ca, ctx):
+    z1, z2 = inputs.batch(700, 300, 256)
+    g1, g2 = gpu(z1), gpu(z2)
+    base = ca.align_batch(g1, g2, ctx=ctx).cpu()
+    for g in (2, 4, 8, 0):
+        ca.tune_set("team_grid", 256, g, ctx=ctx)
+        note(f"team_grid={g}")
+        assert torch.equal(ca.align_batch(g1, g2, ctx=ctx).cpu(), base), g
+    gal = gpu(inputs.gallery(701, 150, 128))
+    ref = ca.align_all_pairs(gal, ctx=ctx).cpu()
+    for cols in (1, 2, 8, 16, 32, 128, 256):
+        ca.tune_set("allpairs_cols", 128, cols, ctx=ctx)
+        note(f"allpairs_cols={cols}")
+        assert torch.equal(ca.align_all_pairs(gal, ctx=ctx).cpu(), ref), cols
+    d = inputs.ragged(702, 60, 64, 4096)
+    r1, r2, off = gpu(d["z1"]), gpu(d["z2"]), gpu(d["off"])
+    ref = ca.align_batch(r1, r2, offsets=off, ctx=ctx).cpu()
+    for g in (2, 4, 0):
+        for cls in range(5):
+            ca.tune_set("block_grid", cls, g, ctx=ctx)
+        note(f"block_grid={g} (all classes)")
+        assert torch.equal(ca.align_batch(r1, r2, offsets=off, ctx=ctx).cpu(), ref), g
+
+
+# (n, radix schedules of its transform size M); each product is M
+PLANS = [
+    (2000, [[8, 2, 5, 5, 5], [5, 5, 5, 8, 2], [4, 4, 5, 5, 5], [2, 8, 5, 5, 5]]),   # M = 2000
+    (1031, [[4, 3, 5, 5, 7], [7, 5, 5, 3, 4], [2, 2, 3, 5, 5, 7]]),                  # M = 2100 (padded)
+    (512, [[8, 8, 8], [4, 4, 4, 8], [2, 4, 4, 4, 4]]),                                # M = 512
+]
+
+
+@pytest.mark.parametrize("n,plans", PLANS)
+def test_radix_schedules_pass_acceptance(ca, ctx, n, plans):
+    M = transform_size(n)
+    for r in plans:
+        assert int(np.prod(r)) == M
+    B = 24
+    z1, z2 = inputs.batch(710 + n, B, n)
+    g1, g2 = gpu(z1), gpu(z2)
+    z1d, z2d = z1.astype(np.complex128), z2.astype(np.complex128)
+    g1d, g2d = gpu(z1d), gpu(z2d)
+    off = gpu(np.arange(B + 1, dtype=np.int64) * n)          # ragged form: always the block engine
+    f1, f2 = g1.reshape(-1), g2.reshape(-1)
+    for r in plans:
+        ca.tune_set("block_plan", M, r, ctx=ctx)
+        assert ca.tune_get("block_plan", M, ctx=ctx) == r
+        note(f"n={n} M={M} plan {r}")
+        rec = ca.to_numpy(ca.align_batch(f1, f2, offsets=off, ctx=ctx))
+        st = acc.check_batch(rec, z1, z2)
+        rec64 = ca.to_numpy(ca.align_batch(g1d, g2d, precision="fp64", ctx=ctx))
+        st64 = acc.check_batch(rec64, z1d, z2d, theta_tol=1e-10, e_rtol=1e-10)
+        note(f"  fp32 {st}\n  fp64 {st64}")
+
+
+def test_fp64_arena_built_after_plan_change(ca, ctx):
+    """A schedule installed before the first FP64 call is used when the FP64
+    twiddle arena is built."""
+    n, r = 1000, [5, 5, 5, 8]
+    ca.tune_set("block_plan", n, r, ctx=ctx)
+    z1, z2 = inputs.batch(720, 12, n)
+    z1d, z2d = z1.astype(np.complex128), z2.astype(np.complex128)
+    rec = ca.to_numpy(ca.align_batch(gpu(z1d), gpu(z2d), precision="fp64", ctx=ctx))
+    note(f"fp64 after plan change: {acc.check_batch(rec, z1d, z2d, theta_tol=1e-10, e_rtol=1e-10)}")
+
+
+def test_save_load_round_trip(ca, ctx, tmp_path):
+    ca.tune_set("team_grid", 512, 4, ctx=ctx)
+    ca.tune_set("allpairs_cols", 64, 32, ctx=ctx)
+    ca.tune_set("block_plan", 4096, [4, 4, 4, 8, 8], ctx=ctx)
+    ca.tune_set("block_grid", 3, 2, ctx=ctx)
+    path = str(tmp_path / "tune.json")
+    ca.tune_save(path, ctx=ctx)
+    text = open(path).read()
+    note(text)
+    other = ca.Context(0)
+    try:
+        assert ca.tune_load(path, ctx=other) == 4
+        assert ca.tune_get("team_grid", 512, ctx=other) == [4]
+        assert ca.tune_get("allpairs_cols", 64, ctx=other) == [32]
+        assert ca.tune_get("block_plan", 4096, ctx=other) == [4, 4, 4, 8, 8]
+        assert ca.tune_get("block_grid", 3, ctx=other) == [2]
+        assert ca.tune_get("team_grid", 1024, ctx=other) == [1]          # untouched default
+        # a file for another device installs nothing
+        foreign = tmp_path / "foreign.json"
+        foreign.write_text(text.replace('"num_cus": ', '"num_cus": 1'))
+        ca.tune_set("team_grid", 512, 2, ctx=other)
+        assert ca.tune_load(str(foreign), ctx=other) == 0
+        assert ca.tune_get("team_grid", 512, ctx=other) == [2]
+        # a malformed file is refused whole
+        broken = tmp_path / "broken.json"
+        broken.write_text(text.replace('"values": [32]', '"values": [0]'))
+        with pytest.raises(ca.CurveAlignError):
+            ca.tune_load(str(broken), ctx=other)
+        assert ca.tune_get("team_grid", 512, ctx=other) == [2]
+        # results with the loaded choices match the defaults
+        z1, z2 = inputs.batch(730, 40, 512)
+        a = ca.align_batch(gpu(z1), gpu(z2), ctx=other).cpu()
+        b = ca.align_batch(gpu(z1), gpu(z2), ctx=ca.default_context(0)).cpu()
+        assert torch.equal(a, b)
+    finally:
+        torch.cuda.synchronize()
+        other.close()
