@@ -118,6 +118,9 @@ template <int W, typename V> __device__ __forceinline__ V team_sum(V v) {
 template <int W> __device__ __forceinline__ float team_max(float v) {
     return team_reduce<W>(v, [](float a, float b) { return fmaxf(a, b); });
 }
+template <int W> __device__ __forceinline__ int team_max(int v) {
+    return team_reduce<W>(v, [](int a, int b) { return max(a, b); });
+}
 template <int W> __device__ __forceinline__ int team_min(int v) {
     return team_reduce<W>(v, [](int a, int b) { return min(a, b); });
 }

@@ -18,6 +18,8 @@
 // ~0.268^kRsW relative, far below FP32 rounding for kRsW = 12.
 #include <math.h>
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -348,6 +350,7 @@ constexpr int kFtK = 512;                  // knots per tile
 constexpr int kFtH = kRsW + 1;             // halo on each side
 constexpr int kFtP = kFtK + 2 * kFtH;      // staged knots
 constexpr int kFtC = 8;                    // knots per lane in the local solve
+constexpr int kFtSegMax = 24;              // most nodes per lane for lane-owned segments
 // Per-knot LDS arrays are padded with one slot per 8 entries: the local solve
 // and the scan give lane l the knots [8 l, 8 l + 8), a stride that would put
 // lanes 8 apart in the same bank.
@@ -366,6 +369,18 @@ __device__ __forceinline__ double wave_sum_d(double v) { return team_sum<64>(v);
 // Hardware reciprocal (1 ulp): the spline quantities are positive, finite and
 // far from the denormal range on the fast path.
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// Hardware square root (1 ulp), for chord lengths of the fast path: their
+// squares are positive normal numbers there, and a zero or non-finite chord
+// sends the curve to the general kernel.
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+// Lane i receives lane (i + 1) mod 64, resp. (i - 1) mod 64 (DPP wave
+// rotations; the whole wave must be active).
+__device__ __forceinline__ float wave_rol1(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x134, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float wave_ror1(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x13C, 0xF, 0xF, false));
+}
 
 __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw, const int64_t* __restrict__ raw_off,
                                                       int64_t num_curves, const int64_t* __restrict__ out_off,
@@ -390,41 +405,45 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
     const int M = general ? 0 : (int)mraw;
 
     // pass 1: perimeter, duplicates, non-finite values.  Eight vertices per
-    // lane per iteration, loads issued together; the successor of vertex j
-    // comes from the next lane (lane 63: the first lane of the next group),
-    // so only the vertex after the 512-vertex window is loaded twice.  The
-    // per-lane order of the chord sum is j = lane, lane + 64, ...
+    // lane per group of 512, loads issued together; the successor of vertex j
+    // comes from the next lane through a wave rotation (lane 63: the first
+    // lane of the next group), so only the vertex after the group is loaded
+    // twice.  Groups that end before the last vertex skip the range checks.
+    // The per-lane order of the chord sum is j = lane, lane + 64, ...
     double Ls = 0.0;
     int bad = 0;
     constexpr int kP1 = 8;
     const cf p0 = M > 0 ? P[0] : cf{0.0f, 0.0f};
-    for (int j0 = 0; j0 < M; j0 += 64 * kP1) {
+    auto group = [&](auto full, int j0) {
+        constexpr bool kFull = decltype(full)::value;
         cf a[kP1 + 1];
 #pragma unroll
         for (int u = 0; u < kP1; ++u) {
             const int j = j0 + lane + 64 * u;
-            a[u] = P[j < M ? j : 0];
+            a[u] = P[(kFull || j < M) ? j : 0];
         }
-        a[kP1] = P[j0 + 64 * kP1 < M ? j0 + 64 * kP1 : 0];
+        a[kP1] = P[(kFull || j0 + 64 * kP1 < M) ? j0 + 64 * kP1 : 0];
 #pragma unroll
         for (int u = 0; u < kP1; ++u) {
             const int j = j0 + lane + 64 * u;
-            cf b;
-            b.x = __shfl(a[u].x, (lane + 1) & 63, 64);
-            b.y = __shfl(a[u].y, (lane + 1) & 63, 64);
+            cf b = {wave_rol1(a[u].x), wave_rol1(a[u].y)};
             const float nx = rdlane(a[u + 1].x, 0), ny = rdlane(a[u + 1].y, 0);
             if (lane == 63) {
                 b.x = nx;
                 b.y = ny;
             }
-            if (j + 1 == M) b = p0;            // closing chord back to vertex 0
-            if (j < M) {
+            if (!kFull && j + 1 == M) b = p0;  // closing chord back to vertex 0
+            if (kFull || j < M) {
                 const float dx = b.x - a[u].x, dy = b.y - a[u].y;
-                const float h = sqrtf(dx * dx + dy * dy);
+                const float h = fsqrt(dx * dx + dy * dy);
                 if (!(h > 0.0f) || !isfinite(h)) bad = 1;
                 Ls += (double)h;
             }
         }
+    };
+    for (int j0 = 0; j0 < M; j0 += 64 * kP1) {
+        if (j0 + 64 * kP1 < M) group(std::true_type{}, j0);
+        else group(std::false_type{}, j0);
     }
     general = general || (__ballot(bad) != 0ull);
     if (general) {
@@ -442,7 +461,7 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
     double carry = 0.0;                        // arc length at knot a
     double sx = 0.0, sy = 0.0;
     constexpr int kStage = (kFtP + 63) / 64;   // staged vertices per lane
-    cf pre[kStage];                            // next tile's vertices, loaded ahead
+    cf pre[kStage] = {};                       // next tile's vertices, loaded ahead
     // staged knot j of the tile at a reads vertex a - kFtH + j (cyclic); with
     // M >= kFtP one correction by M suffices
     const bool wide = M >= kFtP;
@@ -452,48 +471,63 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
         const int i = lane + 64 * u;
         if (i < kFtP) pre[u] = P[vert(i - kFtH)];
     }
-    // LDS index of staged knot lane + 64 u is kpl + 72 u (kp adds one slot per
-    // eight), of knots lane + 1 + 64 u and lane + 2 + 64 u kp1 + 72 u, kp2 + 72 u
-    const int kpl = kp(lane), kp1 = kp(lane + 1), kp2 = kp(lane + 2);
+    // LDS index of staged knot lane + 64 u is kpl + 72 u (kp adds one slot per eight)
+    const int kpl = kp(lane);
     for (int a = 0; a < M; a += kFtK - 1) {
         const bool last = (a + kFtK - 1 >= M);
         const int kt = last ? (M - a + 1) : kFtK;       // knots in this tile incl. the right end
-        // stage knots a - kFtH .. a + kFtK + kFtH - 1 (cyclic), then start
-        // loading the next tile's
+        // stage knots a - kFtH .. a + kFtK + kFtH - 1 (cyclic) with their chord
+        // lengths and, for the spline, the right-hand sides 6 (D_i - D_{i-1}),
+        // all from registers: the successor of staged knot lane + 64 u is the
+        // next lane's (lane 63: lane 0 of u + 1), the slope D_{i-1} the
+        // previous lane's (lane 0: lane 63 of u - 1)
+        cf dprev = {0.0f, 0.0f};
 #pragma unroll
         for (int u = 0; u < kStage; ++u) {
-            if (lane + 64 * u < kFtP) sP[kpl + 72 * u] = pre[u];
+            const int i = lane + 64 * u;
+            cf q = {wave_rol1(pre[u].x), wave_rol1(pre[u].y)};
+            if (u + 1 < kStage) {
+                const float nx = rdlane(pre[u + 1].x, 0), ny = rdlane(pre[u + 1].y, 0);
+                if (lane == 63) {
+                    q.x = nx;
+                    q.y = ny;
+                }
+            }
+            const float dx = q.x - pre[u].x, dy = q.y - pre[u].y;
+            const float h = fsqrt(dx * dx + dy * dy);
+            if (i < kFtP) sP[kpl + 72 * u] = pre[u];
+            if (i < kFtP - 1) sH[kpl + 72 * u] = h;
+            if (mode == CA_RESAMPLE_SPLINE) {
+                const float ih = frcp(h);
+                const cf d = {dx * ih, dy * ih};
+                cf dm = {wave_ror1(d.x), wave_ror1(d.y)};
+                const float px = rdlane(dprev.x, 63), py = rdlane(dprev.y, 63);
+                if (lane == 0) {
+                    dm.x = px;
+                    dm.y = py;
+                }
+                if (i >= 1 && i < kFtP - 1) sR[kpl + 72 * u] = {6.0f * (d.x - dm.x), 6.0f * (d.y - dm.y)};
+                dprev = d;
+            }
         }
+        // start loading the next tile's vertices (no wrap-around except near the end)
         if (!last) {
-            const int an = a + kFtK - 1;
+            const int b0 = a + kFtK - 1 - kFtH;
+            if (b0 + kFtP <= M) {
 #pragma unroll
-            for (int u = 0; u < kStage; ++u) {
-                const int i = lane + 64 * u;
-                if (i < kFtP) pre[u] = P[vert(an - kFtH + i)];
-            }
-        }
-        wave_lds_sync();
+                for (int u = 0; u < kStage; ++u) {
+                    const int i = lane + 64 * u;
+                    if (i < kFtP) pre[u] = P[b0 + i];
+                }
+            } else {
 #pragma unroll
-        for (int u = 0; u < kStage; ++u) {
-            if (lane + 64 * u < kFtP - 1) {
-                const cf p = sP[kpl + 72 * u], q = sP[kp1 + 72 * u];
-                const float dx = q.x - p.x, dy = q.y - p.y;
-                sH[kpl + 72 * u] = sqrtf(dx * dx + dy * dy);
-            }
-        }
-        wave_lds_sync();
-        if (mode == CA_RESAMPLE_SPLINE) {
-#pragma unroll
-            for (int u = 0; u < kStage; ++u) {
-                if (lane + 1 + 64 * u < kFtP - 1) {
-                    const cf pm = sP[kpl + 72 * u], p = sP[kp1 + 72 * u], q = sP[kp2 + 72 * u];
-                    const float hm = sH[kpl + 72 * u], h = sH[kp1 + 72 * u];
-                    const float ih = frcp(h), ihm = frcp(hm);
-                    sR[kp1 + 72 * u] = {6.0f * ((q.x - p.x) * ih - (p.x - pm.x) * ihm),
-                                        6.0f * ((q.y - p.y) * ih - (p.y - pm.y) * ihm)};
+                for (int u = 0; u < kStage; ++u) {
+                    const int i = lane + 64 * u;
+                    if (i < kFtP) pre[u] = P[vert(b0 + i)];
                 }
             }
         }
+        wave_lds_sync();
         // tile-relative arc length: lane owns local knots [8 lane, 8 lane + 8)
         float loc[kFtC];
         double acc = 0.0;
@@ -587,15 +621,48 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
         const int nlo = (int)ceil(carry / uN);
         const int nhi = last ? N : min(N, (int)ceil((carry + span) / uN));
         const float il = (float)invL;
-        for (int nn = nlo + lane; nn < nhi; nn += 64) {
-            const float u = (float)((double)nn * uN - carry);
-            // largest j in [0, kt - 2] with sS[j] <= u
-            int lo = 0, hi = kt - 2;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (sS[kp(mid)] <= u) lo = mid; else hi = mid - 1;
+        auto upar = [&](int nn) { return (float)((double)nn * uN - carry); };
+        // Node nn lies on segment j = the largest j in [0, kt - 2] with
+        // sS[j] <= upar(nn) (j = 0 below sS[0]).  Since upar and sS are
+        // non-decreasing, the nodes of lane l's segments [8 l, 8 l + 8) are the
+        // contiguous range [first(8 l), first(8 l + 8)), first(j) being the
+        // smallest node at or after sS[j]; each lane places its own range with
+        // one LDS round trip per node.  Tiles with many nodes per knot fall
+        // back to one node per lane and a binary search.
+        const int j0 = kFtC * lane;
+        int ns = nhi;
+        if (j0 == 0) {
+            ns = nlo;
+        } else if (j0 <= kt - 2) {
+            const float s0 = sS[kp(j0)];
+            int e = (int)ceil((carry + (double)s0) / uN);
+            e = max(nlo, min(nhi, e));
+            while (e > nlo && upar(e - 1) >= s0) --e;
+            while (e < nhi && upar(e) < s0) ++e;
+            ns = e;
+        }
+        int ne = __shfl_down(ns, 1, 64);
+        if (lane == 63) ne = nhi;
+        const bool seg = team_max<64>(ne - ns) <= kFtSegMax;
+        float sk[kFtC];                        // this lane's knot parameters
+#pragma unroll
+        for (int k = 1; k < kFtC; ++k) sk[k] = (j0 + k <= kt - 2) ? sS[kp(j0 + k)] : 3.0e38f;
+        const int nbeg = seg ? ns : nlo + lane, nend = seg ? ne : nhi, nstep = seg ? 1 : 64;
+        for (int nn = nbeg; nn < nend; nn += nstep) {
+            const float u = upar(nn);
+            int j;
+            if (seg) {
+                j = j0;
+#pragma unroll
+                for (int k = 1; k < kFtC; ++k) j += sk[k] <= u ? 1 : 0;
+            } else {
+                int lo = 0, hi = kt - 2;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (sS[kp(mid)] <= u) lo = mid; else hi = mid - 1;
+                }
+                j = lo;
             }
-            const int j = lo;
             const float hj = sH[kp(kFtH + j)];
             const float bb = u - sS[kp(j)];
             const float aa = hj - bb;
@@ -630,12 +697,24 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
     sy = wave_sum_d(sy);
     const float mx = (float)(sx / N), my = (float)(sy / N);
     double q2 = 0.0;
-    for (int nn = lane; nn < N; nn += 64) {
-        cf z = o[nn];
-        z.x -= mx;
-        z.y -= my;
-        o[nn] = z;
-        q2 = fma((double)z.x, (double)z.x, fma((double)z.y, (double)z.y, q2));
+    for (int n0 = 0; n0 < N; n0 += 64 * 8) {   // eight loads in flight per lane
+        cf zz[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int nn = n0 + lane + 64 * u;
+            if (nn < N) zz[u] = o[nn];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int nn = n0 + lane + 64 * u;
+            if (nn < N) {
+                cf z = zz[u];
+                z.x -= mx;
+                z.y -= my;
+                o[nn] = z;
+                q2 = fma((double)z.x, (double)z.x, fma((double)z.y, (double)z.y, q2));
+            }
+        }
     }
     q2 = wave_sum_d(q2);
     if (lane == 0) {
