@@ -51,6 +51,14 @@ def clean_polygon(P: np.ndarray) -> np.ndarray:
     return P[keep]
 
 
+def signed_area(P: np.ndarray) -> float:
+    """Shoelace area of the closed polygon P (K, 2), positive when the vertices
+    run counter-clockwise (the orientation the paper assumes, section 1)."""
+    P = np.asarray(P, dtype=np.float64).reshape(-1, 2)
+    x, y = P[:, 0], P[:, 1]
+    return 0.5 * float(np.sum(x * np.roll(y, -1) - np.roll(x, -1) * y))
+
+
 def arclength_parameters(P: np.ndarray):
     """Eq. (arc-length-param) for a closed polygon.
 
@@ -116,9 +124,10 @@ def resample(P, n: int, mode: int = SPLINE):
     """Raw closed polygon (K, 2) -> n centred unit-length nodes (complex128).
 
     Returns (z, info) where info holds the cleaned polygon size, the
-    perimeter L and the squared norm (1/n) sum |z|^2.  A polygon with fewer
-    than 3 distinct vertices or zero perimeter is degenerate: z is all zero
-    and info['degenerate'] is True.
+    perimeter L, the squared norm (1/n) sum |z|^2 and the signed area of the
+    cleaned polygon (negative: clockwise vertices, kept in the given order).
+    A polygon with fewer than 3 distinct vertices or zero perimeter is
+    degenerate: z is all zero and info['degenerate'] is True.
     """
     Q = clean_polygon(P)
     K = len(Q)
@@ -134,4 +143,5 @@ def resample(P, n: int, mode: int = SPLINE):
     X = evaluate(s, h, Q, M, t) / L
     z = X[:, 0] + 1j * X[:, 1]
     z = z - z.mean()
-    return z, {"K": K, "L": L, "degenerate": False, "sqnorm": float(np.mean(np.abs(z) ** 2))}
+    return z, {"K": K, "L": L, "degenerate": False, "sqnorm": float(np.mean(np.abs(z) ** 2)),
+               "area": signed_area(Q)}

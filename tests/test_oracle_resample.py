@@ -148,3 +148,35 @@ def test_degenerate_inputs():
     assert info["degenerate"] and np.all(z == 0)
     z, info = rr.resample(np.array([[1.0, 1.0]] * 5), 16)
     assert info["degenerate"]
+
+
+def test_signed_area_pins():
+    """Shoelace area: the unit square, a triangle's half cross product, a
+    regular n-gon's closed form (n/2) sin(2 pi / n) r^2; sign flips with the
+    vertex order, value invariant under translation, rotation and a change
+    of starting vertex, scaled by s^2."""
+    sq = np.array([[0, 0], [1, 0], [1, 1], [0, 1]], float)
+    assert rr.signed_area(sq) == 1.0
+    assert rr.signed_area(sq[::-1]) == -1.0
+    a, b, c = np.array([0.3, -0.2]), np.array([2.0, 0.5]), np.array([0.7, 1.9])
+    cross = (b - a)[0] * (c - a)[1] - (b - a)[1] * (c - a)[0]
+    assert abs(rr.signed_area(np.stack([a, b, c])) - 0.5 * cross) < 1e-15
+    for n in (3, 7, 64):
+        t = 2 * np.pi * np.arange(n) / n
+        P = 1.7 * np.stack([np.cos(t), np.sin(t)], 1)
+        assert abs(rr.signed_area(P) - 0.5 * n * np.sin(2 * np.pi / n) * 1.7 ** 2) < 1e-12
+    rng = np.random.default_rng(3)
+    t = np.sort(rng.uniform(0, 2 * np.pi, 50))
+    P = np.stack([(1 + 0.2 * np.cos(3 * t)) * np.cos(t), (1 + 0.2 * np.cos(3 * t)) * np.sin(t)], 1)
+    A = rr.signed_area(P)
+    assert A > 0
+    th = 0.8
+    R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+    assert abs(rr.signed_area(P @ R.T + [5.0, -3.0]) - A) < 1e-12
+    assert abs(rr.signed_area(np.roll(P, 17, axis=0)) - A) < 1e-12
+    assert abs(rr.signed_area(2.5 * P) - 6.25 * A) < 1e-12
+    # the resampler reports the cleaned polygon's area
+    z, info = rr.resample(np.vstack([P, P[:1]]), 64)
+    assert abs(info["area"] - A) < 1e-12
+    z, info = rr.resample(P[::-1], 64)
+    assert abs(info["area"] + A) < 1e-12
