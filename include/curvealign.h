@@ -79,7 +79,9 @@ enum {
                                        e0 = n1 + n2                                  */
     CA_FLAG_NONFINITE = 1u << 4,    /* NaN/Inf in the input; shift 0, theta 0, e0 NaN */
     CA_FLAG_THETA_FP64 = 1u << 5,   /* theta taken from the FP64 C(s*)               */
-    CA_FLAG_UNSUPPORTED_N = 1u << 6 /* ragged pair with an unsupported n; not aligned */
+    CA_FLAG_UNSUPPORTED_N = 1u << 6, /* ragged pair with an unsupported n; not aligned */
+    CA_FLAG_CLOCKWISE = 1u << 7      /* resample_arclength: the polygon's signed area is
+                                        negative (vertices run clockwise)             */
 };
 
 enum { CA_PREC_FP32 = 0, CA_PREC_SPLIT_BF16 = 1, CA_PREC_FP64 = 2 };
@@ -176,7 +178,11 @@ ca_status_t align_all_pairs(ca_context_t ctx, const void* curves, int32_t m, int
  *   norms_out   : optional FP64 (1/n) sum |z|^2 per curve (NULL to skip)
  *   flags_out   : optional uint32 per curve; CA_FLAG_DEGENERATE when fewer than
  *                 3 distinct vertices remain or the perimeter is zero (nodes
- *                 are then 0); CA_FLAG_NONFINITE for NaN/Inf vertices
+ *                 are then 0); CA_FLAG_NONFINITE for NaN/Inf vertices;
+ *                 otherwise CA_FLAG_CLOCKWISE when the cleaned polygon's
+ *                 signed (shoelace) area is negative.  Section 1 takes both
+ *                 curves counter-clockwise; the nodes keep the given order, and
+ *                 a pair whose curves differ in this flag is aligned as given
  *   mode        : CA_RESAMPLE_SPLINE (periodic C2 cubic spline through the
  *                 arc-length knots) or CA_RESAMPLE_LINEAR
  * Input rules: vertices are counter-clockwise and not closed; trailing copies

@@ -38,6 +38,7 @@ FLAG_DEGENERATE = 1 << 3
 FLAG_NONFINITE = 1 << 4
 FLAG_THETA_FP64 = 1 << 5
 FLAG_UNSUPPORTED_N = 1 << 6
+FLAG_CLOCKWISE = 1 << 7
 
 PRECISION = {"fp32": 0, "split_bf16": 1, "fp64": 2}
 RESCORE = {"top2": 0, "window": 1}

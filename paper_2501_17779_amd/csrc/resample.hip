@@ -223,8 +223,10 @@ __global__ __launch_bounds__(kRsNT) void k_resample(const cf* __restrict__ raw, 
 
         // chord lengths and their FP64 exclusive scan: L_j = sum_{i<j} |Q_{i+1} - Q_i|
         double L = 0.0;
+        double area2 = 0.0;                    // twice the signed area of the cleaned polygon
         if (!fl) {
             double carry = 0.0;
+            const cf q0 = S.Q[0];
             for (int base = 0; base < K; base += kRsNT) {
                 const int j = base + tid;
                 double hj = 0.0;
@@ -234,6 +236,7 @@ __global__ __launch_bounds__(kRsNT) void k_resample(const cf* __restrict__ raw, 
                     const float hf = sqrtf(dx * dx + dy * dy);
                     hj = hf;
                     S.h[j] = hf;
+                    area2 += (double)(a.x - q0.x) * dy - (double)(a.y - q0.y) * dx;
                 }
                 double tot;
                 const double pre = rs_exscan(hj, shd, tot);
@@ -242,6 +245,7 @@ __global__ __launch_bounds__(kRsNT) void k_resample(const cf* __restrict__ raw, 
             }
             L = carry;
             if (!(L > 0.0)) fl = CA_FLAG_DEGENERATE;
+            area2 = rs_sum(area2, shd);
         }
         __syncthreads();
         const double invL = fl ? 0.0 : 1.0 / L;
@@ -330,7 +334,7 @@ __global__ __launch_bounds__(kRsNT) void k_resample(const cf* __restrict__ raw, 
         q2 = rs_sum(q2, shd);
         if (tid == 0) {
             if (norms) norms[c] = q2 / N;
-            if (flags) flags[c] = fl;
+            if (flags) flags[c] = fl ? fl : (area2 < 0.0 ? CA_FLAG_CLOCKWISE : 0u);
         }
         __syncthreads();
     }
@@ -411,6 +415,7 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
     // twice.  Groups that end before the last vertex skip the range checks.
     // The per-lane order of the chord sum is j = lane, lane + 64, ...
     double Ls = 0.0;
+    float ar = 0.0f;
     int bad = 0;
     constexpr int kP1 = 8;
     const cf p0 = M > 0 ? P[0] : cf{0.0f, 0.0f};
@@ -438,6 +443,8 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
                 const float h = fsqrt(dx * dx + dy * dy);
                 if (!(h > 0.0f) || !isfinite(h)) bad = 1;
                 Ls += (double)h;
+                // twice the signed area: sum of (a - p0) x (b - a) over the chords
+                ar = fmaf(a[u].x - p0.x, dy, fmaf(-(a[u].y - p0.y), dx, ar));
             }
         }
     };
@@ -454,6 +461,7 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
         return;
     }
     const double L = wave_sum_d(Ls);
+    const double area2 = wave_sum_d((double)ar);
     const double invL = 1.0 / L;
     const double uN = L / (double)N;           // arc length between output nodes
 
@@ -719,7 +727,7 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
     q2 = wave_sum_d(q2);
     if (lane == 0) {
         if (norms) norms[c] = q2 / N;
-        if (flags) flags[c] = 0;
+        if (flags) flags[c] = area2 < 0.0 ? CA_FLAG_CLOCKWISE : 0u;
     }
 }
 

@@ -68,9 +68,10 @@ int main(void) {
            offsetof(ca_result_t, err_est), offsetof(ca_result_t, gap));
     printf("\"status\": [%d, %d, %d, %d, %d, %d],\n", CA_OK, CA_ERR_INVALID_ARG, CA_ERR_UNSUPPORTED_N,
            CA_ERR_HIP, CA_ERR_OOM, CA_ERR_NO_DEVICE);
-    printf("\"flags\": [%u, %u, %u, %u, %u, %u, %u],\n", (unsigned)CA_FLAG_NEAR_TIE,
+    printf("\"flags\": [%u, %u, %u, %u, %u, %u, %u, %u],\n", (unsigned)CA_FLAG_NEAR_TIE,
            (unsigned)CA_FLAG_RESCORED, (unsigned)CA_FLAG_CAND_CAPPED, (unsigned)CA_FLAG_DEGENERATE,
-           (unsigned)CA_FLAG_NONFINITE, (unsigned)CA_FLAG_THETA_FP64, (unsigned)CA_FLAG_UNSUPPORTED_N);
+           (unsigned)CA_FLAG_NONFINITE, (unsigned)CA_FLAG_THETA_FP64, (unsigned)CA_FLAG_UNSUPPORTED_N,
+           (unsigned)CA_FLAG_CLOCKWISE);
     printf("\"prec\": [%d, %d, %d], \"rescore\": [%d, %d], \"resample\": [%d, %d], \"max_n\": %d}\n",
            CA_PREC_FP32, CA_PREC_SPLIT_BF16, CA_PREC_FP64, CA_RESCORE_TOP2, CA_RESCORE_WINDOW,
            CA_RESAMPLE_SPLINE, CA_RESAMPLE_LINEAR, CA_MAX_N);
@@ -94,7 +95,7 @@ def test_header_layout_matches_binding(tmp_path):
     assert h["status"] == [ca.OK, ca.ERR_INVALID_ARG, ca.ERR_UNSUPPORTED_N, ca.ERR_HIP, ca.ERR_OOM,
                            ca.ERR_NO_DEVICE]
     assert h["flags"] == [ca.FLAG_NEAR_TIE, ca.FLAG_RESCORED, ca.FLAG_CAND_CAPPED, ca.FLAG_DEGENERATE,
-                          ca.FLAG_NONFINITE, ca.FLAG_THETA_FP64, ca.FLAG_UNSUPPORTED_N]
+                          ca.FLAG_NONFINITE, ca.FLAG_THETA_FP64, ca.FLAG_UNSUPPORTED_N, ca.FLAG_CLOCKWISE]
     assert h["prec"] == [ca.PRECISION[k] for k in ("fp32", "split_bf16", "fp64")]
     assert h["rescore"] == [ca.RESCORE[k] for k in ("top2", "window")]
     assert h["resample"] == [ca.RESAMPLE[k] for k in ("spline", "linear")]

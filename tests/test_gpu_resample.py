@@ -117,3 +117,24 @@ def test_resample_full_size_sampled(ca):
         worst = max(worst, err)
         assert err <= TOL_POS
     note(f"full-size resample: worst sampled node error {worst:.3g}")
+
+
+def test_clockwise_flag(ca):
+    """CA_FLAG_CLOCKWISE follows the sign of the oracle's signed area, on the
+    fast kernel and on the general one (a curve with repeated vertices), for
+    curves far from the origin too; reversing a polygon reverses its nodes'
+    orientation and sets the flag."""
+    d = curves.ragged_pairs(78, 12, 64, 1024)
+    polys = [d["raw1"][d["off1"][b]:d["off1"][b + 1]] for b in range(12)]
+    polys = polys + [p[::-1].copy() for p in polys]
+    far = polys[0] + np.float32([300.0, -200.0])
+    polys += [far, far[::-1].copy()]
+    dup = np.vstack([polys[1][:5], polys[1][4:5], polys[1][5:]])          # general kernel
+    polys += [dup, dup[::-1].copy()]
+    ns = [128] * len(polys)
+    out, ooff, norms, flags = run(ca, polys, ns, "spline")
+    for c, p in enumerate(polys):
+        area = rr.resample(p.astype(np.float64), 128)[1]["area"]
+        want = ca.FLAG_CLOCKWISE if area < 0 else 0
+        assert flags[c] == want, (c, area, flags[c])
+    assert sum(int(f) == ca.FLAG_CLOCKWISE for f in flags) == len(polys) // 2
