@@ -4,6 +4,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -201,38 +202,40 @@ ca_status_t ensure_tables(ca_context* c, bool need64) {
     return CA_OK;
 }
 
-ca_status_t upload_block_plan(ca_context* c, int m) {
-    if (!c->d_plans) return CA_OK;             // the tables are built later with the new schedule
-    hipError_t e = hipDeviceSynchronize();     // no kernel may read the tables while they change
+ca_status_t upload_block_plans(ca_context* c, const std::vector<int>& sizes) {
+    if (!c->d_plans || sizes.empty()) return CA_OK;   // tables not built yet: built later with the new schedules
+    hipError_t e = hipDeviceSynchronize();            // no kernel may read the tables while they change
     if (e != hipSuccess) return hip_fail(e, "synchronise before the plan update");
-    const std::vector<int> r = radices_for(c, m);
     for (int n = 2; n <= CA_MAX_N; ++n) {
-        if (c->h_plans[n].n != m) continue;
+        const int m = c->h_plans[n].n;
+        if (std::find(sizes.begin(), sizes.end(), m) == sizes.end()) continue;
         const int64_t off = c->h_plans[n].tw_off;
-        c->h_plans[n] = plan_from(m, r);
+        c->h_plans[n] = plan_from(m, radices_for(c, m));
         c->h_plans[n].tw_off = off;
     }
     if ((e = hipMemcpy(c->d_plans, c->h_plans.data(), sizeof(Plan) * (CA_MAX_N + 1),
                        hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "plan upload");
     std::vector<double> pre, pim;
-    block_twiddles(c, m, pre, pim);
-    const size_t cnt = pre.size();
-    std::vector<float> t32(2 * cnt);
-    std::vector<double> t64(2 * cnt);
-    for (size_t k = 0; k < cnt; ++k) {
-        t32[2 * k] = (float)pre[k];
-        t32[2 * k + 1] = (float)pim[k];
-        t64[2 * k] = pre[k];
-        t64[2 * k + 1] = pim[k];
+    for (int m : sizes) {
+        block_twiddles(c, m, pre, pim);
+        const size_t cnt = pre.size();
+        std::vector<float> t32(2 * cnt);
+        std::vector<double> t64(2 * cnt);
+        for (size_t k = 0; k < cnt; ++k) {
+            t32[2 * k] = (float)pre[k];
+            t32[2 * k + 1] = (float)pim[k];
+            t64[2 * k] = pre[k];
+            t64[2 * k + 1] = pim[k];
+        }
+        const int64_t off = c->tw_off[m];
+        if ((e = hipMemcpy((float*)c->d_tw32 + 2 * off, t32.data(), t32.size() * sizeof(float),
+                           hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "twiddle upload");
+        if (c->d_tw64 && (e = hipMemcpy((double*)c->d_tw64 + 2 * off, t64.data(),
+                                        t64.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "FP64 twiddle upload");
     }
-    const int64_t off = c->tw_off[m];
-    if ((e = hipMemcpy((float*)c->d_tw32 + 2 * off, t32.data(), t32.size() * sizeof(float),
-                       hipMemcpyHostToDevice)) != hipSuccess)
-        return hip_fail(e, "twiddle upload");
-    if (c->d_tw64 && (e = hipMemcpy((double*)c->d_tw64 + 2 * off, t64.data(), t64.size() * sizeof(double),
-                                    hipMemcpyHostToDevice)) != hipSuccess)
-        return hip_fail(e, "FP64 twiddle upload");
     return CA_OK;
 }
 

@@ -96,9 +96,9 @@ struct DeviceGuard {
 ca_status_t ensure_tables(ca_context* c, bool need64);
 ca_status_t ensure_team_tables(ca_context* c);
 const void* team_tw_for(ca_context* c, int n);
-// Installs the current radix schedule of transform size m in the device plan
-// table and both twiddle arenas (synchronises the device first).
-ca_status_t upload_block_plan(ca_context* c, int m);
+// Installs the current radix schedules of the given transform sizes in the
+// device plan table and both twiddle arenas (synchronises the device first).
+ca_status_t upload_block_plans(ca_context* c, const std::vector<int>& sizes);
 
 inline int team_key(int n) {
     int lg = 0;

@@ -125,8 +125,9 @@ bool is_default(int knob, int key, const std::vector<int>& v) {
     }
 }
 
-// Installs validated values (device tables of a radix schedule included).
-ca_status_t install(ca_context* c, int knob, int key, const std::vector<int>& v, float ms) {
+// Installs validated values; a radix schedule also goes to the device tables
+// unless `upload` is false (the caller then uploads a batch of sizes).
+ca_status_t install(ca_context* c, int knob, int key, const std::vector<int>& v, float ms, bool upload = true) {
     switch (knob) {
         case CA_TUNE_TEAM_GRID: c->tune.team_grid[team_key(key)] = v[0]; break;
         case CA_TUNE_ALLPAIRS_COLS: c->tune.allpairs_cols[team_key(key)] = v[0]; break;
@@ -139,7 +140,7 @@ ca_status_t install(ca_context* c, int knob, int key, const std::vector<int>& v,
     const auto id = std::make_pair(knob, key);
     if (is_default(knob, key, v) && ms < 0.0f) c->tune.ms.erase(id);
     else c->tune.ms[id] = ms;
-    if (knob == CA_TUNE_BLOCK_PLAN) return upload_block_plan(c, key);
+    if (knob == CA_TUNE_BLOCK_PLAN && upload) return upload_block_plans(c, {key});
     return CA_OK;
 }
 
@@ -353,7 +354,7 @@ ca_status_t autotune(ca_context* c, int knob, int key, hipStream_t s, float& bes
             if (knob == CA_TUNE_BLOCK_PLAN) {
                 if (v == default_radices(key)) c->tune.blk_plan.erase(key);
                 else c->tune.blk_plan[key] = v;
-                if ((st = upload_block_plan(c, key)) != CA_OK) break;
+                if ((st = upload_block_plans(c, {key})) != CA_OK) break;
             }
             ca::BlkArgs a = blk_args(c, z1.p, z2.p, n, pairs, (ca_result_t*)out.p);
             if (knob == CA_TUNE_BLOCK_GRID) a.grid_mult[key] = v[0];
@@ -653,10 +654,13 @@ ca_status_t ca_tune_load(ca_context_t c, const char* path, int32_t* applied) {
     if (arch != c->arch || cus != c->num_cus) return CA_OK;
     DeviceGuard g(c->device);
     int32_t n = 0;
+    std::vector<int> plans;
     for (const Entry& e : entries) {
-        if ((st = install(c, e.knob, e.key, e.values, e.ms)) != CA_OK) return st;
+        if ((st = install(c, e.knob, e.key, e.values, e.ms, false)) != CA_OK) return st;
+        if (e.knob == CA_TUNE_BLOCK_PLAN) plans.push_back(e.key);
         ++n;
     }
+    if ((st = upload_block_plans(c, plans)) != CA_OK) return st;
     if (applied) *applied = n;
     return CA_OK;
 }
