@@ -241,9 +241,10 @@ ca_status_t srv_transform(ca_context_t ctx, const void* curves, const int64_t* o
  * Launch tuning.  The kernels above take a few launch choices at run time;
  * each context holds one value per (knob, key), starting from defaults that
  * need no tuning.  A choice changes how work is scheduled, never what is
- * computed: grid and tile knobs give bit-identical results, and a radix
- * schedule changes only the rounding order of the FFT (results stay within
- * the error bound every record reports).
+ * computed: grid and tile knobs give bit-identical results; a radix
+ * schedule changes the rounding order of the FFT and a thread count that of
+ * the FP64 norm and re-scoring sums (results stay within the error bound
+ * every record reports).
  *
  *   knob                    key                          values (count)
  *   CA_TUNE_TEAM_GRID       n in {64,...,1024}           1: persistent blocks per CU of
@@ -262,19 +263,30 @@ ca_status_t srv_transform(ca_context_t ctx, const void* curves, const int64_t* o
  *                           engine (M <= 512, 1024, 2048,   multiples of the occupancy limit,
  *                           4096, 8192)                     1..8, or 0 for one block per pair
  *                                                           (default 1)
+ *   CA_TUNE_BLOCK_THREADS   size class 3 or 4            1: threads per block of the FP32
+ *                                                           class kernel, 256 or 512 (defaults
+ *                                                           256 for class 3, 512 for class 4;
+ *                                                           FP64 keeps 256)
  *
  * ca_tune_set and ca_tune_load change the tables the kernels read: they
  * synchronise the device first and must not be called while work of this
  * context is in flight on another stream or during stream capture.
  */
-enum { CA_TUNE_TEAM_GRID = 0, CA_TUNE_ALLPAIRS_COLS = 1, CA_TUNE_BLOCK_PLAN = 2, CA_TUNE_BLOCK_GRID = 3 };
+enum {
+    CA_TUNE_TEAM_GRID = 0,
+    CA_TUNE_ALLPAIRS_COLS = 1,
+    CA_TUNE_BLOCK_PLAN = 2,
+    CA_TUNE_BLOCK_GRID = 3,
+    CA_TUNE_BLOCK_THREADS = 4
+};
 
 /*
  * ca_autotune -- measure every candidate of one (knob, key) on a synthetic
  * batch that the library generates on the device (smooth star-shaped curves
  * with rotated, shifted templates; about 2^25 nodes per side), install the
  * fastest and report its time per launch in *best_ms (optional).  Candidates:
- * grid knobs 1, 2, 4 and 0; all-pairs columns 2, 4, 8, 16, 32, 64; radix
+ * grid knobs 1, 2, 4 and 0; all-pairs columns 2, 4, 8, 16, 32, 64; threads
+ * 256 and 512; radix
  * schedules: the orderings of the power-of-two part as eights, fours or
  * mixed, each with the odd radices first or last.  Each candidate is timed
  * with HIP events over three launches after one warm-up launch on `stream`.
@@ -299,7 +311,8 @@ ca_status_t ca_tune_set(ca_context_t ctx, int32_t knob, int32_t key, const int32
  * file (host path):
  *   {"format": "curvealign-tune/1", "arch": "gfx950", "num_cus": 256,
  *    "entries": [{"knob": "team_grid", "key": 1024, "values": [2], "ms": 0.41}, ...]}
- * knob names: team_grid, allpairs_cols, block_plan, block_grid; "ms" is the
+ * knob names: team_grid, allpairs_cols, block_plan, block_grid, block_threads;
+ * "ms" is the
  * time ca_autotune measured (-1 for values set by hand).
  * ca_tune_load -- read such a file and install its entries.  The whole file
  * is validated before anything is installed: a file that cannot be read or

@@ -50,7 +50,7 @@ EXPORTED = ("ca_create", "ca_destroy", "ca_status_string", "ca_last_error", "ca_
             "srv_transform", "ca_autotune", "ca_tune_get", "ca_tune_set", "ca_tune_save", "ca_tune_load")
 
 # launch-tuning knobs (ca_autotune / ca_tune_*)
-TUNE_KNOBS = {"team_grid": 0, "allpairs_cols": 1, "block_plan": 2, "block_grid": 3}
+TUNE_KNOBS = {"team_grid": 0, "allpairs_cols": 1, "block_plan": 2, "block_grid": 3, "block_threads": 4}
 # tuning cache shipped with the package, loaded by default_context when it
 # matches the device; CURVEALIGN_TUNE_FILE names another file ("" = none)
 TUNE_CACHE = os.path.join(_HERE, "tune_cache.json")

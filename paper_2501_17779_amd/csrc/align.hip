@@ -506,7 +506,8 @@ static hipError_t launch_blk_class(const BlkArgs& a, int cls, hipStream_t s) {
 }
 
 // Size classes by transform size: (64 threads, M <= 512), (128, <= 1024),
-// (256, <= 2048), (256, <= 4096) and, FP32 only, (256, <= 8192).  A uniform
+// (256, <= 2048), (256 or, FP32, 512, <= 4096) and, FP32 only, (512 or 256,
+// <= 8192); the FP32 thread counts of the two large classes are tuning choices.  A uniform
 // batch launches its one class; a ragged batch is binned on the device first.
 template <typename T>
 static hipError_t launch_blk(const BlkArgs& a, hipStream_t s) {
@@ -521,9 +522,13 @@ static hipError_t launch_blk(const BlkArgs& a, hipStream_t s) {
     if (lo <= 512 && e == hipSuccess) e = launch_blk_class<T, 64, 512>(a, 0, s);
     if (hi > 512 && lo <= 1024 && e == hipSuccess) e = launch_blk_class<T, 128, 1024>(a, 1, s);
     if (hi > 1024 && lo <= 2048 && e == hipSuccess) e = launch_blk_class<T, 256, 2048>(a, 2, s);
-    if (hi > 2048 && lo <= 4096 && e == hipSuccess) e = launch_blk_class<T, 256, 4096>(a, 3, s);
     if constexpr (sizeof(T) == 4) {
-        if (hi > 4096 && e == hipSuccess) e = launch_blk_class<T, 256, 8192>(a, 4, s);
+        if (hi > 2048 && lo <= 4096 && e == hipSuccess)
+            e = a.threads[3] == 512 ? launch_blk_class<T, 512, 4096>(a, 3, s) : launch_blk_class<T, 256, 4096>(a, 3, s);
+        if (hi > 4096 && e == hipSuccess)
+            e = a.threads[4] == 256 ? launch_blk_class<T, 256, 8192>(a, 4, s) : launch_blk_class<T, 512, 8192>(a, 4, s);
+    } else {
+        if (hi > 2048 && lo <= 4096 && e == hipSuccess) e = launch_blk_class<T, 256, 4096>(a, 3, s);
     }
     return e;
 }

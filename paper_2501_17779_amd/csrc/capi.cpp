@@ -480,7 +480,10 @@ ca_status_t align_batch(ca_context_t c, const void* z1, const void* z2, const in
         a.rescore = o.rescore;
         a.theta64 = o.theta_fp64;
         a.num_cus = c->num_cus;
-        for (int k = 0; k < ca::kBlkClasses; ++k) a.grid_mult[k] = c->tune.blk_grid[k];
+        for (int k = 0; k < ca::kBlkClasses; ++k) {
+            a.grid_mult[k] = c->tune.blk_grid[k];
+            a.threads[k] = c->tune.blk_threads[k];
+        }
         a.bins = nullptr;
         if (offsets) {
             if (num_pairs > c->bins_cap) {

@@ -29,6 +29,9 @@ struct BlkArgs {
     // persistent blocks per CU of each size class, in multiples of the
     // kernel's occupancy limit; 0 = one block per pair
     int grid_mult[kBlkClasses];
+    // threads per block of the FP32 classes 3 and 4 (256 or 512; other
+    // classes and FP64 use their fixed sizes)
+    int threads[kBlkClasses];
     // ragged batches: device workspace of kBlkClasses counters followed by
     // kBlkClasses lists of num_pairs pair indices (blk_bin_ints(num_pairs) ints)
     int* bins;

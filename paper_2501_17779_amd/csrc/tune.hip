@@ -70,7 +70,9 @@ __global__ void k_tune_curves(cf* __restrict__ z1, cf* __restrict__ z2, int n, i
 
 namespace {
 
-const char* const kKnobNames[4] = {"team_grid", "allpairs_cols", "block_plan", "block_grid"};
+constexpr int kKnobs = 5;
+const char* const kKnobNames[kKnobs] = {"team_grid", "allpairs_cols", "block_plan", "block_grid", "block_threads"};
+const int kDefaultThreads[ca::kBlkClasses] = {64, 128, 256, 256, 512};
 const int kTeamSizes[kTeamKeys] = {64, 128, 256, 512, 1024};
 const int kClassMax[ca::kBlkClasses] = {512, 1024, 2048, 4096, 8192};
 
@@ -102,6 +104,11 @@ ca_status_t validate(int knob, int key, const std::vector<int>& v) {
             if (v.size() != 1 || v[0] < 0 || v[0] > 8)
                 return fail(CA_ERR_INVALID_ARG, "block_grid takes one value in [0, 8]");
             return CA_OK;
+        case CA_TUNE_BLOCK_THREADS:
+            if (key != 3 && key != 4) return fail(CA_ERR_INVALID_ARG, "block_threads key must be class 3 or 4");
+            if (v.size() != 1 || (v[0] != 256 && v[0] != 512))
+                return fail(CA_ERR_INVALID_ARG, "block_threads takes one value, 256 or 512");
+            return CA_OK;
         default:
             return fail(CA_ERR_INVALID_ARG, "unknown tuning knob");
     }
@@ -112,6 +119,7 @@ std::vector<int> current(const ca_context* c, int knob, int key) {
         case CA_TUNE_TEAM_GRID: return {c->tune.team_grid[team_key(key)]};
         case CA_TUNE_ALLPAIRS_COLS: return {c->tune.allpairs_cols[team_key(key)]};
         case CA_TUNE_BLOCK_PLAN: return radices_for(c, key);
+        case CA_TUNE_BLOCK_THREADS: return {c->tune.blk_threads[key]};
         default: return {c->tune.blk_grid[key]};
     }
 }
@@ -121,6 +129,7 @@ bool is_default(int knob, int key, const std::vector<int>& v) {
         case CA_TUNE_TEAM_GRID: return v[0] == 1;
         case CA_TUNE_ALLPAIRS_COLS: return v[0] == 64;
         case CA_TUNE_BLOCK_PLAN: return v == default_radices(key);
+        case CA_TUNE_BLOCK_THREADS: return v[0] == kDefaultThreads[key];
         default: return v[0] == 1;
     }
 }
@@ -135,6 +144,7 @@ ca_status_t install(ca_context* c, int knob, int key, const std::vector<int>& v,
             if (v == default_radices(key)) c->tune.blk_plan.erase(key);
             else c->tune.blk_plan[key] = v;
             break;
+        case CA_TUNE_BLOCK_THREADS: c->tune.blk_threads[key] = v[0]; break;
         default: c->tune.blk_grid[key] = v[0]; break;
     }
     const auto id = std::make_pair(knob, key);
@@ -277,7 +287,10 @@ ca::BlkArgs blk_args(ca_context* c, const void* z1, const void* z2, int n, int64
     a.rescore = CA_RESCORE_TOP2;
     a.theta64 = 0;
     a.num_cus = c->num_cus;
-    for (int k = 0; k < ca::kBlkClasses; ++k) a.grid_mult[k] = c->tune.blk_grid[k];
+    for (int k = 0; k < ca::kBlkClasses; ++k) {
+        a.grid_mult[k] = c->tune.blk_grid[k];
+        a.threads[k] = c->tune.blk_threads[k];
+    }
     a.bins = nullptr;
     return a;
 }
@@ -299,6 +312,9 @@ ca_status_t autotune(ca_context* c, int knob, int key, hipStream_t s, float& bes
         case CA_TUNE_BLOCK_GRID:
             cands = {{1}, {2}, {4}, {0}};
             break;
+        case CA_TUNE_BLOCK_THREADS:
+            cands = {{256}, {512}};
+            break;
         case CA_TUNE_ALLPAIRS_COLS:
             cands = {{2}, {4}, {8}, {16}, {32}, {64}};
             break;
@@ -308,7 +324,7 @@ ca_status_t autotune(ca_context* c, int knob, int key, hipStream_t s, float& bes
     }
     if (knob == CA_TUNE_TEAM_GRID || knob == CA_TUNE_ALLPAIRS_COLS) n = key;
     else if (knob == CA_TUNE_BLOCK_PLAN) n = representative_n(key);
-    else n = representative_n(kClassMax[key]);
+    else n = representative_n(kClassMax[key]);      // block_grid, block_threads
     if (n == 0) return fail(CA_ERR_UNSUPPORTED_N, "no curve size in [2, 4096] uses this transform size");
 
     DevBuf z1, z2, out, spec, norms;
@@ -358,6 +374,7 @@ ca_status_t autotune(ca_context* c, int knob, int key, hipStream_t s, float& bes
             }
             ca::BlkArgs a = blk_args(c, z1.p, z2.p, n, pairs, (ca_result_t*)out.p);
             if (knob == CA_TUNE_BLOCK_GRID) a.grid_mult[key] = v[0];
+            if (knob == CA_TUNE_BLOCK_THREADS) a.threads[key] = v[0];
             auto launch = [&]() { return ca::launch_align_blk_f32(a, s); };
             st = time_launch(launch, s, t, ms);
         }
@@ -496,7 +513,7 @@ bool as_int(const JVal* v, int& out) {
 }
 
 int knob_of(const std::string& s) {
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < kKnobs; ++k)
         if (s == kKnobNames[k]) return k;
     return -1;
 }
@@ -552,12 +569,14 @@ extern "C" {
 
 ca_status_t ca_autotune(ca_context_t c, int32_t knob, int32_t key, float* best_ms, void* stream) {
     if (!c) return fail(CA_ERR_INVALID_ARG, "context is NULL");
-    if (knob < 0 || knob > 3) return fail(CA_ERR_INVALID_ARG, "unknown tuning knob");
+    if (knob < 0 || knob >= kKnobs) return fail(CA_ERR_INVALID_ARG, "unknown tuning knob");
     if (knob == CA_TUNE_TEAM_GRID || knob == CA_TUNE_ALLPAIRS_COLS) {
         if (!team_size(key)) return fail(CA_ERR_UNSUPPORTED_N, "key must be n in {64, 128, 256, 512, 1024}");
     } else if (knob == CA_TUNE_BLOCK_PLAN) {
         if (key < 2 || key > kMaxM || !smooth7_size(key))
             return fail(CA_ERR_UNSUPPORTED_N, "block_plan key must be a 7-smooth size in [2, 8192]");
+    } else if (knob == CA_TUNE_BLOCK_THREADS) {
+        if (key != 3 && key != 4) return fail(CA_ERR_INVALID_ARG, "block_threads key must be class 3 or 4");
     } else if (key < 0 || key >= ca::kBlkClasses) {
         return fail(CA_ERR_INVALID_ARG, "block_grid key must be 0..4");
     }
@@ -572,9 +591,10 @@ ca_status_t ca_autotune(ca_context_t c, int32_t knob, int32_t key, float* best_m
 ca_status_t ca_tune_get(ca_context_t c, int32_t knob, int32_t key, int32_t* values, int32_t* count) {
     if (!c) return fail(CA_ERR_INVALID_ARG, "context is NULL");
     if (!values || !count) return fail(CA_ERR_INVALID_ARG, "values and count must be non-NULL");
-    if (knob < 0 || knob > 3) return fail(CA_ERR_INVALID_ARG, "unknown tuning knob");
+    if (knob < 0 || knob >= kKnobs) return fail(CA_ERR_INVALID_ARG, "unknown tuning knob");
     std::vector<int> probe = knob == CA_TUNE_BLOCK_PLAN ? default_radices(key) : std::vector<int>{1};
     if (knob == CA_TUNE_ALLPAIRS_COLS) probe = {64};
+    if (knob == CA_TUNE_BLOCK_THREADS) probe = {256};
     ca_status_t st = validate(knob, key, probe);        // key check only
     if (st != CA_OK) return st;
     std::lock_guard<std::mutex> lk(c->mu);
@@ -607,6 +627,7 @@ ca_status_t ca_tune_save(ca_context_t c, const char* path) {
     }
     for (const auto& kv : c->tune.blk_plan) ids.push_back({CA_TUNE_BLOCK_PLAN, kv.first});
     for (int k = 0; k < ca::kBlkClasses; ++k) ids.push_back({CA_TUNE_BLOCK_GRID, k});
+    for (int k = 3; k < ca::kBlkClasses; ++k) ids.push_back({CA_TUNE_BLOCK_THREADS, k});
     for (const auto& kv : c->tune.ms)   // measured defaults are kept too (they record the sweep)
         if (std::find(ids.begin(), ids.end(), kv.first) == ids.end()) ids.push_back(kv.first);
     std::sort(ids.begin(), ids.end());

@@ -4,7 +4,8 @@ cache that default_context() loads.
     python -m paper_2501_17779_amd.tune_all [--out FILE] [--quick]
 
 Tunes the team-kernel grid and the all-pairs tile width for n = 64..1024,
-the persistent grid of the five block-engine size classes, and the radix
+the thread count of the two largest block-engine size classes (FP32), the
+persistent grid of the five classes, and the radix
 schedule of every block-engine transform size from 16 to 8192 with no prime
 factor above 7 that some n in [2, 4096] uses (--quick: powers of two and the
 class maxima only).  Each (knob, key) is measured by ca_autotune on a
@@ -58,6 +59,7 @@ def main(argv=None) -> int:
     t0 = time.time()
     for knob, keys in (("team_grid", [64, 128, 256, 512, 1024]),
                        ("allpairs_cols", [64, 128, 256, 512, 1024]),
+                       ("block_threads", [3, 4]),
                        ("block_grid", [0, 1, 2, 3, 4])):
         for key in keys:
             ms = ca.autotune(knob, key, ctx=ctx)

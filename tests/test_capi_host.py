@@ -231,7 +231,7 @@ def test_tuning_arguments_rejected_on_host(L):
     assert L.ca_tune_set(None, 0, 1024, vals, 1) == ca.ERR_INVALID_ARG
     assert L.ca_tune_save(None, b"/tmp/x.json") == ca.ERR_INVALID_ARG
     assert L.ca_tune_load(None, b"/tmp/x.json", None) == ca.ERR_INVALID_ARG
-    for knob in (-1, 4):
+    for knob in (-1, 5):
         assert L.ca_autotune(ctx, knob, 1024, None, None) == ca.ERR_INVALID_ARG
         assert L.ca_tune_get(ctx, knob, 1024, vals, ctypes.byref(cnt)) == ca.ERR_INVALID_ARG
         assert L.ca_tune_set(ctx, knob, 1024, vals, 1) == ca.ERR_INVALID_ARG
@@ -254,6 +254,9 @@ def test_tuning_arguments_rejected_on_host(L):
     assert setv(2, 4096, 16, 16, 16) == ca.ERR_INVALID_ARG       # radix 16 is not a block-engine radix
     assert setv(2, 3000, 8, 3, 5, 5) == ca.ERR_INVALID_ARG       # product 600
     assert setv(3, 0, 9) == ca.ERR_INVALID_ARG
+    assert setv(4, 2, 256) == ca.ERR_INVALID_ARG                  # classes 3 and 4 only
+    assert setv(4, 3, 384) == ca.ERR_INVALID_ARG
+    assert L.ca_autotune(ctx, 4, 2, None, None) == ca.ERR_INVALID_ARG
     assert L.ca_tune_set(ctx, 0, 1024, vals, 0) == ca.ERR_INVALID_ARG
     assert L.ca_tune_set(ctx, 2, 4096, vals, 17) == ca.ERR_INVALID_ARG
     assert L.ca_tune_set(ctx, 0, 1024, None, 1) == ca.ERR_INVALID_ARG
@@ -288,6 +291,7 @@ def test_tuning_file_rejections_on_host(L, tmp_path):
         "plan_radix": head % '[{"knob": "block_plan", "key": 4096, "values": [16, 16, 16]}]',
         "plan_key": head % '[{"knob": "block_plan", "key": 4099, "values": [4099]}]',
         "class": head % '[{"knob": "block_grid", "key": 5, "values": [1]}]',
+        "threads": head % '[{"knob": "block_threads", "key": 4, "values": [1024]}]',
         "values_type": head % '[{"knob": "block_grid", "key": 1, "values": ["2"]}]',
         "one_bad_of_two": head % ('[{"knob": "block_grid", "key": 1, "values": [2]}, '
                                   '{"knob": "block_grid", "key": 2, "values": [-2]}]'),

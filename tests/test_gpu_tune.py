@@ -64,6 +64,8 @@ def transform_size(n):
     ("allpairs_cols", 128, {(2,), (4,), (8,), (16,), (32,), (64,)}),
     ("block_grid", 1, {(1,), (2,), (4,), (0,)}),
     ("block_grid", 4, {(1,), (2,), (4,), (0,)}),
+    ("block_threads", 3, {(256,), (512,)}),
+    ("block_threads", 4, {(256,), (512,)}),
 ])
 def test_autotune_installs_a_candidate(ca, ctx, knob, key, allowed):
     note(f"autotune {knob} key={key}")
@@ -198,3 +200,31 @@ def test_save_load_round_trip(ca, ctx, tmp_path):
     finally:
         torch.cuda.synchronize()
         other.close()
+
+
+def test_thread_counts_agree(ca, ctx):
+    """The 256- and 512-thread kernels of classes 3 and 4 run the same
+    butterflies; only the order of the FP64 norm and re-scoring sums differs."""
+    sizes = [2053, 2500, 3001, 3072, 4093, 4096, 2187, 3500]   # padded (class 4) and 7-smooth (class 3)
+    z1s, z2s = [], []
+    for k, n in enumerate(sizes):
+        a, b = inputs.batch(740 + k, 5, n)
+        z1s += list(a)
+        z2s += list(b)
+    offs = np.zeros(len(z1s) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([len(z) for z in z1s])
+    d = {"z1": np.concatenate(z1s), "z2": np.concatenate(z2s), "off": offs}
+    r1, r2, off = gpu(d["z1"]), gpu(d["z2"]), gpu(d["off"])
+    recs = {}
+    for t in (256, 512):
+        ca.tune_set("block_threads", 3, t, ctx=ctx)
+        ca.tune_set("block_threads", 4, t, ctx=ctx)
+        note(f"block_threads={t}")
+        recs[t] = ca.to_numpy(ca.align_batch(r1, r2, offsets=off, ctx=ctx))
+    a, b = recs[256], recs[512]
+    assert np.array_equal(a["shift"], b["shift"]) and np.array_equal(a["flags"], b["flags"])
+    assert np.array_equal(a["theta"], b["theta"])
+    assert np.all(np.abs(a["e0"] - b["e0"]) <= 1e-12 * np.abs(a["e0"]) + 1e-15)
+    for i in range(0, 40, 8):
+        lo, hi = d["off"][i], d["off"][i + 1]
+        acc.check_pair(b[i], d["z1"][lo:hi], d["z2"][lo:hi])
