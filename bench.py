@@ -311,7 +311,9 @@ def accuracy_sample(torch, ca, raw1, raw2, n, precisions, k=256):
     """Accuracy against the FP64 oracle on k pairs of the workload: the raw
     polygons are resampled by the oracle, aligned on the GPU with each
     precision and by the oracle, and compared (max/mean theta and e0 error,
-    shift mismatches outside near-ties)."""
+    shift mismatches outside near-ties, and the largest relative shortfall
+    (T(s0) - T(shift)) / T(s0) of the chosen shift's |C| below the oracle's
+    maximum: at a near-tie any shift within 1e-6 is accepted)."""
     import oracle
     from oracle import resample_ref as rr
     z1 = np.stack([rr.resample(raw1[i].astype(np.float64), n)[0] for i in range(k)]).astype(np.complex64)
@@ -324,12 +326,13 @@ def accuracy_sample(torch, ca, raw1, raw2, n, precisions, k=256):
     for prec in precisions:
         res = ca.to_numpy(ca.align_batch(torch.from_numpy(z1).cuda(), torch.from_numpy(z2).cuda(),
                                          precision=prec))
-        dth, de, mism, near = [], [], 0, 0
+        dth, de, mism, near, excess = [], [], 0, 0, 0.0
         for i in range(k):
             T, th, m, thp = orc[i]
             s0 = int(np.argmax(T))
             T2 = np.max(np.delete(T, s0))
             s = int(res["shift"][i])
+            excess = max(excess, float((T[s0] - T[s]) / T[s0]))
             if (T[s0] - T2) / T[s0] < 1e-6:
                 near += 1
             elif s != s0:
@@ -339,7 +342,8 @@ def accuracy_sample(torch, ca, raw1, raw2, n, precisions, k=256):
             de.append(abs(res["e0"][i] - E) / max(E, 1e-300))
         out[prec] = {"pairs": k, "theta_err_max": max(dth), "theta_err_mean": float(np.mean(dth)),
                      "e0_rel_err_max": max(de), "e0_rel_err_mean": float(np.mean(de)),
-                     "shift_mismatch_outside_near_ties": mism, "near_ties": near}
+                     "shift_mismatch_outside_near_ties": mism, "near_ties": near,
+                     "shift_rel_excess_max": excess}
     return out
 
 
