@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256, 2) void k_align_team(const cf* __restrict__ z1
             lds[N + t + T * q] = b0[q];
         }
         wave_lds_sync();
-        const ca_result_t res = team_epilogue<N, T, kZTwice>(v, a0, lds, cand, t, n1, n2, rescore, theta64);
+        const ca_result_t res = team_epilogue<N, T, kZTwice, true>(v, a0, lds, cand, t, n1, n2, rescore, theta64);
         if (t == 0) out[pair] = res;
         wave_lds_sync();
     }

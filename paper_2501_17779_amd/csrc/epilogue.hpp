@@ -52,7 +52,7 @@ __device__ __forceinline__ void finish(ca_result_t& res, const Pick& pk, int n, 
     float gap;
     if (pk.count > 1 && pk.second >= 0.0)
         gap = (float)(pk.best - pk.second) *
-              __builtin_amdgcn_rcpf((float)(pk.best + c64 * (double)sqrtf((float)pk.second)));
+              __builtin_amdgcn_rcpf((float)(pk.best + c64 * (double)__builtin_amdgcn_sqrtf((float)pk.second)));
     else
         gap = (float)(d1 - d2) * __builtin_amdgcn_rcpf((float)d1);
     if (gap < kNearTie) flags |= CA_FLAG_NEAR_TIE;
@@ -97,7 +97,7 @@ enum { kZPad = 0, kZTwice = 1 };
 // a0[q] = z1[t + T q] (FP32 nodes of curve 1), zb = LDS copy of curve 2's
 // nodes in layout ZL, cand = the team's candidate list in LDS.
 // Returns the finished result (every lane).
-template <int N, int T, int ZL = kZPad>
+template <int N, int T, int ZL = kZPad, bool FUSE2 = false>
 __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const cf (&a0)[N / T],
                                                      const cf* zb, int* cand, int t, double n1, double n2,
                                                      int rescore, int theta64,
@@ -137,9 +137,12 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
 
     ca_result_t res;
     if (special_case(res, n1, n2, (double)bv)) return res;
-    const double d1 = (double)sqrtf(bv), d2 = (double)sqrtf(fmaxf(cv, 0.0f));
-    const double epsD =
-        (double)((float)(kErrScale * err_u * (double)ilog2_ceil(N) * N * N) * sqrtf((float)(n1 * n2)));
+    // |D| of the best and runner-up and the error bound only steer the choice
+    // of shifts to re-score and the reported gap: the hardware square root
+    // (1 ulp) is ample there
+    const double d1 = (double)__builtin_amdgcn_sqrtf(bv), d2 = (double)__builtin_amdgcn_sqrtf(fmaxf(cv, 0.0f));
+    const double epsD = (double)((float)(kErrScale * err_u * (double)ilog2_ceil(N) * N * N) *
+                                 __builtin_amdgcn_sqrtf((float)(n1 * n2)));
     const bool two = d1 - d2 < 2.0 * epsD;
 
     // candidate list (team-uniform order: by register, then by lane)
@@ -190,13 +193,39 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
     }
     wave_lds_sync();
     Pick pk;
-    for (int k = 0; k < cnt; ++k) {
-        const int c = cand[k];
-        double re = 0.0, im = 0.0;
-        const cf* zs = zb + ((t - c) & (N - 1));
+    auto zat = [&](int c, int q) {
+        return (ZL == kZTwice) ? zb[((t - c) & (N - 1)) + T * q] : zb[lpad<N>((t + T * q - c) & (N - 1))];
+    };
+    int k = 0;
+    if (FUSE2 && cnt >= 2) {
+        // the first two candidates in one pass: curve 1's nodes converted once
+        // (where the runner-up is usually re-scored: near-copies in a batch)
+        const int c0 = cand[0], c1 = cand[1];
+        double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            const cf zz = (ZL == kZTwice) ? zs[T * q] : zb[lpad<N>((t + T * q - c) & (N - 1))];
+            const cf u = zat(c0, q), w = zat(c1, q);
+            const double ax = a0[q].x, ay = a0[q].y;
+            const double ux = u.x, uy = u.y, wx = w.x, wy = w.y;
+            re0 = fma(ax, ux, fma(ay, uy, re0));
+            im0 = fma(ay, ux, fma(-ax, uy, im0));
+            re1 = fma(ax, wx, fma(ay, wy, re1));
+            im1 = fma(ay, wx, fma(-ax, wy, im1));
+        }
+        re0 = team_sum<T>(re0);
+        im0 = team_sum<T>(im0);
+        re1 = team_sum<T>(re1);
+        im1 = team_sum<T>(im1);
+        pk.offer(c0, re0, im0);
+        pk.offer(c1, re1, im1);
+        k = 2;
+    }
+    for (; k < cnt; ++k) {
+        const int c = cand[k];
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const cf zz = zat(c, q);
             const double ax = a0[q].x, ay = a0[q].y, bx = zz.x, by = zz.y;
             re = fma(ax, bx, fma(ay, by, re));
             im = fma(ay, bx, fma(-ax, by, im));
