@@ -32,8 +32,10 @@ RESULT_BYTES = 32
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default per workload, see DEFAULT_STEPS)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed warmup steps (default per workload, see DEFAULT_STEPS)")
     ap.add_argument("--config", default="batch",
                     choices=["batch", "pair", "allpairs", "ragged", "ragged_any", "bf16", "srv", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -41,7 +43,21 @@ def parse():
                     help="launch every step from Python instead of replaying a captured HIP graph")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target wall time of the CPU oracle sample")
-    return ap.parse_args()
+    args = ap.parse_args()
+    steps, warmup = DEFAULT_STEPS[args.config]
+    if args.steps is None:
+        args.steps = steps
+    if args.warmup is None:
+        args.warmup = warmup
+    return args
+
+
+# Default (timed steps, warmup steps) per workload: the GPU's clock takes a
+# few tens of milliseconds of load to settle (the batch workload's step time
+# falls from ~0.42 ms in the first steps to ~0.35 ms), so the defaults give
+# every workload >= 0.1 s of warmup and ~0.1-0.5 s of timed steps.
+DEFAULT_STEPS = {"batch": (400, 300), "pair": (2000, 500), "allpairs": (40, 10), "ragged": (50, 15),
+                 "ragged_any": (40, 10), "bf16": (200, 60), "srv": (300, 150), "copy": (200, 100)}
 
 
 def sources_digest(names):
@@ -214,12 +230,11 @@ def bench_pair(args, torch, ca):
     z = nodes.to(torch.complex128)
     z1, z2 = z[:256].contiguous(), z[256:].contiguous()
     out = ca.empty_results(1, dev)
-    steps = max(args.steps, 200)
+    steps = args.steps
     ms, _ = time_steps(lambda: ca.align_pair(z1, z2, precision="fp64", out=out), steps, args.warmup, torch)
     line = base_line(args, 1e3 / ms, "pairs/s", ms, "f64",
                      {"workload": "single curve pair, n=256 nodes, FP64 (latency of one call)",
                       "pairs": 1, "n": 256})
-    line["steps"] = steps
     line["us_per_call"] = ms * 1e3
     msg, _ = time_steps(lambda: ca.align_pair(z1, z2, precision="fp64", out=out), steps, args.warmup, torch,
                         graph=True)

@@ -24,3 +24,16 @@ def test_workloads_listed_in_help():
     assert r.returncode == 0
     for c in ("batch", "pair", "allpairs", "ragged", "ragged_any", "bf16", "srv", "copy"):
         assert c in r.stdout
+
+
+def test_per_workload_defaults_and_explicit_flags(monkeypatch):
+    sys.path.insert(0, ROOT)
+    import bench
+    for cfg, (steps, warmup) in bench.DEFAULT_STEPS.items():
+        monkeypatch.setattr(sys, "argv", ["bench.py", "--config", cfg])
+        a = bench.parse()
+        assert (a.steps, a.warmup) == (steps, warmup)
+        assert warmup >= 10 and steps >= 40
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--steps", "7", "--warmup", "2"])
+    a = bench.parse()
+    assert (a.steps, a.warmup, a.config) == (7, 2, "batch")
