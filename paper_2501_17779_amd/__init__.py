@@ -14,6 +14,7 @@ from __future__ import annotations
 import ctypes
 import os
 import threading
+import warnings
 
 import numpy as np
 
@@ -148,14 +149,19 @@ _contexts: dict[int, Context] = {}
 
 def default_context(device: int | None = None) -> Context:
     """The per-device context of this process, created on first use with the
-    tuning cache (CURVEALIGN_TUNE_FILE, else the packaged one) loaded."""
+    tuning cache (CURVEALIGN_TUNE_FILE, else the packaged one) loaded; a cache
+    that cannot be read leaves the default launch choices (with a warning)."""
     import torch
     dev = torch.cuda.current_device() if device is None else int(device)
     if dev not in _contexts:
         ctx = Context(dev)
+        ctx.tune_applied = 0
         path = os.environ.get("CURVEALIGN_TUNE_FILE", TUNE_CACHE)
         if path and os.path.exists(path):
-            ctx.tune_applied = tune_load(path, ctx=ctx)
+            try:
+                ctx.tune_applied = tune_load(path, ctx=ctx)
+            except CurveAlignError as e:      # unreadable cache: the defaults stay in force
+                warnings.warn(f"tuning cache {path} not loaded ({e}); using default launch choices")
         _contexts[dev] = ctx
     return _contexts[dev]
 

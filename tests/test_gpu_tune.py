@@ -228,3 +228,27 @@ def test_thread_counts_agree(ca, ctx):
     for i in range(0, 40, 8):
         lo, hi = d["off"][i], d["off"][i + 1]
         acc.check_pair(b[i], d["z1"][lo:hi], d["z2"][lo:hi])
+
+
+def test_corrupt_cache_falls_back_to_defaults(ca, tmp_path, monkeypatch):
+    """default_context() with an unreadable tuning cache warns and keeps the
+    default launch choices (checked on a fresh default context)."""
+    bad = tmp_path / "bad.json"
+    bad.write_text("{not json")
+    monkeypatch.setenv("CURVEALIGN_TUNE_FILE", str(bad))
+    saved = dict(ca._contexts)
+    ca._contexts.clear()
+    try:
+        with pytest.warns(UserWarning):
+            c = ca.default_context(0)
+        assert c.tune_applied == 0
+        assert ca.tune_get("allpairs_cols", 512, ctx=c) == [64]
+        z1, z2 = inputs.batch(750, 8, 256)
+        rec = ca.to_numpy(ca.align_batch(gpu(z1), gpu(z2), ctx=c))
+        acc.check_batch(rec, z1, z2)
+    finally:
+        torch.cuda.synchronize()
+        for k, v in ca._contexts.items():
+            v.close()
+        ca._contexts.clear()
+        ca._contexts.update(saved)
