@@ -386,6 +386,26 @@ __device__ __forceinline__ float wave_ror1(float x) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x13C, 0xF, 0xF, false));
 }
 
+// Inclusive scan of a double over the wave: shifts by 1, 2, 4, 8 inside each
+// row of 16 lanes (DPP row_shr; lanes without a source add 0), then the row
+// totals read from lanes 15, 31, 47.  The whole wave must be active.
+template <int CTRL> __device__ __forceinline__ double dpp_shr_d(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double wave_incl_scan(double x, int lane) {
+    x += dpp_shr_d<0x111>(x);
+    x += dpp_shr_d<0x112>(x);
+    x += dpp_shr_d<0x114>(x);
+    x += dpp_shr_d<0x118>(x);
+    const double r0 = rdlane(x, 15), r1 = rdlane(x, 31), r2 = rdlane(x, 47);
+    const int row = lane >> 4;
+    const double off = row == 0 ? 0.0 : (row == 1 ? r0 : (row == 2 ? r0 + r1 : (r0 + r1) + r2));
+    return x + off;
+}
+
 __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw, const int64_t* __restrict__ raw_off,
                                                       int64_t num_curves, const int64_t* __restrict__ out_off,
                                                       cf* __restrict__ out, double* __restrict__ norms,
@@ -544,13 +564,7 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
             loc[k] = (float)acc;
             acc += (double)sH[kp(kFtH + kFtC * lane + k)];
         }
-        double incl = acc;
-#pragma unroll
-        for (int o2 = 1; o2 < 64; o2 <<= 1) {
-            const double y = __shfl_up(incl, o2, 64);
-            if (lane >= o2) incl += y;
-        }
-        const double base = incl - acc;        // arc length from knot a to knot a + 8 lane
+        const double base = wave_incl_scan(acc, lane) - acc;   // arc length from knot a to knot a + 8 lane
 #pragma unroll
         for (int k = 0; k < kFtC; ++k) sS[kp(kFtC * lane + k)] = (float)(base + (double)loc[k]);
         // arc length from knot a to knot a + kt - 1 (tile end), exact in FP64
@@ -558,11 +572,11 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
         {
             const int e = kt - 1;              // local index of the right end
             const int el = e / kFtC, ek = e % kFtC;
-            double part = 0.0;
+            double part = 0.0;                 // same on every lane (el is wave-uniform)
 #pragma unroll
             for (int k = 0; k < kFtC; ++k)
                 if (k < ek) part += (double)sH[kp(kFtH + kFtC * el + k)];
-            span = __shfl(base, el, 64) + __shfl(part, el, 64);
+            span = rdlane(base, el) + part;
         }
         wave_lds_sync();
         if (mode == CA_RESAMPLE_SPLINE) {
