@@ -138,3 +138,27 @@ def test_clockwise_flag(ca):
         want = ca.FLAG_CLOCKWISE if area < 0 else 0
         assert flags[c] == want, (c, area, flags[c])
     assert sum(int(f) == ca.FLAG_CLOCKWISE for f in flags) == len(polys) // 2
+
+
+def test_dense_tiles_and_mixed_node_placement(ca):
+    """Upsampled curves (more nodes than raw vertices) over several tiles, and
+    a curve whose first tile of knots holds few nodes per knot while its second
+    holds hundreds: both node-placement paths inside one curve, against the
+    oracle."""
+    t = np.linspace(0.0, 2 * np.pi, 700, endpoint=False)
+    up = np.stack([np.cos(t) * (1 + 0.2 * np.cos(3 * t)), np.sin(t) * (1 + 0.2 * np.cos(3 * t))], 1)
+    dense = np.linspace(0.0, 0.6, 520, endpoint=False)             # 520 knots on a short arc
+    sparse = np.linspace(0.6, 2 * np.pi, 40, endpoint=False)       # 40 knots on the rest
+    tt = np.concatenate([dense, sparse])
+    mixed = np.stack([np.cos(tt) * (1 + 0.1 * np.sin(2 * tt)), np.sin(tt) * (1 + 0.1 * np.sin(2 * tt))], 1)
+    polys = [up.astype(np.float32), mixed.astype(np.float32), (mixed[::-1] * 3 + 1).astype(np.float32)]
+    ns = [4000, 3000, 2048]
+    for mode in ("spline", "linear"):
+        out, ooff, norms, flags = run(ca, polys, ns, mode)
+        m = rr.SPLINE if mode == "spline" else rr.LINEAR
+        for c, p in enumerate(polys):
+            z, info = rr.resample(p.astype(np.float64), ns[c], m)
+            err = np.max(np.abs(out[ooff[c]:ooff[c + 1]] - z))
+            note(f"dense/mixed curve {c} {mode}: node error {err:.3g}")
+            assert err <= TOL_POS
+            assert flags[c] == (ca.FLAG_CLOCKWISE if info["area"] < 0 else 0)
