@@ -107,18 +107,23 @@ def time_steps(fn, steps, warmup, torch, graph=False):
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    # two events bracket the timed steps; an event after every step (only for
+    # BENCH_PER_STEP) adds its own cost to steps of a few microseconds
+    per_step = bool(os.environ.get("BENCH_PER_STEP"))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1 if per_step else 2)]
     t0 = time.perf_counter()
     ev[0].record()
     for i in range(steps):
         fn()
-        ev[i + 1].record()
+        if per_step:
+            ev[i + 1].record()
+    ev[-1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
-    if os.environ.get("BENCH_PER_STEP"):
+    if per_step:
+        per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
         print("per-step ms:", " ".join(f"{x:.4f}" for x in per), file=sys.stderr, flush=True)
-    return ev[0].elapsed_time(ev[steps]) / steps, wall
+    return ev[0].elapsed_time(ev[-1]) / steps, wall
 
 
 def time_parts(fns, steps, warmup, torch, graph=False):
