@@ -288,8 +288,10 @@ enum {
  * grid knobs 1, 2, 4 and 0; all-pairs columns 2, 4, 8, 16, 32, 64; threads
  * 256 and 512; radix
  * schedules: the orderings of the power-of-two part as eights, fours or
- * mixed, each with the odd radices first or last.  Each candidate is timed
- * with HIP events over three launches after one warm-up launch on `stream`.
+ * mixed, each with the odd radices first or last.  The first candidate runs
+ * for about 20 ms first so that the clock settles; then every candidate is
+ * timed with HIP events on `stream` in each of three rounds (three launches
+ * after one warm-up launch per round) and keeps its best round.
  * Allocates and frees its own device buffers and synchronises the stream.
  * CA_ERR_UNSUPPORTED_N: the key names no size the knob serves (a transform
  * size that no n in [2, CA_MAX_N] uses).

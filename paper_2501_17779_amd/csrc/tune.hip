@@ -349,41 +349,57 @@ ca_status_t autotune(ca_context* c, int knob, int key, hipStream_t s, float& bes
     }
 
     const std::vector<int> before = current(c, knob, key);
-    int best = -1;
-    best_ms = 0.0f;
-    for (size_t i = 0; i < cands.size(); ++i) {
+    // One candidate: install it where it lives in tables, then time it.
+    auto run = [&](size_t i, float& ms) -> ca_status_t {
         const std::vector<int>& v = cands[i];
-        float ms = 0.0f;
         if (knob == CA_TUNE_TEAM_GRID) {
             auto launch = [&]() {
                 return ca::launch_align_team(z1.p, z2.p, n, pairs, (ca_result_t*)out.p, team_tw_for(c, n),
                                              CA_RESCORE_TOP2, 0, c->num_cus, v[0], s);
             };
-            st = time_launch(launch, s, t, ms);
-        } else if (knob == CA_TUNE_ALLPAIRS_COLS) {
+            return time_launch(launch, s, t, ms);
+        }
+        if (knob == CA_TUNE_ALLPAIRS_COLS) {
             auto launch = [&]() {
                 return ca::launch_allpairs(z1.p, spec.p, (const double*)norms.p, m, n, (ca_result_t*)out.p,
                                            team_tw_for(c, n), CA_RESCORE_TOP2, 0, v[0], s);
             };
-            st = time_launch(launch, s, t, ms);
-        } else {
-            if (knob == CA_TUNE_BLOCK_PLAN) {
-                if (v == default_radices(key)) c->tune.blk_plan.erase(key);
-                else c->tune.blk_plan[key] = v;
-                if ((st = upload_block_plans(c, {key})) != CA_OK) break;
-            }
-            ca::BlkArgs a = blk_args(c, z1.p, z2.p, n, pairs, (ca_result_t*)out.p);
-            if (knob == CA_TUNE_BLOCK_GRID) a.grid_mult[key] = v[0];
-            if (knob == CA_TUNE_BLOCK_THREADS) a.threads[key] = v[0];
-            auto launch = [&]() { return ca::launch_align_blk_f32(a, s); };
-            st = time_launch(launch, s, t, ms);
+            return time_launch(launch, s, t, ms);
         }
-        if (st != CA_OK) break;
-        if (best < 0 || ms < best_ms) {
-            best = (int)i;
-            best_ms = ms;
+        if (knob == CA_TUNE_BLOCK_PLAN) {
+            if (v == default_radices(key)) c->tune.blk_plan.erase(key);
+            else c->tune.blk_plan[key] = v;
+            const ca_status_t us = upload_block_plans(c, {key});
+            if (us != CA_OK) return us;
+        }
+        ca::BlkArgs a = blk_args(c, z1.p, z2.p, n, pairs, (ca_result_t*)out.p);
+        if (knob == CA_TUNE_BLOCK_GRID) a.grid_mult[key] = v[0];
+        if (knob == CA_TUNE_BLOCK_THREADS) a.threads[key] = v[0];
+        auto launch = [&]() { return ca::launch_align_blk_f32(a, s); };
+        return time_launch(launch, s, t, ms);
+    };
+    // The GPU clock needs tens of milliseconds of load to settle: run the
+    // first candidate for at least ~20 ms before timing, then time every
+    // candidate in each of three rounds and keep its best time.
+    float warm = 0.0f;
+    if ((st = run(0, warm)) != CA_OK) {
+        (void)install(c, knob, key, before, -1.0f);
+        return st;
+    }
+    for (int r = 0, reps = (int)(20.0f / fmaxf(4.0f * warm, 0.05f)); r < reps && r < 400; ++r)
+        if ((st = run(0, warm)) != CA_OK) break;
+    std::vector<float> best_of(cands.size(), 3.0e38f);
+    for (int round = 0; round < 3 && st == CA_OK; ++round) {
+        for (size_t i = 0; i < cands.size(); ++i) {
+            float ms = 0.0f;
+            if ((st = run(i, ms)) != CA_OK) break;
+            best_of[i] = fminf(best_of[i], ms);
         }
     }
+    int best = 0;
+    for (size_t i = 1; i < cands.size(); ++i)
+        if (best_of[i] < best_of[best]) best = (int)i;
+    best_ms = best_of[best];
     if (st != CA_OK) {
         (void)install(c, knob, key, before, -1.0f);   // leave the previous choice in place
         return st;
