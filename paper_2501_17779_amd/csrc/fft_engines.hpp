@@ -49,22 +49,38 @@ __device__ __forceinline__ int mod_small(int j, int ns, float inv_ns) {
     return r;
 }
 
+// A pass first requests its twiddles (global memory for the large classes),
+// then waits at the barrier that publishes the previous pass's output, so the
+// loads are in flight during the wait and the LDS reads.  It ends after its
+// writes without a barrier: the next pass, or the caller, synchronises.
 template <int R, int NT, int NMAX, typename T>
 __device__ __forceinline__ void blk_pass(cpx<T>* buf, int n, int ns, const cpx<T>* __restrict__ tw) {
     constexpr int UM = (NMAX / R + NT - 1) / NT;
     const int nb = n / R;
     const float inv_ns = 1.0f / (float)ns;
+    int kk[UM];
+    cpx<T> f[UM][R - 1];
+#pragma unroll
+    for (int u = 0; u < UM; ++u) {
+        const int j = threadIdx.x + u * NT;
+        kk[u] = 0;
+        if (j < nb && ns > 1) {
+            kk[u] = mod_small(j, ns, inv_ns);
+#pragma unroll
+            for (int r = 1; r < R; ++r) f[u][r - 1] = tw[(r - 1) * ns + kk[u]];
+        }
+    }
+    __syncthreads();
     cpx<T> v[UM][R];
 #pragma unroll
     for (int u = 0; u < UM; ++u) {
         const int j = threadIdx.x + u * NT;
         if (j < nb) {
-            const int k = mod_small(j, ns, inv_ns);
 #pragma unroll
             for (int r = 0; r < R; ++r) v[u][r] = buf[j + r * nb];
             if (ns > 1) {
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[u][r] = mul(v[u][r], tw[(r - 1) * ns + k]);
+                for (int r = 1; r < R; ++r) v[u][r] = mul(v[u][r], f[u][r - 1]);
             }
             dft<R>(v[u]);
         }
@@ -74,13 +90,12 @@ __device__ __forceinline__ void blk_pass(cpx<T>* buf, int n, int ns, const cpx<T
     for (int u = 0; u < UM; ++u) {
         const int j = threadIdx.x + u * NT;
         if (j < nb) {
-            const int k = mod_small(j, ns, inv_ns);
+            const int k = kk[u];
             const int base = (j - k) * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) buf[base + r * ns] = v[u][r];
         }
     }
-    __syncthreads();
 }
 
 // The same pass on two buffers, sharing twiddles and barriers.
@@ -89,20 +104,31 @@ __device__ __forceinline__ void blk_pass2(cpx<T>* b1, cpx<T>* b2, int n, int ns,
     constexpr int UM = (NMAX / R + NT - 1) / NT;
     const int nb = n / R;
     const float inv_ns = 1.0f / (float)ns;
+    int kk[UM];
+    cpx<T> f[UM][R - 1];
+#pragma unroll
+    for (int u = 0; u < UM; ++u) {
+        const int j = threadIdx.x + u * NT;
+        kk[u] = 0;
+        if (j < nb && ns > 1) {
+            kk[u] = mod_small(j, ns, inv_ns);
+#pragma unroll
+            for (int r = 1; r < R; ++r) f[u][r - 1] = tw[(r - 1) * ns + kk[u]];
+        }
+    }
+    __syncthreads();
     cpx<T> v[UM][R], w[UM][R];
 #pragma unroll
     for (int u = 0; u < UM; ++u) {
         const int j = threadIdx.x + u * NT;
         if (j < nb) {
-            const int k = mod_small(j, ns, inv_ns);
 #pragma unroll
             for (int r = 0; r < R; ++r) { v[u][r] = b1[j + r * nb]; w[u][r] = b2[j + r * nb]; }
             if (ns > 1) {
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    const cpx<T> f = tw[(r - 1) * ns + k];
-                    v[u][r] = mul(v[u][r], f);
-                    w[u][r] = mul(w[u][r], f);
+                    v[u][r] = mul(v[u][r], f[u][r - 1]);
+                    w[u][r] = mul(w[u][r], f[u][r - 1]);
                 }
             }
             dft<R>(v[u]);
@@ -114,13 +140,12 @@ __device__ __forceinline__ void blk_pass2(cpx<T>* b1, cpx<T>* b2, int n, int ns,
     for (int u = 0; u < UM; ++u) {
         const int j = threadIdx.x + u * NT;
         if (j < nb) {
-            const int k = mod_small(j, ns, inv_ns);
+            const int k = kk[u];
             const int base = (j - k) * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) { b1[base + r * ns] = v[u][r]; b2[base + r * ns] = w[u][r]; }
         }
     }
-    __syncthreads();
 }
 
 template <int NT, int NMAX, typename T>
@@ -139,6 +164,7 @@ __device__ void blk_fft2(cpx<T>* b1, cpx<T>* b2, const Plan& p, const cpx<T>* __
         tw += (r - 1) * ns;
         ns *= r;
     }
+    __syncthreads();
 }
 
 template <int NT, int NMAX, typename T>
@@ -157,6 +183,7 @@ __device__ void blk_fft(cpx<T>* buf, const Plan& p, const cpx<T>* __restrict__ t
         tw += (r - 1) * ns;
         ns *= r;
     }
+    __syncthreads();
 }
 
 // ------------------------------------------------------------------- team engine
