@@ -256,8 +256,9 @@ ca_status_t srv_transform(ca_context_t ctx, const void* curves, const int64_t* o
  *                                                           1..256 (default 64)
  *   CA_TUNE_BLOCK_PLAN      M, a transform size with no  1..16: radix schedule of the block
  *                           prime factor above 7,           engine's FFT of size M, radices
- *                           2 <= M <= 2 * CA_MAX_N          2, 3, 4, 5, 7, 8 whose product
- *                                                           is M (default: eights, then a four
+ *                           2 <= M <= 2 * CA_MAX_N          2, 3, 4, 5, 7, 8 (and 16 when
+ *                                                           M > 2048) whose product is M
+ *                                                           (default: eights, then a four
  *                                                           or two, then 3, 5, 7)
  *   CA_TUNE_BLOCK_GRID      size class 0..4 of the block 1: persistent blocks per CU,
  *                           engine (M <= 512, 1024, 2048,   multiples of the occupancy limit,
@@ -287,8 +288,8 @@ enum {
  * fastest and report its time per launch in *best_ms (optional).  Candidates:
  * grid knobs 1, 2, 4 and 0; all-pairs columns 2, 4, 8, 16, 32, 64; threads
  * 256 and 512; radix
- * schedules: the orderings of the power-of-two part as eights, fours or
- * mixed, each with the odd radices first or last.  The first candidate runs
+ * schedules: the orderings of the power-of-two part as eights, fours,
+ * mixed or (M > 2048) sixteens, each with the odd radices first or last.  The first candidate runs
  * for about 20 ms first so that the clock settles; then every candidate is
  * timed with HIP events on `stream` in each of three rounds (three launches
  * after one warm-up launch per round) and keeps its best round.

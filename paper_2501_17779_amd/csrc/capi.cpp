@@ -71,7 +71,8 @@ bool valid_radices(int m, const std::vector<int>& r) {
     if (r.empty() || r.size() > 16) return false;
     int64_t prod = 1;
     for (int x : r) {
-        if (x != 2 && x != 3 && x != 4 && x != 5 && x != 7 && x != 8) return false;
+        if (x != 2 && x != 3 && x != 4 && x != 5 && x != 7 && x != 8 && x != 16) return false;
+        if (x == 16 && m <= kBlkR16Min / 2) return false;   // only the large classes compile it
         prod *= x;
         if (prod > m) return false;
     }

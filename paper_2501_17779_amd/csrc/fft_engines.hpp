@@ -148,6 +148,11 @@ __device__ __forceinline__ void blk_pass2(cpx<T>* b1, cpx<T>* b2, int n, int ns,
     }
 }
 
+// Radix 16 is compiled only into the kernels of the large size classes (it
+// needs more registers than the others can spare); plans use it only for
+// transform sizes above kBlkR16Min / 2.
+constexpr int kBlkR16Min = 4096;
+
 template <int NT, int NMAX, typename T>
 __device__ void blk_fft2(cpx<T>* b1, cpx<T>* b2, const Plan& p, const cpx<T>* __restrict__ tw) {
     int ns = 1;
@@ -159,6 +164,12 @@ __device__ void blk_fft2(cpx<T>* b1, cpx<T>* b2, const Plan& p, const cpx<T>* __
             case 4: blk_pass2<4, NT, NMAX>(b1, b2, p.n, ns, tw); break;
             case 5: blk_pass2<5, NT, NMAX>(b1, b2, p.n, ns, tw); break;
             case 7: blk_pass2<7, NT, NMAX>(b1, b2, p.n, ns, tw); break;
+            case 16:
+                if constexpr (NMAX >= kBlkR16Min) {
+                    blk_pass2<16, NT, NMAX>(b1, b2, p.n, ns, tw);
+                    break;
+                }
+                [[fallthrough]];
             default: blk_pass2<8, NT, NMAX>(b1, b2, p.n, ns, tw); break;
         }
         tw += (r - 1) * ns;
@@ -178,6 +189,12 @@ __device__ void blk_fft(cpx<T>* buf, const Plan& p, const cpx<T>* __restrict__ t
             case 4: blk_pass<4, NT, NMAX>(buf, p.n, ns, tw); break;
             case 5: blk_pass<5, NT, NMAX>(buf, p.n, ns, tw); break;
             case 7: blk_pass<7, NT, NMAX>(buf, p.n, ns, tw); break;
+            case 16:
+                if constexpr (NMAX >= kBlkR16Min) {
+                    blk_pass<16, NT, NMAX>(buf, p.n, ns, tw);
+                    break;
+                }
+                [[fallthrough]];
             default: blk_pass<8, NT, NMAX>(buf, p.n, ns, tw); break;
         }
         tw += (r - 1) * ns;

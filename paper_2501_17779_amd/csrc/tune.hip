@@ -156,8 +156,9 @@ ca_status_t install(ca_context* c, int knob, int key, const std::vector<int>& v,
 
 // Radix schedules tried for size m: the power-of-two part as eights (with a
 // trailing four or two), as eights with the remainder first, as fours (with a
-// trailing two), and as eights and fours alternating; each with the odd
-// radices last or first.  Duplicates removed, the default first.
+// trailing two), as eights and fours alternating, and (sizes of the large
+// classes only) as sixteens with the remainder last or first; each with the
+// odd radices last or first.  Duplicates removed, the default first.
 std::vector<std::vector<int>> plan_candidates(int m) {
     int p2 = 0, rest = m;
     while (rest % 2 == 0) { rest /= 2; ++p2; }
@@ -196,6 +197,19 @@ std::vector<std::vector<int>> plan_candidates(int m) {
             eight = !eight;
         }
         pow2.push_back(a);
+    }
+    if (m > ca::kBlkR16Min / 2 && p2 >= 4) {
+        std::vector<int> a, rem;
+        int e = p2;
+        while (e >= 4) { a.push_back(16); e -= 4; }
+        if (e == 3) rem.push_back(8);
+        if (e == 2) rem.push_back(4);
+        if (e == 1) rem.push_back(2);
+        std::vector<int> b = rem;
+        b.insert(b.end(), a.begin(), a.end());
+        a.insert(a.end(), rem.begin(), rem.end());
+        pow2.push_back(a);
+        pow2.push_back(b);
     }
     std::vector<std::vector<int>> out;
     out.push_back(default_radices(m));

@@ -251,7 +251,8 @@ def test_tuning_arguments_rejected_on_host(L):
     assert setv(1, 512, 0) == ca.ERR_INVALID_ARG
     assert setv(1, 512, 257) == ca.ERR_INVALID_ARG
     assert setv(2, 4096, 8, 8, 8) == ca.ERR_INVALID_ARG          # product 512
-    assert setv(2, 4096, 16, 16, 16) == ca.ERR_INVALID_ARG       # radix 16 is not a block-engine radix
+    assert setv(2, 2048, 16, 16, 8) == ca.ERR_INVALID_ARG        # radix 16 only above M = 2048
+    assert setv(2, 3072, 6, 16, 32) == ca.ERR_INVALID_ARG        # 6 and 32 are not radices
     assert setv(2, 3000, 8, 3, 5, 5) == ca.ERR_INVALID_ARG       # product 600
     assert setv(3, 0, 9) == ca.ERR_INVALID_ARG
     assert setv(4, 2, 256) == ca.ERR_INVALID_ARG                  # classes 3 and 4 only
@@ -288,7 +289,8 @@ def test_tuning_file_rejections_on_host(L, tmp_path):
         "value": head % '[{"knob": "team_grid", "key": 1024, "values": [9]}]',
         "cols": head % '[{"knob": "allpairs_cols", "key": 512, "values": [0]}]',
         "plan_product": head % '[{"knob": "block_plan", "key": 4096, "values": [8, 8, 8]}]',
-        "plan_radix": head % '[{"knob": "block_plan", "key": 4096, "values": [16, 16, 16]}]',
+        "plan_radix": head % '[{"knob": "block_plan", "key": 4096, "values": [32, 16, 8]}]',
+        "plan_r16_small": head % '[{"knob": "block_plan", "key": 1024, "values": [16, 16, 4]}]',
         "plan_key": head % '[{"knob": "block_plan", "key": 4099, "values": [4099]}]',
         "class": head % '[{"knob": "block_grid", "key": 5, "values": [1]}]',
         "threads": head % '[{"knob": "block_threads", "key": 4, "values": [1024]}]',

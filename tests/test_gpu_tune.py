@@ -83,7 +83,7 @@ def test_autotune_radix_schedule(ca, ctx, M):
     r = ca.tune_get("block_plan", M, ctx=ctx)
     note(f"block_plan[{M}] -> {r} at {ms:.4f} ms")
     assert ms > 0.0
-    assert int(np.prod(r)) == M and set(r) <= {2, 3, 4, 5, 7, 8}
+    assert int(np.prod(r)) == M and set(r) <= ({2, 3, 4, 5, 7, 8, 16} if M > 2048 else {2, 3, 4, 5, 7, 8})
 
 
 def test_autotune_rejects_unused_transform_size(ca, ctx):
@@ -150,6 +150,37 @@ def test_radix_schedules_pass_acceptance(ca, ctx, n, plans):
         rec64 = ca.to_numpy(ca.align_batch(g1d, g2d, precision="fp64", ctx=ctx))
         st64 = acc.check_batch(rec64, z1d, z2d, theta_tol=1e-10, e_rtol=1e-10)
         note(f"  fp32 {st}\n  fp64 {st64}")
+
+
+# radix 16 (transform sizes above 2048): n = 4096 in FP32 and FP64, and the
+# zero-padded n = 4093 (M = 8192, FP32 only)
+R16 = [
+    (4096, [[16, 16, 16], [16, 16, 4, 4], [4, 16, 16, 4], [16, 8, 8, 4]], True),
+    (3072, [[16, 16, 4, 3], [3, 16, 16, 4], [3, 4, 16, 16]], True),
+    (4093, [[16, 16, 16, 2], [2, 16, 16, 16], [8, 16, 16, 4]], False),
+]
+
+
+@pytest.mark.parametrize("n,plans,fp64", R16)
+def test_radix16_schedules_pass_acceptance(ca, ctx, n, plans, fp64):
+    M = transform_size(n)
+    B = 16
+    z1, z2 = inputs.batch(760 + n % 97, B, n)
+    g1, g2 = gpu(z1), gpu(z2)
+    off = gpu(np.arange(B + 1, dtype=np.int64) * n)
+    f1, f2 = g1.reshape(-1), g2.reshape(-1)
+    z1d, z2d = z1.astype(np.complex128), z2.astype(np.complex128)
+    g1d, g2d = gpu(z1d), gpu(z2d)
+    for r in plans:
+        assert int(np.prod(r)) == M
+        ca.tune_set("block_plan", M, r, ctx=ctx)
+        assert ca.tune_get("block_plan", M, ctx=ctx) == r
+        note(f"n={n} M={M} plan {r}")
+        rec = ca.to_numpy(ca.align_batch(f1, f2, offsets=off, ctx=ctx))
+        note(f"  fp32 {acc.check_batch(rec, z1, z2)}")
+        if fp64:
+            rec64 = ca.to_numpy(ca.align_batch(g1d, g2d, precision="fp64", ctx=ctx))
+            note(f"  fp64 {acc.check_batch(rec64, z1d, z2d, theta_tol=1e-10, e_rtol=1e-10)}")
 
 
 def test_fp64_arena_built_after_plan_change(ca, ctx):
