@@ -32,7 +32,9 @@ __global__ __launch_bounds__(256, 2) void k_align_team(const cf* __restrict__ z1
     __shared__ cf lds_all[TEAMS * BUF];
     __shared__ int cand_all[TEAMS * kCandCap];
     load_twiddles<TeamCfg<N>::TW>(tws, tw);
-    const int team = threadIdx.x / T;
+    // a team of 64 is one wave: its pair index is wave-uniform, which keeps
+    // the pair's base addresses in scalar registers
+    const int team = T == 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / T) : threadIdx.x / T;
     const int t = threadIdx.x % T;
     cf* lds = lds_all + team * BUF;
     int* cand = cand_all + team * kCandCap;

@@ -97,7 +97,7 @@ ca_status_t validate(int knob, int key, const std::vector<int>& v) {
                 return fail(CA_ERR_INVALID_ARG, "block_plan key must be a 7-smooth size in [2, 8192]");
             if (!valid_radices(key, v))
                 return fail(CA_ERR_INVALID_ARG,
-                            "block_plan takes 1..16 radices from {2, 3, 4, 5, 7, 8} whose product is the key");
+                            "block_plan takes 1..16 radices from {2, 3, 4, 5, 7, 8} (and 16 for keys above 2048) whose product is the key");
             return CA_OK;
         case CA_TUNE_BLOCK_GRID:
             if (key < 0 || key >= ca::kBlkClasses) return fail(CA_ERR_INVALID_ARG, "block_grid key must be 0..4");
