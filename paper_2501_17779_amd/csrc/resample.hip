@@ -378,13 +378,16 @@ __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x)
 // sends the curve to the general kernel.
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 // Lane i receives lane (i + 1) mod 64, resp. (i - 1) mod 64 (DPP wave
-// rotations; the whole wave must be active).
+// rotations; the whole wave must be active, so every lane is written and no
+// previous value is kept).
 __device__ __forceinline__ float wave_rol1(float x) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x134, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x134, 0xF, 0xF, false));
 }
 __device__ __forceinline__ float wave_ror1(float x) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x13C, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x13C, 0xF, 0xF, false));
 }
+__device__ __forceinline__ cf wave_rol1(cf z) { return {wave_rol1(z.x), wave_rol1(z.y)}; }
+__device__ __forceinline__ cf wave_ror1(cf z) { return {wave_ror1(z.x), wave_ror1(z.y)}; }
 
 // Inclusive scan of a double over the wave: shifts by 1, 2, 4, 8 inside each
 // row of 16 lanes (DPP row_shr; lanes without a source add 0), then the row
@@ -441,22 +444,22 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
     const cf p0 = M > 0 ? P[0] : cf{0.0f, 0.0f};
     auto group = [&](auto full, int j0) {
         constexpr bool kFull = decltype(full)::value;
-        cf a[kP1 + 1];
+        cf a[kP1 + 1], rot[kP1 + 1];
 #pragma unroll
         for (int u = 0; u < kP1; ++u) {
             const int j = j0 + lane + 64 * u;
             a[u] = P[(kFull || j < M) ? j : 0];
         }
-        a[kP1] = P[(kFull || j0 + 64 * kP1 < M) ? j0 + 64 * kP1 : 0];
+        a[kP1] = P[(kFull || j0 + 64 * kP1 < M) ? j0 + 64 * kP1 : 0];   // the same on every lane
+#pragma unroll
+        for (int u = 0; u < kP1; ++u) rot[u] = wave_rol1(a[u]);
+        rot[kP1] = a[kP1];
 #pragma unroll
         for (int u = 0; u < kP1; ++u) {
             const int j = j0 + lane + 64 * u;
-            cf b = {wave_rol1(a[u].x), wave_rol1(a[u].y)};
-            const float nx = rdlane(a[u + 1].x, 0), ny = rdlane(a[u + 1].y, 0);
-            if (lane == 63) {
-                b.x = nx;
-                b.y = ny;
-            }
+            // lane 63's successor is lane 0's vertex of the next step, which
+            // the rotation of that step has put in lane 63
+            cf b = lane == 63 ? rot[u + 1] : rot[u];
             if (!kFull && j + 1 == M) b = p0;  // closing chord back to vertex 0
             if (kFull || j < M) {
                 const float dx = b.x - a[u].x, dy = b.y - a[u].y;
@@ -509,35 +512,34 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
         // all from registers: the successor of staged knot lane + 64 u is the
         // next lane's (lane 63: lane 0 of u + 1), the slope D_{i-1} the
         // previous lane's (lane 0: lane 63 of u - 1)
-        cf dprev = {0.0f, 0.0f};
+        // (a rotation of step u + 1 puts lane 0's knot in lane 63, one of step
+        // u - 1 lane 63's slope in lane 0)
+        auto stage = [&](auto spline) {
+            constexpr bool kSpline = decltype(spline)::value;
+            cf rot[kStage];
 #pragma unroll
-        for (int u = 0; u < kStage; ++u) {
-            const int i = lane + 64 * u;
-            cf q = {wave_rol1(pre[u].x), wave_rol1(pre[u].y)};
-            if (u + 1 < kStage) {
-                const float nx = rdlane(pre[u + 1].x, 0), ny = rdlane(pre[u + 1].y, 0);
-                if (lane == 63) {
-                    q.x = nx;
-                    q.y = ny;
+            for (int u = 0; u < kStage; ++u) rot[u] = wave_rol1(pre[u]);
+            cf dmprev = {0.0f, 0.0f};
+#pragma unroll
+            for (int u = 0; u < kStage; ++u) {
+                const int i = lane + 64 * u;
+                const cf q = (u + 1 < kStage && lane == 63) ? rot[u + 1 < kStage ? u + 1 : u] : rot[u];
+                const float dx = q.x - pre[u].x, dy = q.y - pre[u].y;
+                const float h = fsqrt(dx * dx + dy * dy);
+                if (i < kFtP) sP[kpl + 72 * u] = pre[u];
+                if (i < kFtP - 1) sH[kpl + 72 * u] = h;
+                if constexpr (kSpline) {
+                    const float ih = frcp(h);
+                    const cf d = {dx * ih, dy * ih};
+                    const cf dr = wave_ror1(d);
+                    const cf dm = lane == 0 ? dmprev : dr;
+                    if (i >= 1 && i < kFtP - 1) sR[kpl + 72 * u] = {6.0f * (d.x - dm.x), 6.0f * (d.y - dm.y)};
+                    dmprev = dr;
                 }
             }
-            const float dx = q.x - pre[u].x, dy = q.y - pre[u].y;
-            const float h = fsqrt(dx * dx + dy * dy);
-            if (i < kFtP) sP[kpl + 72 * u] = pre[u];
-            if (i < kFtP - 1) sH[kpl + 72 * u] = h;
-            if (mode == CA_RESAMPLE_SPLINE) {
-                const float ih = frcp(h);
-                const cf d = {dx * ih, dy * ih};
-                cf dm = {wave_ror1(d.x), wave_ror1(d.y)};
-                const float px = rdlane(dprev.x, 63), py = rdlane(dprev.y, 63);
-                if (lane == 0) {
-                    dm.x = px;
-                    dm.y = py;
-                }
-                if (i >= 1 && i < kFtP - 1) sR[kpl + 72 * u] = {6.0f * (d.x - dm.x), 6.0f * (d.y - dm.y)};
-                dprev = d;
-            }
-        }
+        };
+        if (mode == CA_RESAMPLE_SPLINE) stage(std::true_type{});
+        else stage(std::false_type{});
         // start loading the next tile's vertices (no wrap-around except near the end)
         if (!last) {
             const int b0 = a + kFtK - 1 - kFtH;
