@@ -670,7 +670,10 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
         const bool seg = team_max<64>(ne - ns) <= kFtSegMax;
         float sk[kFtC];                        // this lane's knot parameters
 #pragma unroll
-        for (int k = 1; k < kFtC; ++k) sk[k] = (j0 + k <= kt - 2) ? sS[kp(j0 + k)] : 3.0e38f;
+        for (int k = 1; k < kFtC; ++k) {
+            const float v = sS[kp(j0 + k)];    // j0 + k <= 511: inside sS
+            sk[k] = (j0 + k <= kt - 2) ? v : 3.0e38f;
+        }
         const int nbeg = seg ? ns : nlo + lane, nend = seg ? ne : nhi, nstep = seg ? 1 : 64;
         for (int nn = nbeg; nn < nend; nn += nstep) {
             const float u = upar(nn);
