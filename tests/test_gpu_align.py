@@ -243,3 +243,44 @@ def test_full_size_batch_sampled(ca):
     note(f"full size sampled: {st}")
     fl = ca.unpack(out)["flags"]
     assert int(((fl & (ca.FLAG_DEGENERATE | ca.FLAG_NONFINITE)) != 0).sum().item()) == 0
+
+
+@pytest.mark.parametrize("snap", [True, False])
+def test_full_size_ragged_sampled(ca, snap):
+    """The ragged workload in the benchmark's launch configuration: 100,000
+    raw polygon pairs (n log-uniform in [64, 4096]; snap=False keeps every
+    integer n, so padded transforms run too) resampled on the GPU, then one
+    ragged align_batch; sampled pairs, a third of them from the largest size
+    classes, checked against the oracle on the GPU's own nodes."""
+    from synth import curves
+    B = 100000
+    note(f"full-size ragged (snap={snap}): generating")
+    d = curves.ragged_pairs_torch(17782, B, "cuda", snap=snap)
+    raw = torch.cat([d["raw1"], d["raw2"]])
+    roff = torch.cat([d["off1"], d["off2"][1:] + d["off1"][-1]])
+    n = d["n"].long()
+    ooff = torch.zeros(2 * B + 1, dtype=torch.int64, device="cuda")
+    ooff[1:] = torch.cumsum(torch.cat([n, n]), 0)
+    note("full-size ragged: resample_arclength")
+    nodes, _, _ = ca.resample_arclength(raw, roff, ooff, with_norms=False, with_flags=False)
+    off = ooff[: B + 1].contiguous()
+    half = int(off[-1].item())
+    note("full-size ragged: align_batch with offsets")
+    out = ca.align_batch(nodes[:half], nodes[half:], offsets=off)
+    torch.cuda.synchronize()
+    fl = ca.unpack(out)["flags"]
+    assert int(((fl & (ca.FLAG_DEGENERATE | ca.FLAG_NONFINITE | ca.FLAG_UNSUPPORTED_N)) != 0).sum().item()) == 0
+    n_h = n.cpu().numpy()
+    rng = np.random.default_rng(5 if snap else 6)
+    big = np.flatnonzero(n_h > 2048)
+    idx = np.concatenate([rng.choice(B, 20, replace=False), rng.choice(big, 10, replace=False)])
+    res = ca.to_numpy(out[torch.from_numpy(idx).cuda()])
+    off_h = off.cpu().numpy()
+    stats = []
+    for r, b in zip(res, idx):
+        z1 = nodes[off_h[b]:off_h[b + 1]].cpu().numpy()
+        z2 = nodes[half + off_h[b]:half + off_h[b + 1]].cpu().numpy()
+        stats.append(acc.check_pair(r, z1, z2))
+    note(f"full-size ragged sampled: {len(stats)} pairs, n up to {int(n_h[idx].max())}, "
+         f"theta err max {max(s['theta_err'] for s in stats):.3g}, "
+         f"e0 rel err max {max(s['e0_rel_err'] for s in stats):.3g}")
