@@ -320,12 +320,17 @@ __global__ void k_zero_ints(int* p, int count) {
     if (i < count) p[i] = 0;
 }
 
-// Ragged batches: every pair goes to the list of its size class (wave-
-// aggregated atomics; the order inside a list does not affect any result);
-// pairs that no class can take get their CA_FLAG_UNSUPPORTED_N record here.
+// Ragged batches: every pair goes to the list of its size class (the order
+// inside a list does not affect any result); pairs that no class can take get
+// their CA_FLAG_UNSUPPORTED_N record here.  Positions are reserved per wave in
+// LDS and per block with one global atomic per class; the class counters sit
+// in separate cache lines, so the blocks' atomics on different classes do not
+// queue on one line.
 __global__ __launch_bounds__(256) void k_blk_bin(const int64_t* __restrict__ offsets, int64_t num_pairs,
                                                  const Plan* __restrict__ plans, int mcap, int* __restrict__ bins,
                                                  ca_result_t* __restrict__ out) {
+    __shared__ int s_cnt[kBlkClasses], s_base[kBlkClasses];
+    if (threadIdx.x < kBlkClasses) s_cnt[threadIdx.x] = 0;
     const int64_t pair = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int cls = -1;
     if (pair < num_pairs) {
@@ -341,17 +346,26 @@ __global__ __launch_bounds__(256) void k_blk_bin(const int64_t* __restrict__ off
             cls = blk_class(M);
         }
     }
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const uint64_t below = (1ull << lane) - 1ull;
+    int pos = 0;                                   // position inside the block's share of the list
     for (int c = 0; c < kBlkClasses; ++c) {
         const uint64_t mask = __ballot(cls == c);
         if (mask == 0ull) continue;
         const int leader = __ffsll((long long)mask) - 1;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&bins[c], __popcll(mask));
-        base = __shfl(base, leader, 64);
-        if (cls == c) bins[kBlkClasses + c * num_pairs + base + __popcll(mask & below)] = (int)pair;
+        int wbase = 0;
+        if (lane == leader) wbase = atomicAdd(&s_cnt[c], __popcll(mask));
+        wbase = __shfl(wbase, leader, 64);
+        if (cls == c) pos = wbase + __popcll(mask & below);
     }
+    __syncthreads();
+    if (threadIdx.x < kBlkClasses) {
+        const int k = s_cnt[threadIdx.x];
+        s_base[threadIdx.x] = k > 0 ? atomicAdd(&bins[threadIdx.x * kBinStride], k) : 0;
+    }
+    __syncthreads();
+    if (cls >= 0) bins[kBlkClasses * kBinStride + cls * num_pairs + s_base[cls] + pos] = (int)pair;
 }
 
 template <typename T, int NT, int MMAX>
@@ -499,8 +513,8 @@ static hipError_t launch_blk_class(const BlkArgs& a, int cls, hipStream_t s) {
     if (g < 0) return hipErrorInvalidValue;
     int64_t grid = g == 0 ? a.num_pairs : (int64_t)a.num_cus * per_cu * g;
     if (grid > a.num_pairs) grid = a.num_pairs;
-    const int* count = a.offsets ? a.bins + cls : nullptr;
-    const int* list = a.offsets ? a.bins + kBlkClasses + cls * a.num_pairs : nullptr;
+    const int* count = a.offsets ? a.bins + cls * kBinStride : nullptr;
+    const int* list = a.offsets ? a.bins + kBlkClasses * kBinStride + cls * a.num_pairs : nullptr;
     hipLaunchKernelGGL((k_align_blk<T, NT, MMAX>), dim3((unsigned)grid), dim3(NT), 0, s,
                        (const cpx<T>*)a.z1, (const cpx<T>*)a.z2, a.offsets, a.n_uniform, a.num_pairs, a.out,
                        a.plans, (const cpx<T>*)a.tw_arena, a.rescore, a.theta64, count, list);
@@ -516,7 +530,8 @@ static hipError_t launch_blk(const BlkArgs& a, hipStream_t s) {
     const int lo = a.offsets ? 0 : a.m_uniform, hi = a.offsets ? a.m_cap : a.m_uniform;
     hipError_t e = hipSuccess;
     if (a.offsets) {
-        hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, s, a.bins, kBlkClasses);
+        hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(kBlkClasses * kBinStride), 0, s, a.bins,
+                           kBlkClasses * kBinStride);
         hipLaunchKernelGGL(k_blk_bin, dim3((unsigned)((a.num_pairs + 255) / 256)), dim3(256), 0, s, a.offsets,
                            a.num_pairs, a.plans, a.m_cap, a.bins, a.out);
         e = hipGetLastError();

@@ -32,12 +32,14 @@ struct BlkArgs {
     // threads per block of the FP32 classes 3 and 4 (256 or 512; other
     // classes and FP64 use their fixed sizes)
     int threads[kBlkClasses];
-    // ragged batches: device workspace of kBlkClasses counters followed by
-    // kBlkClasses lists of num_pairs pair indices (blk_bin_ints(num_pairs) ints)
+    // ragged batches: device workspace of kBlkClasses counters (kBinStride
+    // ints apart, one cache line each) followed by kBlkClasses lists of
+    // num_pairs pair indices (blk_bin_ints(num_pairs) ints)
     int* bins;
 };
 
-inline int64_t blk_bin_ints(int64_t num_pairs) { return kBlkClasses + kBlkClasses * num_pairs; }
+constexpr int kBinStride = 32;
+inline int64_t blk_bin_ints(int64_t num_pairs) { return kBlkClasses * kBinStride + kBlkClasses * num_pairs; }
 
 // Persistent size-class kernels, one pair per workgroup at a time,
 // LDS-resident Stockham FFT.  A 7-smooth n is transformed at size n; any
