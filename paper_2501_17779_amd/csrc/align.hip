@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256, TeamCfg<N>::AW) void k_allpairs(const cf* __re
     __shared__ int cand_all[TEAMS * kCandCap];
     const int i0 = blockIdx.y * TEAMS;
     const int j0 = blockIdx.x * cols;
-    if (j0 + cols - 1 <= i0) return;   // no j > i in this tile
+    if (j0 >= m || j0 + cols - 1 <= i0) return;   // padding column tile, or no j > i in this tile
     load_twiddles<TeamCfg<N>::TW>(tws, tw);
     const int team = threadIdx.x / T;
     const int t = threadIdx.x % T;
@@ -267,7 +267,12 @@ static hipError_t launch_allpairs_n(const void* curves, const void* spec, const 
                                     hipStream_t s) {
     constexpr int TEAMS = 256 / TeamCfg<N>::T;
     if (cols < 1) return hipErrorInvalidValue;
-    dim3 grid((unsigned)((m + cols - 1) / cols), (unsigned)((m + TEAMS - 1) / TEAMS));
+    // Workgroups are dealt to the 8 XCDs round-robin by linear id x + y gx;
+    // with gx a multiple of 8 every column tile x lands on XCD x mod 8 for
+    // all row tiles y, so its spectra and nodes are reused from that XCD's L2
+    // (the padding columns exit at once).
+    const unsigned gx = (unsigned)(((m + cols - 1) / cols + 7) / 8 * 8);
+    dim3 grid(gx, (unsigned)((m + TEAMS - 1) / TEAMS));
     hipLaunchKernelGGL((k_allpairs<N>), grid, dim3(256), 0, s, (const cf*)curves, (const cf*)spec,
                        norms, m, cols, out, (const cf*)tw, rescore, theta64);
     return hipGetLastError();
