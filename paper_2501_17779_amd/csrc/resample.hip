@@ -500,7 +500,7 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
 #pragma unroll
     for (int u = 0; u < kStage; ++u) {
         const int i = lane + 64 * u;
-        if (i < kFtP) pre[u] = P[vert(i - kFtH)];
+        if (64 * (u + 1) <= kFtP || i < kFtP) pre[u] = P[vert(i - kFtH)];
     }
     // LDS index of staged knot lane + 64 u is kpl + 72 u (kp adds one slot per eight)
     const int kpl = kp(lane);
@@ -523,17 +523,20 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
 #pragma unroll
             for (int u = 0; u < kStage; ++u) {
                 const int i = lane + 64 * u;
+                // every step but the last stages only knots below kFtP - 1
+                const bool kInside = 64 * (u + 1) <= kFtP - 1;   // folds once the loop is unrolled
                 const cf q = (u + 1 < kStage && lane == 63) ? rot[u + 1 < kStage ? u + 1 : u] : rot[u];
                 const float dx = q.x - pre[u].x, dy = q.y - pre[u].y;
                 const float h = fsqrt(dx * dx + dy * dy);
-                if (i < kFtP) sP[kpl + 72 * u] = pre[u];
-                if (i < kFtP - 1) sH[kpl + 72 * u] = h;
+                if (kInside || i < kFtP) sP[kpl + 72 * u] = pre[u];
+                if (kInside || i < kFtP - 1) sH[kpl + 72 * u] = h;
                 if constexpr (kSpline) {
                     const float ih = frcp(h);
                     const cf d = {dx * ih, dy * ih};
                     const cf dr = wave_ror1(d);
                     const cf dm = lane == 0 ? dmprev : dr;
-                    if (i >= 1 && i < kFtP - 1) sR[kpl + 72 * u] = {6.0f * (d.x - dm.x), 6.0f * (d.y - dm.y)};
+                    if ((u > 0 || i >= 1) && (kInside || i < kFtP - 1))
+                        sR[kpl + 72 * u] = {6.0f * (d.x - dm.x), 6.0f * (d.y - dm.y)};
                     dmprev = dr;
                 }
             }
@@ -547,13 +550,13 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
 #pragma unroll
                 for (int u = 0; u < kStage; ++u) {
                     const int i = lane + 64 * u;
-                    if (i < kFtP) pre[u] = P[b0 + i];
+                    if (64 * (u + 1) <= kFtP || i < kFtP) pre[u] = P[b0 + i];
                 }
             } else {
 #pragma unroll
                 for (int u = 0; u < kStage; ++u) {
                     const int i = lane + 64 * u;
-                    if (i < kFtP) pre[u] = P[vert(b0 + i)];
+                    if (64 * (u + 1) <= kFtP || i < kFtP) pre[u] = P[vert(b0 + i)];
                 }
             }
         }
@@ -724,17 +727,19 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
     sy = wave_sum_d(sy);
     const float mx = (float)(sx / N), my = (float)(sy / N);
     double q2 = 0.0;
-    for (int n0 = 0; n0 < N; n0 += 64 * 8) {   // eight loads in flight per lane
+    // eight loads in flight per lane; groups that end before N skip the range checks
+    auto centre = [&](auto full, int n0) {
+        constexpr bool kFull = decltype(full)::value;
         cf zz[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int nn = n0 + lane + 64 * u;
-            if (nn < N) zz[u] = o[nn];
+            if (kFull || nn < N) zz[u] = o[nn];
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int nn = n0 + lane + 64 * u;
-            if (nn < N) {
+            if (kFull || nn < N) {
                 cf z = zz[u];
                 z.x -= mx;
                 z.y -= my;
@@ -742,6 +747,10 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
                 q2 = fma((double)z.x, (double)z.x, fma((double)z.y, (double)z.y, q2));
             }
         }
+    };
+    for (int n0 = 0; n0 < N; n0 += 64 * 8) {
+        if (n0 + 64 * 8 <= N) centre(std::true_type{}, n0);
+        else centre(std::false_type{}, n0);
     }
     q2 = wave_sum_d(q2);
     if (lane == 0) {
