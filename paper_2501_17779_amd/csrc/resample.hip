@@ -487,6 +487,10 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
     const double area2 = wave_sum_d((double)ar);
     const double invL = 1.0 / L;
     const double uN = L / (double)N;           // arc length between output nodes
+    // node index of an arc length, up to rounding: the tile bounds below are
+    // the same expression of the same carry for consecutive tiles, so every
+    // node is placed exactly once whatever the rounding
+    const double inv_uN = (double)N / L;
 
     // pass 2: tiles of kFtK knots starting at a; segments [a, a + kFtK - 1)
     double carry = 0.0;                        // arc length at knot a
@@ -645,8 +649,8 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
         }
         wave_lds_sync();
         // output nodes with arc length in [carry, carry + span) (up to N on the last tile)
-        const int nlo = (int)ceil(carry / uN);
-        const int nhi = last ? N : min(N, (int)ceil((carry + span) / uN));
+        const int nlo = (int)ceil(carry * inv_uN);
+        const int nhi = last ? N : min(N, (int)ceil((carry + span) * inv_uN));
         const float il = (float)invL;
         auto upar = [&](int nn) { return (float)((double)nn * uN - carry); };
         // Node nn lies on segment j = the largest j in [0, kt - 2] with
@@ -662,7 +666,7 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
             ns = nlo;
         } else if (j0 <= kt - 2) {
             const float s0 = sS[kp(j0)];
-            int e = (int)ceil((carry + (double)s0) / uN);
+            int e = (int)ceil((carry + (double)s0) * inv_uN);
             e = max(nlo, min(nhi, e));
             while (e > nlo && upar(e - 1) >= s0) --e;
             while (e < nhi && upar(e) < s0) ++e;
