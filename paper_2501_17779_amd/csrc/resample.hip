@@ -350,17 +350,19 @@ __global__ __launch_bounds__(kRsNT) void k_resample(const cf* __restrict__ raw, 
 // and the local spline solves are computed there, and every output node
 // whose parameter falls in the tile is evaluated after a binary search over
 // the tile's knots.  Pass 3 centres the nodes and accumulates their norm.
-constexpr int kFtK = 512;                  // knots per tile
+constexpr int kFtC = 7;                    // knots per lane in the local solve
+constexpr int kFtK = 64 * kFtC;            // knots per tile
 constexpr int kFtH = kRsW + 1;             // halo on each side
 constexpr int kFtP = kFtK + 2 * kFtH;      // staged knots
-constexpr int kFtC = 8;                    // knots per lane in the local solve
 constexpr int kFtSegMax = 24;              // most nodes per lane for lane-owned segments
-// Per-knot LDS arrays are padded with one slot per 8 entries: the local solve
-// and the scan give lane l the knots [8 l, 8 l + 8), a stride that would put
-// lanes 8 apart in the same bank.
-constexpr int kFtPP = kFtP + kFtP / 8 + 1;
-constexpr int kFtKP = kFtK + kFtK / 8 + 1;
-__device__ __forceinline__ int kp(int i) { return i + (i >> 3); }
+// Per-knot LDS arrays are not padded: the local solve and the scan give lane
+// l the knots [7 l, 7 l + 7), a stride coprime to the bank count.  The
+// spline moments share the right-hand sides' array (the solve's sweeps read
+// every right-hand side before the back substitution writes a moment), which
+// with 7 knots per lane keeps a wave's LDS at ~11 KB: three waves per SIMD.
+constexpr int kFtPP = kFtP;
+constexpr int kFtKP = kFtK + 1;
+__device__ __forceinline__ int kp(int i) { return i; }
 
 __device__ __forceinline__ int wrapm(int i, int m) {
     while (i < 0) i += m;
@@ -409,16 +411,16 @@ __device__ __forceinline__ double wave_incl_scan(double x, int lane) {
     return x + off;
 }
 
-__global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw, const int64_t* __restrict__ raw_off,
+__global__ __launch_bounds__(64, 3) void k_resample_fast(const cf* __restrict__ raw, const int64_t* __restrict__ raw_off,
                                                       int64_t num_curves, const int64_t* __restrict__ out_off,
                                                       cf* __restrict__ out, double* __restrict__ norms,
                                                       uint32_t* __restrict__ flags, int mode,
                                                       int* __restrict__ slow_count, int* __restrict__ slow_list) {
     __shared__ cf sP[kFtPP];
     __shared__ float sH[kFtPP];
-    __shared__ cf sR[kFtPP];
+    __shared__ cf sR[kFtPP > kFtKP ? kFtPP : kFtKP];
     __shared__ float sS[kFtKP];
-    __shared__ cf sM[kFtKP];
+    cf* const sM = sR;                         // moments over the right-hand sides
     const int64_t c = blockIdx.x;
     if (c >= num_curves) return;
     const int lane = threadIdx.x;
@@ -506,7 +508,7 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
         const int i = lane + 64 * u;
         if (64 * (u + 1) <= kFtP || i < kFtP) pre[u] = P[vert(i - kFtH)];
     }
-    // LDS index of staged knot lane + 64 u is kpl + 72 u (kp adds one slot per eight)
+    // LDS index of staged knot lane + 64 u
     const int kpl = kp(lane);
     for (int a = 0; a < M; a += kFtK - 1) {
         const bool last = (a + kFtK - 1 >= M);
@@ -532,15 +534,15 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
                 const cf q = (u + 1 < kStage && lane == 63) ? rot[u + 1 < kStage ? u + 1 : u] : rot[u];
                 const float dx = q.x - pre[u].x, dy = q.y - pre[u].y;
                 const float h = fsqrt(dx * dx + dy * dy);
-                if (kInside || i < kFtP) sP[kpl + 72 * u] = pre[u];
-                if (kInside || i < kFtP - 1) sH[kpl + 72 * u] = h;
+                if (kInside || i < kFtP) sP[kpl + kp(64 * u)] = pre[u];
+                if (kInside || i < kFtP - 1) sH[kpl + kp(64 * u)] = h;
                 if constexpr (kSpline) {
                     const float ih = frcp(h);
                     const cf d = {dx * ih, dy * ih};
                     const cf dr = wave_ror1(d);
                     const cf dm = lane == 0 ? dmprev : dr;
                     if ((u > 0 || i >= 1) && (kInside || i < kFtP - 1))
-                        sR[kpl + 72 * u] = {6.0f * (d.x - dm.x), 6.0f * (d.y - dm.y)};
+                        sR[kpl + kp(64 * u)] = {6.0f * (d.x - dm.x), 6.0f * (d.y - dm.y)};
                     dmprev = dr;
                 }
             }
@@ -565,7 +567,7 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
             }
         }
         wave_lds_sync();
-        // tile-relative arc length: lane owns local knots [8 lane, 8 lane + 8)
+        // tile-relative arc length: lane owns local knots [kFtC lane, kFtC lane + kFtC)
         float loc[kFtC];
         double acc = 0.0;
 #pragma unroll
@@ -573,7 +575,7 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
             loc[k] = (float)acc;
             acc += (double)sH[kp(kFtH + kFtC * lane + k)];
         }
-        const double base = wave_incl_scan(acc, lane) - acc;   // arc length from knot a to knot a + 8 lane
+        const double base = wave_incl_scan(acc, lane) - acc;   // arc length from knot a to knot a + kFtC lane
 #pragma unroll
         for (int k = 0; k < kFtC; ++k) sS[kp(kFtC * lane + k)] = (float)(base + (double)loc[k]);
         // arc length from knot a to knot a + kt - 1 (tile end), exact in FP64
@@ -589,7 +591,7 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
         }
         wave_lds_sync();
         if (mode == CA_RESAMPLE_SPLINE) {
-            // local solve for knots [8 lane, 8 lane + 8): window kRsW each side
+            // local solve for knots [kFtC lane, kFtC (lane + 1)): window kRsW each side
             float al[kFtC];
             cf de[kFtC];
             const int i0 = kFtH + kFtC * lane;           // staged index of the chunk's first knot
@@ -638,6 +640,7 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
             const float iaL = frcp(aL);
             const float iden = frcp(beta - ae * ae * iaL);
             cf Mn = {(eps.x - ae * dL.x * iaL) * iden, (eps.y - ae * dL.y * iaL) * iden};
+            wave_lds_sync();                   // every right-hand side is read before moments overwrite them
 #pragma unroll
             for (int i = kFtC - 1; i >= 0; --i) {
                 const float cj = sH[kp(i0 + i)];
@@ -655,8 +658,8 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
         auto upar = [&](int nn) { return (float)((double)nn * uN - carry); };
         // Node nn lies on segment j = the largest j in [0, kt - 2] with
         // sS[j] <= upar(nn) (j = 0 below sS[0]).  Since upar and sS are
-        // non-decreasing, the nodes of lane l's segments [8 l, 8 l + 8) are the
-        // contiguous range [first(8 l), first(8 l + 8)), first(j) being the
+        // non-decreasing, the nodes of lane l's segments [kFtC l, kFtC (l + 1)) are the
+        // contiguous range [first(kFtC l), first(kFtC (l + 1))), first(j) being the
         // smallest node at or after sS[j]; each lane places its own range with
         // one LDS round trip per node.  Tiles with many nodes per knot fall
         // back to one node per lane and a binary search.
@@ -678,7 +681,7 @@ __global__ __launch_bounds__(64) void k_resample_fast(const cf* __restrict__ raw
         float sk[kFtC];                        // this lane's knot parameters
 #pragma unroll
         for (int k = 1; k < kFtC; ++k) {
-            const float v = sS[kp(j0 + k)];    // j0 + k <= 511: inside sS
+            const float v = sS[kp(j0 + k)];    // j0 + k <= kFtK - 1: inside sS
             sk[k] = (j0 + k <= kt - 2) ? v : 3.0e38f;
         }
         const int nbeg = seg ? ns : nlo + lane, nend = seg ? ne : nhi, nstep = seg ? 1 : 64;
