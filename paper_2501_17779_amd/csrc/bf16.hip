@@ -42,12 +42,22 @@ constexpr int kBPad = team_padn<kBN>();
 // twenty times below the bound this unit gives (1.1e-4 relative at n = 128).
 constexpr double kBf16U = 7.62939453125e-06;   // 2^-17
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two values at a time: one packed conversion per BF16 pair, the hi parts
+// widened back exactly, the remainders converted as one more pair.
 __device__ __forceinline__ void split8(const float (&v)[8], bf16x8& hi, bf16x8& lo) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const __bf16 h = (__bf16)v[e];
-        hi[e] = h;
-        lo[e] = (__bf16)(v[e] - (float)h);
+    for (int e = 0; e < 8; e += 2) {
+        const f32x2 a = {v[e], v[e + 1]};
+        const bf16x2 h = __builtin_convertvector(a, bf16x2);
+        const f32x2 r = a - __builtin_convertvector(h, f32x2);
+        const bf16x2 l = __builtin_convertvector(r, bf16x2);
+        hi[e] = h[0];
+        hi[e + 1] = h[1];
+        lo[e] = l[0];
+        lo[e + 1] = l[1];
     }
 }
 
