@@ -113,8 +113,9 @@ def test_fp64_single_pair(ca):
 
 
 def test_fp64_batch_block_sizes(ca):
-    for n in (128, 360, 1024):
-        z1, z2 = inputs.batch(900 + n, 16, n)
+    # one size per FP64 class: <= 512, <= 1024, <= 2048 (1500), <= 4096 (3000, 4096)
+    for n in (128, 360, 1024, 1500, 3000, 4096):
+        z1, z2 = inputs.batch(900 + n, 16 if n <= 1024 else 8, n)
         note(f"align_batch fp64 n={n}")
         res = ca.to_numpy(ca.align_batch(gpu(z1.astype(np.complex128)), gpu(z2.astype(np.complex128)),
                                          precision="fp64"))
