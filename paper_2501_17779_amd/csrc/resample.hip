@@ -1,9 +1,10 @@
 // Uniform arc-length resampling of closed polygons (section 2: Eq.
 // arc-length-param, then cubic-spline interpolation evaluated at the uniform
 // parameters t_n = n/N), followed by scaling to unit length and centering on
-// the node mean.  One workgroup per curve, persistent over the batch; each
-// workgroup owns a slot of global scratch for the cleaned vertex list and the
-// per-knot quantities.
+// the node mean.  Two kernels: a fast path with one wave per curve (below),
+// and a general path for the curves it rejects, one workgroup per listed
+// curve, persistent over the list, each owning a slot of global scratch for
+// the cleaned vertex list and the per-knot quantities.
 //
 // Spline: the periodic C2 cubic through (s_j, Q_j) has second derivatives
 // M_j solving the cyclic tridiagonal system
@@ -348,8 +349,9 @@ __global__ __launch_bounds__(kRsNT) void k_resample(const cf* __restrict__ raw, 
 // knot): the tile and a halo of kRsW + 1 knots on each side are staged in
 // LDS, chord lengths, right-hand sides, tile-relative arc-length parameters
 // and the local spline solves are computed there, and every output node
-// whose parameter falls in the tile is evaluated after a binary search over
-// the tile's knots.  Pass 3 centres the nodes and accumulates their norm.
+// whose parameter falls in the tile is evaluated by the lane that owns its
+// segment (a binary search over the tile's knots only for tiles with many
+// nodes per knot).  Pass 3 centres the nodes and accumulates their norm.
 constexpr int kFtC = 7;                    // knots per lane in the local solve
 constexpr int kFtK = 64 * kFtC;            // knots per tile
 constexpr int kFtH = kRsW + 1;             // halo on each side
