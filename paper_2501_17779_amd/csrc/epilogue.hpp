@@ -96,8 +96,12 @@ enum { kZPad = 0, kZTwice = 1 };
 // Epilogue of one pair held by a team: d[q] = D[t + T q] (D = n conj C),
 // a0[q] = z1[t + T q] (FP32 nodes of curve 1), zb = LDS copy of curve 2's
 // nodes in layout ZL, cand = the team's candidate list in LDS.
+// With OWN_N1 the n1 argument is ignored and n1 = (1/n) sum |z1|^2 is formed
+// here from a0: under the top-two rule in the pass that re-scores the best
+// shift, whose FP64 conversions of curve 1's nodes it shares (same terms in
+// the same order as a separate pass, so the same value).
 // Returns the finished result (every lane).
-template <int N, int T, int ZL = kZPad, bool FUSE2 = false>
+template <int N, int T, int ZL = kZPad, bool FUSE2 = false, bool OWN_N1 = false>
 __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const cf (&a0)[N / T],
                                                      const cf* zb, int* cand, int t, double n1, double n2,
                                                      int rescore, int theta64,
@@ -110,7 +114,8 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         m2[q] = norm2(d[q]);
-        b2 = fmaxf(b2, fminf(b1, m2[q]));
+        // new second largest = median of (largest, second largest, value)
+        b2 = __builtin_amdgcn_fmed3f(b1, b2, m2[q]);
         b1 = fmaxf(b1, m2[q]);
     }
     // best value, then the smallest shift holding it
@@ -135,7 +140,74 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
         return c == kNone ? ((bi + 1) & (N - 1)) : c;
     };
 
+    auto zat = [&](int c, int q) {
+        return (ZL == kZTwice) ? zb[((t - c) & (N - 1)) + T * q] : zb[lpad<N>((t + T * q - c) & (N - 1))];
+    };
+    // FP64 C at shift c (times n): sum over k of conj(z1[k]) z2[k + c]
+    auto dot64 = [&](int c, double& re, double& im) {
+        re = 0.0;
+        im = 0.0;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const cf zz = zat(c, q);
+            const double ax = a0[q].x, ay = a0[q].y, bx = zz.x, by = zz.y;
+            re = fma(ax, bx, fma(ay, by, re));
+            im = fma(ay, bx, fma(-ax, by, im));
+        }
+        re = team_sum<T>(re);
+        im = team_sum<T>(im);
+    };
+    // the path's own C at the chosen shift: arg C = atan2(-Im D, Re D)
+    auto theta_at = [&](int shift) {
+        const int qs = shift / T, ls = shift % T;
+        cf sel = d[0];
+#pragma unroll
+        for (int q = 1; q < R; ++q)
+            if (q == qs) sel = d[q];
+        sel.x = __shfl(sel.x, ls, T);
+        sel.y = __shfl(sel.y, ls, T);
+        return (double)wrap_pi(atan2f(-sel.y, sel.x));
+    };
+
     ca_result_t res;
+    if (OWN_N1 && rescore != CA_RESCORE_WINDOW) {
+        // top-two rule: the best shift is re-scored before n1 is needed, and
+        // the same pass sums |z1|^2
+        double re = 0.0, im = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const cf zz = zat(bi, q);
+            const double ax = a0[q].x, ay = a0[q].y, bx = zz.x, by = zz.y;
+            s1 = fma(ax, ax, fma(ay, ay, s1));
+            re = fma(ax, bx, fma(ay, by, re));
+            im = fma(ay, bx, fma(-ax, by, im));
+        }
+        re = team_sum<T>(re);
+        im = team_sum<T>(im);
+        n1 = team_sum<T>(s1) / N;
+        if (special_case(res, n1, n2, (double)bv)) return res;
+        const double d1 = (double)__builtin_amdgcn_sqrtf(bv), d2 = (double)__builtin_amdgcn_sqrtf(fmaxf(cv, 0.0f));
+        const double epsD = (double)((float)(kErrScale * err_u * (double)ilog2_ceil(N) * N * N) *
+                                     __builtin_amdgcn_sqrtf((float)(n1 * n2)));
+        Pick pk;
+        pk.offer(bi, re, im);
+        if (d1 - d2 < 2.0 * epsD) {
+            const int ci = runner_up();
+            dot64(ci, re, im);
+            pk.offer(ci, re, im);
+        }
+        finish(res, pk, N, n1, n2, d1, d2, epsD, false, theta_at(pk.shift), theta64);
+        return res;
+    }
+    if (OWN_N1) {
+        double s1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const double ax = a0[q].x, ay = a0[q].y;
+            s1 = fma(ax, ax, fma(ay, ay, s1));
+        }
+        n1 = team_sum<T>(s1) / N;
+    }
     if (special_case(res, n1, n2, (double)bv)) return res;
     // |D| of the best and runner-up and the error bound only steer the choice
     // of shifts to re-score and the reported gap: the hardware square root
@@ -193,13 +265,9 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
     }
     wave_lds_sync();
     Pick pk;
-    auto zat = [&](int c, int q) {
-        return (ZL == kZTwice) ? zb[((t - c) & (N - 1)) + T * q] : zb[lpad<N>((t + T * q - c) & (N - 1))];
-    };
     int k = 0;
     if (FUSE2 && cnt >= 2) {
         // the first two candidates in one pass: curve 1's nodes converted once
-        // (where the runner-up is usually re-scored: near-copies in a batch)
         const int c0 = cand[0], c1 = cand[1];
         double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
 #pragma unroll
@@ -222,29 +290,12 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
     }
     for (; k < cnt; ++k) {
         const int c = cand[k];
-        double re = 0.0, im = 0.0;
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const cf zz = zat(c, q);
-            const double ax = a0[q].x, ay = a0[q].y, bx = zz.x, by = zz.y;
-            re = fma(ax, bx, fma(ay, by, re));
-            im = fma(ay, bx, fma(-ax, by, im));
-        }
-        re = team_sum<T>(re);
-        im = team_sum<T>(im);
+        double re, im;
+        dot64(c, re, im);
         pk.offer(c, re, im);
     }
     wave_lds_sync();
-    // the path's own C at the chosen shift: arg C = atan2(-Im D, Re D)
-    const int qs = pk.shift / T, ls = pk.shift % T;
-    cf sel = d[0];
-#pragma unroll
-    for (int q = 1; q < R; ++q)
-        if (q == qs) sel = d[q];
-    sel.x = __shfl(sel.x, ls, T);
-    sel.y = __shfl(sel.y, ls, T);
-    const double thp = (double)wrap_pi(atan2f(-sel.y, sel.x));
-    finish(res, pk, N, n1, n2, d1, d2, epsD, capped, thp, theta64);
+    finish(res, pk, N, n1, n2, d1, d2, epsD, capped, theta_at(pk.shift), theta64);
     return res;
 }
 
