@@ -372,6 +372,49 @@ __global__ __launch_bounds__(256) void k_blk_bin(const int64_t* __restrict__ off
     if (cls >= 0) bins[kBlkClasses * kBinStride + cls * num_pairs + s_base[cls] + pos] = (int)pair;
 }
 
+// Largest value and runner-up of a block in one pair of barriers.  Each
+// thread brings its own largest (b1 at i1) and second largest (b2 at i2),
+// smallest index first on equal values.  Returns the block's largest (bv at
+// bi) and the largest over every other index (cv at ci), both with the
+// smallest index on equal values; scratch holds 4 * (blockDim / 64) doubles.
+template <int NT, typename V>
+__device__ __forceinline__ void block_top2(V b1, int i1, V b2, int i2, V& bv, int& bi, V& cv, int& ci,
+                                           double* scratch) {
+    // per wave: its largest, then the largest over its other indices (the
+    // lane holding the wave's largest offers its second largest)
+    V w1 = b1;
+    int j1 = i1;
+    team_argmax<64>(w1, j1);
+    V w2 = i1 == j1 ? b2 : b1;
+    int j2 = i1 == j1 ? i2 : i1;
+    team_argmax<64>(w2, j2);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        scratch[4 * w] = (double)w1;
+        scratch[4 * w + 1] = (double)j1;
+        scratch[4 * w + 2] = (double)w2;
+        scratch[4 * w + 3] = (double)j2;
+    }
+    __syncthreads();
+    // the block's largest, and which wave holds it
+    V v = (V)scratch[0];
+    int iv = (int)scratch[1], kw = 0;
+#pragma unroll
+    for (int k = 1; k < NT / 64; ++k) {
+        const V o = (V)scratch[4 * k];
+        const int oi = (int)scratch[4 * k + 1];
+        if (o > v || (o == v && oi < iv)) { v = o; iv = oi; kw = k; }
+    }
+    // runner-up: that wave's second, every other wave's first
+    V c = (V)scratch[4 * kw + 2];
+    int ic = (int)scratch[4 * kw + 3];
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k)
+        if (k != kw) argmax_combine(c, ic, (V)scratch[4 * k], (int)scratch[4 * k + 1]);
+    bv = v; bi = iv; cv = c; ci = ic;
+}
+
 template <typename T, int NT, int MMAX>
 __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1, const cpx<T>* __restrict__ z2,
                                                   const int64_t* __restrict__ offsets, int n_uniform,
@@ -384,7 +427,7 @@ __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1,
     __shared__ cpx<T> A[MMAX];
     __shared__ cpx<T> B[MMAX];
     __shared__ cpx<T> TWL[kTwLds ? MMAX : 1];
-    __shared__ double red[2 * (NT / 64)];
+    __shared__ double red[4 * (NT / 64)];
     __shared__ int clist[kCandCap + 1];
     const int64_t todo = list ? (int64_t)*list_count : num_pairs;
     for (int64_t it = blockIdx.x; it < todo; it += gridDim.x) {
@@ -431,20 +474,21 @@ __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1,
         blk_fft<NT, MMAX>(A, p, tw);
         for (int k = threadIdx.x; k < n; k += NT) B[k] = pb[k];   // z2 again, for re-scoring
 
-        T bv = T(-1);
-        int bi = 0;
+        // largest |D|^2 and runner-up in one scan: per thread the two
+        // largest (smallest shift first on equal values), then one reduction
+        T b1 = T(-1), b2 = T(-1);
+        int i1 = 0, i2 = 0;
         for (int k = threadIdx.x; k < n; k += NT) {
             const T m = norm2(A[base + k]);
-            if (m > bv) { bv = m; bi = k; }
+            if (m > b1) {
+                b2 = b1; i2 = i1; b1 = m; i1 = k;
+            } else if (m > b2) {
+                b2 = m; i2 = k;
+            }
         }
-        block_argmax<NT>(bv, bi, red);
-        T cv = T(-1);
-        int ci = 0;
-        for (int k = threadIdx.x; k < n; k += NT) {
-            const T m = norm2(A[base + k]);
-            if (k != bi && m > cv) { cv = m; ci = k; }
-        }
-        block_argmax<NT>(cv, ci, red);
+        T bv, cv;
+        int bi, ci;
+        block_top2<NT>(b1, i1, b2, i2, bv, bi, cv, ci, red);
 
         ca_result_t res;
         if (!special_case(res, n1, n2, (double)bv)) {

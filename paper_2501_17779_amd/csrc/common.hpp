@@ -174,19 +174,6 @@ template <int NT> __device__ __forceinline__ void block_sum2(double& a, double& 
     a = sa;
     b = sb;
 }
-template <int NT, typename V> __device__ __forceinline__ void block_argmax(V& v, int& i, double* scratch) {
-    team_argmax<64>(v, i);
-    const int w = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) { scratch[2 * w] = (double)v; scratch[2 * w + 1] = (double)i; }
-    __syncthreads();
-    V bv = (V)scratch[0];
-    int bi = (int)scratch[1];
-#pragma unroll
-    for (int k = 1; k < NT / 64; ++k) argmax_combine(bv, bi, (V)scratch[2 * k], (int)scratch[2 * k + 1]);
-    v = bv; i = bi;
-}
-
 __device__ __forceinline__ int ilog2_ceil(int n) {
     int l = 0;
     while ((1 << l) < n) ++l;
