@@ -36,7 +36,7 @@ def build(force: bool = False) -> str:
     """Compile align_ref.c with gcc (no fast-math) into liboracle_align.so."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c99",
                                "-Wall", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -56,8 +56,8 @@ def lib():
         L.oracle_energy.restype = ctypes.c_double
         L.oracle_sqnorm.argtypes = [dp, ctypes.c_int]
         L.oracle_sqnorm.restype = ctypes.c_double
-        L.oracle_argmax_first.argtypes = [dp, ctypes.c_int]
-        L.oracle_argmax_first.restype = ctypes.c_int
+        L.oracle_best_index.argtypes = [dp, ctypes.c_int]
+        L.oracle_best_index.restype = ctypes.c_int
         ip = ctypes.POINTER(ctypes.c_int)
         L.oracle_align_pair.argtypes = [dp, dp, ctypes.c_int, ip, dp, dp, dp, dp, dp]
         L.oracle_align_pair.restype = None

@@ -30,10 +30,14 @@
  * over a fine angle grid.
  *
  * The outer loop over every start index is the O(n^2) method described in
- * section 2 just before the convolution-theorem argument.  Ties are resolved
- * like a plain "keep the first highest" loop: the smallest m wins.
+ * section 2 just before the convolution-theorem argument.  Algorithm 2 returns
+ * the start index with the highest value and is silent on exact ties; this
+ * oracle keeps, among indices whose values are exactly equal, the one whose
+ * correlation shift s = (n - m) mod n is smallest (the library's convention
+ * for reporting the optimum as a shift).  The scan therefore visits the
+ * indices in the order m = 0, n-1, n-2, ..., 1 and keeps the first highest.
  *
- * Build: gcc -O2 -fopenmp -shared -fPIC align_ref.c -o liboracle_align.so -lm
+ * Build: gcc -O3 -fopenmp -shared -fPIC align_ref.c -o liboracle_align.so -lm
  * (no fast-math: the reference must round like the plain formulas).
  */
 #include <math.h>
@@ -120,12 +124,18 @@ double oracle_sqnorm(const double* b, int n)
     return e / (double)n;
 }
 
-/* First index of the largest value (a plain "keep the first highest" scan). */
-int oracle_argmax_first(const double* v, int n)
+/*
+ * Start index of the largest value among v[m], m = 0..n-1, visiting the
+ * indices by increasing shift s = (n - m) mod n and keeping the first highest,
+ * so that exact ties go to the smallest s.
+ */
+int oracle_best_index(const double* v, int n)
 {
     int best = 0;
-    for (int i = 1; i < n; ++i)
-        if (v[i] > v[best]) best = i;
+    for (int s = 1; s < n; ++s) {
+        int m = n - s;
+        if (v[m] > v[best]) best = m;
+    }
     return best;
 }
 
@@ -141,7 +151,7 @@ void oracle_align_pair(const double* b1, const double* b2, int n,
     double* Tloc = T ? T : (double*)malloc(sizeof(double) * (size_t)n);
     double* Hloc = theta ? theta : (double*)malloc(sizeof(double) * (size_t)n);
     oracle_shift_scores(b1, b2, n, Tloc, Hloc);
-    int m = oracle_argmax_first(Tloc, n);
+    int m = oracle_best_index(Tloc, n);
     *m_best = m;
     *theta_best = Hloc[m];
     *t_best = Tloc[m];

@@ -243,6 +243,117 @@ def test_k_fold_symmetry_gives_k_ties():
     assert rest.max() < T[0] * (1 - 1e-4)
 
 
+def symmetric_curve(n, fold, a=0.3):
+    """Nodes of r(t) = 1 + a cos(fold t), t = 2 pi l / n, with the fold-fold
+    symmetry exact in floating point: the first n/fold nodes are computed and
+    the others are copies turned by a quarter turn (fold 4, (x, y) -> (-y, x))
+    or a half turn (fold 2, (x, y) -> (-x, -y)), both exact."""
+    assert fold in (2, 4) and n % fold == 0
+    q = n // fold
+    t = 2 * np.pi * np.arange(q) / n
+    r = 1.0 + a * np.cos(fold * t)
+    x, y = r * np.cos(t), r * np.sin(t)
+    xs, ys = [x], [y]
+    for _ in range(fold - 1):
+        if fold == 4:
+            x, y = -y, x
+        else:
+            x, y = -x, -y
+        xs.append(x)
+        ys.append(y)
+    z = np.empty(n, dtype=np.complex128)
+    z.real = np.concatenate(xs)
+    z.imag = np.concatenate(ys)
+    return z
+
+
+@pytest.mark.parametrize("n,fold,m0", [(64, 4, 11), (96, 4, 70), (50, 2, 7), (62, 2, 40)])
+def test_exact_ties_go_to_the_smallest_shift(n, fold, m0):
+    """Algorithm 2 keeps the highest value and is silent on exact ties; the
+    oracle reports the tied start index whose shift s = (n - m) mod n is
+    smallest.  A curve with exact fold-fold symmetry read from start index m0
+    ties exactly (bit for bit) at m = -m0 + j n / fold, j = 0..fold-1: a turn
+    by 2 pi / fold negates or swaps the sums of Eq. A-mtx term by term.  The
+    expected index is worked out here by hand from that set; keeping the
+    smallest m, or the last of the scan, picks another member."""
+    z1 = symmetric_curve(n, fold)
+    z2 = np.roll(z1, -m0)                      # z2[l] = z1[(l + m0) mod n]
+    T, _ = oracle.shift_scores(z1, z2)
+    ties = sorted(((-m0 + j * n // fold) % n) for j in range(fold))
+    assert np.ptp(T[ties]) == 0.0              # exact ties
+    assert np.delete(T, ties).max() < T[ties[0]] * (1 - 1e-6)
+    shifts = [(n - m) % n for m in ties]
+    expect_m = ties[int(np.argmin(shifts))]
+    assert expect_m != min(ties)               # the two tie rules differ here
+    res = oracle.align_pair(z1, z2)
+    assert res["m"] == expect_m
+    # at tie member m the copy is curve 1 turned by k turns of 2 pi / fold,
+    # k = ((m + m0) mod n) / (n / fold), counter-clockwise; R(theta) of
+    # section 2 turns it back clockwise by theta = 2 pi k / fold, and the
+    # energy vanishes
+    k = ((expect_m + m0) % n) // (n // fold)
+    assert abs(oracle.wrap_angle(res["theta_paper"] - 2 * np.pi * k / fold)) < 1e-12
+    assert res["E"] < 1e-28
+    # the batch entry point applies the same rule
+    m, _, _, _, _ = oracle.align_batch_f32(z1[None].astype(np.complex64), z2[None].astype(np.complex64))
+    T32, _ = oracle.shift_scores(z1.astype(np.complex64), z2.astype(np.complex64))
+    assert np.ptp(T32[ties]) == 0.0
+    assert m[0] == expect_m
+    # initializer hand-off: t0 = m / n with the same m
+    t0, R, _ = oracle.initializer(z1, z2)
+    assert t0 == expect_m / n
+    assert np.allclose(R, R_paper(2 * np.pi * k / fold), atol=1e-12)
+
+
+@pytest.mark.parametrize("n", [60, 64, 97])
+def test_circle_through_align_pair(n):
+    """A circle aligned to a turned, restarted copy of itself: every start
+    index is optimal up to rounding (T constant, E = 0), and the angle at the
+    returned index is the one that undoes the turn and the restart: the node
+    at start index m sits 2 pi m / n further along the circle."""
+    alpha, m0 = 0.9, 5
+    l = np.arange(n)
+    z1 = np.exp(2j * np.pi * l / n)
+    z2 = np.exp(1j * alpha) * np.exp(2j * np.pi * ((l + m0) % n) / n)
+    res = oracle.align_pair(z1, z2)
+    T = res["T_all"]
+    assert np.ptp(T) <= 1e-13 * T.max()
+    m = res["m"]
+    # R(theta) beta2(l + m) = beta1(l): clockwise by alpha + 2 pi (m + m0) / n
+    expect = oracle.wrap_angle(alpha + 2 * np.pi * (m + m0) / n)
+    assert abs(oracle.wrap_angle(res["theta_paper"] - expect)) < 1e-12
+    assert res["E"] < 1e-26
+
+
+@pytest.mark.parametrize("n", [60, 300, 301])
+def test_three_fold_curve_through_align_pair(n):
+    """r = 1 + 0.3 cos 3t against a restarted copy: three start indices tie
+    mathematically (exactly when 3 | n, up to rounding of the node values
+    otherwise the copy is only near them).  With 3 | n the returned index is
+    one of the three, its energy vanishes and its angle is a multiple of
+    2 pi / 3."""
+    m0 = 17
+    l = np.arange(n)
+    t = 2 * np.pi * l / n
+    z1 = (1 + 0.3 * np.cos(3 * t)) * np.exp(1j * t)
+    z2 = np.roll(z1, -m0)
+    res = oracle.align_pair(z1, z2)
+    T = res["T_all"]
+    top = np.argsort(-T)[:3]
+    if n % 3 == 0:
+        ties = sorted(((-m0 + j * n // 3) % n) for j in range(3))
+        assert sorted(top) == ties
+        assert res["m"] in ties
+        assert np.ptp(T[ties]) <= 1e-13 * T.max()
+        k = ((res["m"] + m0) % n) // (n // 3)
+        assert abs(oracle.wrap_angle(res["theta_paper"] - 2 * np.pi * k / 3)) < 1e-12
+        assert res["E"] < 1e-26
+    else:
+        # without 3 | n only the restart index itself matches exactly
+        assert res["m"] == (-m0) % n
+        assert res["E"] < 1e-26
+
+
 def test_batch_matches_pairs():
     rng = np.random.default_rng(5)
     B, n = 6, 40
