@@ -403,7 +403,7 @@ def bench_small_batch(args, torch, ca):
 
 
 def bench_srv(args, torch, ca):
-    """The (t0, R) step of the elastic solver on SRV functions (section 4) at
+    """The (t0, R) step of the elastic solver on SRV functions (section 3) at
     the batch workload's size: SRV transform of both curves of 65,536 pairs
     (n = 1024), then the alignment of (q2, q1), every step."""
     from synth import curves

@@ -97,6 +97,7 @@ enum { CA_PREC_FP32 = 0, CA_PREC_SPLIT_BF16 = 1, CA_PREC_FP64 = 2 };
 enum { CA_RESCORE_TOP2 = 0, CA_RESCORE_WINDOW = 1 };
 
 enum { CA_RESAMPLE_SPLINE = 0, CA_RESAMPLE_LINEAR = 1 };
+#define CA_RESAMPLE_MAX_RAW 32768   /* raw vertices per curve, resample_arclength */
 
 typedef struct {
     int32_t precision;   /* CA_PREC_*                                         */
@@ -108,8 +109,17 @@ typedef struct {
 typedef struct ca_context* ca_context_t;
 
 /* Create a context on HIP device `device` (must be gfx950).  The context owns
- * twiddle tables, DFT matrices and workspace, all released by ca_destroy. */
-ca_status_t ca_create(ca_context_t* ctx, int device);
+ * twiddle tables, DFT matrices and workspace, all released by ca_destroy.
+ * tune_cache_path (host string, may be NULL): a launch-tuning file written by
+ * ca_tune_save (format under ca_tune_save below), loaded as by ca_tune_load;
+ * NULL leaves the default launch choices.  A file that cannot be read or
+ * parsed fails the call with CA_ERR_INVALID_ARG (no context is created); a
+ * file written for another architecture or CU count installs nothing.
+ * Workspace that a call needs beyond what the context holds is allocated in
+ * that call (never under stream capture: size it with an eager call of the
+ * largest batch first); a buffer the context outgrows is kept until
+ * ca_destroy, so a HIP graph captured earlier stays valid. */
+ca_status_t ca_create(ca_context_t* ctx, int device, const char* tune_cache_path);
 ca_status_t ca_destroy(ca_context_t ctx);
 const char* ca_status_string(ca_status_t status);
 /* Text of the last error raised on this thread (empty if none). */
@@ -156,9 +166,14 @@ ca_status_t align_batch(ca_context_t ctx, const void* z1, const void* z2,
                         ca_result_t* out, const ca_options_t* opt, void* stream);
 
 /*
- * align_all_pairs -- every unordered pair (i, j), i < j, of a gallery of m
- * curves with n nodes each (complex64, curve-contiguous [m][n]).  Per-curve
- * spectra and norms are computed once.  Results are packed in row-major
+ * align_all_pairs -- Algorithm 2 of section 2 for every unordered pair (i, j),
+ * i < j, of a gallery of m curves with n nodes each (complex64,
+ * curve-contiguous [m][n]): the distance-matrix use of the rigid alignment
+ * that section 3 builds on (a matrix of pairwise shape distances).  The
+ * correlation of each pair is the inverse transform of the product of the two
+ * curves' spectra (the convolution-theorem argument of section 2), so
+ * per-curve spectra and norms are computed once and only the product, one
+ * transform and the epilogue run per pair.  Results are packed in row-major
  * upper-triangle order: pair (i, j) is at k = i*m - i*(i+1)/2 + (j - i - 1),
  * m*(m-1)/2 results in total.  FP32 precision only; n must be a power of
  * two in [64, 1024], else CA_ERR_UNSUPPORTED_N.
@@ -187,9 +202,9 @@ ca_status_t align_all_pairs(ca_context_t ctx, const void* curves, int32_t m, int
  *                 arc-length knots) or CA_RESAMPLE_LINEAR
  * Input rules: vertices are counter-clockwise and not closed; trailing copies
  * of the first vertex and runs of consecutive duplicates are dropped.
- * Raw curves may have at most 65536 vertices (CA_ERR_INVALID_ARG is not
- * detectable on the host for device offsets: longer curves get
- * CA_FLAG_UNSUPPORTED_N and zero nodes).
+ * Raw curves may have at most CA_RESAMPLE_MAX_RAW = 32768 vertices before
+ * cleaning (the offsets live on the device, so this cannot be checked on the
+ * host: a longer curve gets CA_FLAG_UNSUPPORTED_N and zero nodes).
  */
 ca_status_t resample_arclength(ca_context_t ctx, const void* raw, const int64_t* raw_offsets,
                                int64_t num_curves, const int64_t* out_offsets, void* out,
@@ -197,7 +212,7 @@ ca_status_t resample_arclength(ca_context_t ctx, const void* raw, const int64_t*
                                void* stream);
 
 /*
- * to_initializer -- hand-off to an elastic shape-distance solver (section 4:
+ * to_initializer -- hand-off to an elastic shape-distance solver (section 3:
  * the iterative solver is started from the rigid optimum (t0*, R*) with
  * gamma(t) = t).  Converts alignment records into the paper's notation.
  *   results : count records written by align_pair / align_batch /
@@ -218,7 +233,7 @@ ca_status_t to_initializer(ca_context_t ctx, const ca_result_t* results, int32_t
                            void* stream);
 
 /*
- * srv_transform -- square-root-velocity function of section 4,
+ * srv_transform -- square-root-velocity function of section 3,
  * q = beta' / |beta'|^(1/2), for curves given as n nodes at the uniform
  * parameters t_k = k / n.  The curve is read as the closed polygon through
  * its nodes, so q is piecewise constant on the segments:

@@ -173,7 +173,7 @@ def R_paper(theta_paper: float) -> np.ndarray:
 
 
 def initializer(z1, z2):
-    """The rigid optimum handed to an elastic solver (section 4): the start
+    """The rigid optimum handed to an elastic solver (section 3): the start
     parameter t0 = m / n at which curve 2 is read and R(theta_paper), the
     slow method's minimiser of Eq. disc-energy.  Returns (t0, R, align_pair dict)."""
     res = align_pair(z1, z2)

@@ -1,9 +1,9 @@
-"""FP64 reference for the square-root-velocity (SRV) step of section 4.
+"""FP64 reference for the square-root-velocity (SRV) step of section 3.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring): the GPU SRV transform
 is checked against this module; the library never imports it.
 
-Section 4 represents a closed curve beta of unit length by its SRV function
+Section 3 represents a closed curve beta of unit length by its SRV function
 q = beta' / |beta'|^(1/2) and proposes to run the rigid alignment of section
 2 on SRV functions inside the elastic solver: with gamma fixed, (t0, R)
 minimise Eq. (dist2-energy), the integral of |R q1(t + t0) - q2*(t)|^2 with

@@ -45,6 +45,7 @@ PRECISION = {"fp32": 0, "split_bf16": 1, "fp64": 2}
 RESCORE = {"top2": 0, "window": 1}
 RESAMPLE = {"spline": 0, "linear": 1}
 MAX_N = 4096
+RESAMPLE_MAX_RAW = 32768   # raw vertices per curve accepted by resample_arclength
 
 EXPORTED = ("ca_create", "ca_destroy", "ca_status_string", "ca_last_error", "ca_n_supported",
             "align_pair", "align_batch", "align_all_pairs", "resample_arclength", "to_initializer",
@@ -84,7 +85,7 @@ def lib():
                                   "`python -c 'import __graft_entry__ as g; g.build()'`")
             L = ctypes.CDLL(LIB_PATH)
             vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
-            L.ca_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+            L.ca_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_char_p]
             L.ca_destroy.argtypes = [vp]
             L.ca_status_string.argtypes = [i32]
             L.ca_status_string.restype = ctypes.c_char_p
@@ -126,10 +127,11 @@ def n_supported(n: int) -> bool:
 class Context:
     """Owns the library context (plans, twiddle tables, workspace) on one device."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, tune_file: str | None = None):
         self.device = int(device)
         h = ctypes.c_void_p()
-        _check(lib().ca_create(ctypes.byref(h), self.device))
+        path = None if tune_file is None else os.fsencode(tune_file)
+        _check(lib().ca_create(ctypes.byref(h), self.device, path))
         self.handle = h
 
     def close(self):
@@ -341,7 +343,7 @@ def to_initializer(results, n=None, offsets=None, *, stream=None, ctx=None):
 
 
 def srv_transform(curves, offsets=None, *, out=None, stream=None, ctx=None):
-    """Square-root-velocity values q_k of closed polygons (section 4).
+    """Square-root-velocity values q_k of closed polygons (section 3).
 
     Uniform: curves complex64 [count, n].  Ragged: curves flat complex64 with
     int64 `offsets` [count+1].  Returns q with the layout of `curves`."""

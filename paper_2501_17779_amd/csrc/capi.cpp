@@ -343,6 +343,19 @@ ca_status_t ensure_bf16_tables(ca_context* c) {
     return CA_OK;
 }
 
+// Grows a context-owned workspace buffer to at least `need` bytes.  The
+// outgrown buffer is retired, not freed: a HIP graph captured earlier may
+// still hold its address, so it stays allocated until ca_destroy.
+ca_status_t grow(ca_context* c, void** p, size_t* cap, size_t need, const char* what) {
+    if (need <= *cap && *p) return CA_OK;
+    void* q = nullptr;
+    if (hipMalloc(&q, need) != hipSuccess) return fail(CA_ERR_OOM, std::string(what) + " allocation failed");
+    if (*p) c->retired.push_back(*p);
+    *p = q;
+    *cap = need;
+    return CA_OK;
+}
+
 const void* team_tw_for(ca_context* c, int n) {
     int lg = 0;
     while ((1 << lg) < n) ++lg;
@@ -386,7 +399,7 @@ int32_t ca_n_supported(int32_t n) {
     return (n >= 2 && n <= CA_MAX_N) ? 2 : 0;
 }
 
-ca_status_t ca_create(ca_context_t* ctx, int device) {
+ca_status_t ca_create(ca_context_t* ctx, int device, const char* tune_cache_path) {
     if (!ctx) return fail(CA_ERR_INVALID_ARG, "ctx is NULL");
     *ctx = nullptr;
     int count = 0;
@@ -407,8 +420,11 @@ ca_status_t ca_create(ca_context_t* ctx, int device) {
     if (colon != std::string::npos) c->arch.resize(colon);
     DeviceGuard g(device);
     ca_status_t st = ensure_tables(c, false);
+    if (st == CA_OK && tune_cache_path) st = ca_tune_load(c, tune_cache_path, nullptr);
     if (st != CA_OK) {
+        const std::string msg = g_err;
         ca_destroy(c);
+        g_err = msg;
         return st;
     }
     *ctx = c;
@@ -431,6 +447,7 @@ ca_status_t ca_destroy(ca_context_t c) {
         if (c->d_bins) (void)hipFree(c->d_bins);
         if (c->d_spec) (void)hipFree(c->d_spec);
         if (c->d_norms) (void)hipFree(c->d_norms);
+        for (void* p : c->retired) (void)hipFree(p);
     }
     delete c;
     return CA_OK;
@@ -487,14 +504,9 @@ ca_status_t align_batch(ca_context_t c, const void* z1, const void* z2, const in
         }
         a.bins = nullptr;
         if (offsets) {
-            if (num_pairs > c->bins_cap) {
-                if (c->d_bins) (void)hipFree(c->d_bins);
-                c->d_bins = nullptr;
-                c->bins_cap = 0;
-                if (hipMalloc(&c->d_bins, (size_t)ca::blk_bin_ints(num_pairs) * sizeof(int)) != hipSuccess)
-                    return fail(CA_ERR_OOM, "size-class lists");
-                c->bins_cap = num_pairs;
-            }
+            st = grow(c, (void**)&c->d_bins, &c->bins_bytes, (size_t)ca::blk_bin_ints(num_pairs) * sizeof(int),
+                      "size-class lists");
+            if (st != CA_OK) return st;
             a.bins = c->d_bins;
         }
         if (o.precision == CA_PREC_FP64) {
@@ -537,22 +549,10 @@ ca_status_t align_all_pairs(ca_context_t c, const void* curves, int32_t m, int32
     if (st != CA_OK) return st;
     hipError_t e;
     if (ca::allpairs_supported(n)) {
-        const size_t need = (size_t)m * n * 2 * sizeof(float);
-        if (need > c->spec_bytes) {
-            if (c->d_spec) (void)hipFree(c->d_spec);
-            c->d_spec = nullptr;
-            c->spec_bytes = 0;
-            if (hipMalloc(&c->d_spec, need) != hipSuccess) return fail(CA_ERR_OOM, "spectra workspace");
-            c->spec_bytes = need;
-        }
-        if ((size_t)m > c->norms_count) {
-            if (c->d_norms) (void)hipFree(c->d_norms);
-            c->d_norms = nullptr;
-            c->norms_count = 0;
-            if (hipMalloc(&c->d_norms, (size_t)m * sizeof(double)) != hipSuccess)
-                return fail(CA_ERR_OOM, "norms workspace");
-            c->norms_count = m;
-        }
+        st = grow(c, &c->d_spec, &c->spec_bytes, (size_t)m * n * 2 * sizeof(float), "spectra workspace");
+        if (st != CA_OK) return st;
+        st = grow(c, (void**)&c->d_norms, &c->norms_bytes, (size_t)m * sizeof(double), "norms workspace");
+        if (st != CA_OK) return st;
         e = ca::launch_spectra(curves, m, n, c->d_spec, c->d_norms, team_tw_for(c, n), s);
         if (e != hipSuccess) return hip_fail(e, "spectra kernel launch");
         e = ca::launch_allpairs(curves, c->d_spec, c->d_norms, m, n, out_upper, team_tw_for(c, n),
@@ -582,14 +582,9 @@ ca_status_t resample_arclength(ca_context_t c, const void* raw, const int64_t* r
             return fail(CA_ERR_OOM, "resampler scratch");
         c->rs_slots = slots;
     }
-    if (num_curves + 1 > c->slow_cap) {
-        if (c->d_slow) (void)hipFree(c->d_slow);
-        c->d_slow = nullptr;
-        c->slow_cap = 0;
-        if (hipMalloc(&c->d_slow, (size_t)(num_curves + 1) * sizeof(int)) != hipSuccess)
-            return fail(CA_ERR_OOM, "resampler curve list");
-        c->slow_cap = num_curves + 1;
-    }
+    ca_status_t st = grow(c, (void**)&c->d_slow, &c->slow_bytes, (size_t)(num_curves + 1) * sizeof(int),
+                          "resampler curve list");
+    if (st != CA_OK) return st;
     hipError_t e = ca::launch_resample(raw, raw_offsets, num_curves, out_offsets, out, norms_out,
                                        flags_out, mode, c->d_rs, ca::resample_slot_bytes(),
                                        c->rs_slots, c->d_slow, c->d_slow + 1, (hipStream_t)stream);

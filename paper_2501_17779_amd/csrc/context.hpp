@@ -54,15 +54,18 @@ struct ca_context {
     void* d_rs = nullptr;
     int64_t rs_slots = 0;
     int* d_slow = nullptr;          // [0] = count, [1..] = curve indices
-    int64_t slow_cap = 0;
+    size_t slow_bytes = 0;
     // block-engine size-class lists of ragged batches
     int* d_bins = nullptr;
-    int64_t bins_cap = 0;           // pairs
+    size_t bins_bytes = 0;
     // all-pairs spectra workspace
     void* d_spec = nullptr;
     size_t spec_bytes = 0;
     double* d_norms = nullptr;
-    size_t norms_count = 0;
+    size_t norms_bytes = 0;
+    // workspace buffers the context has outgrown: kept until ca_destroy,
+    // since graphs captured before the growth still address them
+    std::vector<void*> retired;
     ca::host::Tuning tune;
 };
 

@@ -1,4 +1,4 @@
-// Hand-off to an elastic shape-distance solver (section 4): the rigid optimum
+// Hand-off to an elastic shape-distance solver (section 3): the rigid optimum
 // in the paper's notation, t0* and R(theta_p) of section 2.
 #include "common.hpp"
 #include "launch.hpp"

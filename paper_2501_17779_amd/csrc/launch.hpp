@@ -78,7 +78,7 @@ bool allpairs_supported(int n);
 hipError_t launch_initializer(const ca_result_t* res, int n, const int64_t* offsets, int64_t count,
                               double* t0, double* rot, hipStream_t s);
 
-// Square-root-velocity transform (section 4), one wave per curve.
+// Square-root-velocity transform (section 3), one wave per curve.
 hipError_t launch_srv(const void* z, const int64_t* offsets, int n, int64_t count, void* q, int num_cus,
                       hipStream_t s);
 

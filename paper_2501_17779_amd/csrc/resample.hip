@@ -29,7 +29,7 @@ namespace ca {
 constexpr int kRsNT = 256;
 constexpr int kRsW = 12;
 constexpr int kRsC = 16;
-constexpr int kRsMCap = 32768;   // raw vertices per curve
+constexpr int kRsMCap = CA_RESAMPLE_MAX_RAW;   // raw vertices per curve
 
 struct RsSlot {
     cf* Q;        // cleaned vertices            [cap]

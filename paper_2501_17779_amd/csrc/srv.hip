@@ -1,4 +1,4 @@
-// Square-root-velocity transform of section 4: q = beta' / |beta'|^(1/2) for
+// Square-root-velocity transform of section 3: q = beta' / |beta'|^(1/2) for
 // the closed polygon through n nodes at t_k = k / n, piecewise constant on
 // the segments: beta'_k = n (z[k+1] - z[k]), q_k = beta'_k |beta'_k|^(-1/2).
 #include "common.hpp"

@@ -72,9 +72,10 @@ int main(void) {
            (unsigned)CA_FLAG_RESCORED, (unsigned)CA_FLAG_CAND_CAPPED, (unsigned)CA_FLAG_DEGENERATE,
            (unsigned)CA_FLAG_NONFINITE, (unsigned)CA_FLAG_THETA_FP64, (unsigned)CA_FLAG_UNSUPPORTED_N,
            (unsigned)CA_FLAG_CLOCKWISE);
-    printf("\"prec\": [%d, %d, %d], \"rescore\": [%d, %d], \"resample\": [%d, %d], \"max_n\": %d}\n",
+    printf("\"prec\": [%d, %d, %d], \"rescore\": [%d, %d], \"resample\": [%d, %d], \"max_n\": %d,\n",
            CA_PREC_FP32, CA_PREC_SPLIT_BF16, CA_PREC_FP64, CA_RESCORE_TOP2, CA_RESCORE_WINDOW,
            CA_RESAMPLE_SPLINE, CA_RESAMPLE_LINEAR, CA_MAX_N);
+    printf("\"max_raw\": %d}\n", CA_RESAMPLE_MAX_RAW);
     return 0;
 }
 """
@@ -100,6 +101,27 @@ def test_header_layout_matches_binding(tmp_path):
     assert h["rescore"] == [ca.RESCORE[k] for k in ("top2", "window")]
     assert h["resample"] == [ca.RESAMPLE[k] for k in ("spline", "linear")]
     assert h["max_n"] == ca.MAX_N
+    assert h["max_raw"] == ca.RESAMPLE_MAX_RAW == 32768
+
+
+# entry points that compute a step of the paper's method (the others create
+# and destroy contexts, report status or tune launches)
+COMPUTE_ENTRY_POINTS = ("align_pair", "align_batch", "align_all_pairs", "resample_arclength",
+                        "to_initializer", "srv_transform")
+
+
+def test_every_compute_declaration_cites_the_paper():
+    """The comment block in front of each compute entry point names the
+    passage that defines its operation: a section of the paper (sections 1-3;
+    section 4 is the conclusions), an algorithm or an equation."""
+    text = open(HEADER).read()
+    for name in COMPUTE_ENTRY_POINTS:
+        m = re.search(r"/\*((?:(?!\*/).)*)\*/\s*ca_status_t\s+" + name + r"\s*\(", text, flags=re.S)
+        assert m, f"no comment block in front of {name}"
+        block = m.group(1)
+        assert re.search(r"section [123]\b|Algorithm [12]\b|Eq\. ?\(?[a-z0-9-]+", block), name
+        assert not re.search(r"section [4-9]", block), name
+    assert not re.search(r"section [4-9]", text)
 
 
 def _expected_support(n):
@@ -142,7 +164,7 @@ def test_null_context_is_rejected_on_host(L):
     assert L.resample_arclength(None, dummy, dummy, 4, dummy, dummy, None, None, 0, None) == ca.ERR_INVALID_ARG
     assert L.to_initializer(None, dummy, 64, None, 4, dummy, dummy, None) == ca.ERR_INVALID_ARG
     assert L.srv_transform(None, dummy, None, 64, 4, dummy, None) == ca.ERR_INVALID_ARG
-    assert L.ca_create(None, 0) == ca.ERR_INVALID_ARG
+    assert L.ca_create(None, 0, None) == ca.ERR_INVALID_ARG
     assert L.ca_destroy(None) == ca.OK
 
 
@@ -151,7 +173,7 @@ def test_create_without_gpu_reports_no_device(L):
     if torch.cuda.device_count() > 0:
         pytest.skip("a GPU is visible; covered by the GPU tests")
     h = ctypes.c_void_p()
-    assert L.ca_create(ctypes.byref(h), 0) == ca.ERR_NO_DEVICE
+    assert L.ca_create(ctypes.byref(h), 0, None) == ca.ERR_NO_DEVICE
     assert h.value is None
     assert _last(L)
     with pytest.raises(ca.CurveAlignError) as ei:

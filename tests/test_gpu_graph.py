@@ -114,3 +114,58 @@ def test_graph_resample(ca):
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(out, eager)
+
+
+@pytest.mark.parametrize("kind", ["ragged", "allpairs", "resample"])
+def test_graph_survives_workspace_growth(ca, kind):
+    """A graph captured on a fresh context, then a larger eager call that
+    outgrows the context's workspace (size-class lists, spectra and norms,
+    resampler curve list), then replays: the replays still match the eager
+    result of the captured call, because the outgrown buffers are kept until
+    the context is destroyed."""
+    print(f"[gpu] graph after workspace growth {kind}", flush=True)
+    ctx = ca.Context(0)
+    if kind == "ragged":
+        small, big = inputs.ragged(21, 10), inputs.ragged(22, 300)
+        z1, z2, off = (torch.from_numpy(small[k]).cuda() for k in ("z1", "z2", "off"))
+        out = ca.empty_results(10, "cuda")
+        fn = lambda: ca.align_batch(z1, z2, offsets=off, out=out, ctx=ctx)  # noqa: E731
+        b1, b2, boff = (torch.from_numpy(big[k]).cuda() for k in ("z1", "z2", "off"))
+        grow = lambda: ca.align_batch(b1, b2, offsets=boff, ctx=ctx)  # noqa: E731
+    elif kind == "allpairs":
+        g_small = torch.from_numpy(inputs.gallery(23, 20, 256)).cuda()
+        g_big = torch.from_numpy(inputs.gallery(24, 90, 256)).cuda()
+        out = ca.empty_results(20 * 19 // 2, "cuda")
+        fn = lambda: ca.align_all_pairs(g_small, out=out, ctx=ctx)  # noqa: E731
+        grow = lambda: ca.align_all_pairs(g_big, ctx=ctx)  # noqa: E731
+    else:
+        from synth import curves
+        d = curves.ragged_pairs(25, 8)
+        raw = torch.view_as_complex(torch.from_numpy(d["raw1"]).cuda()).contiguous()
+        roff = torch.from_numpy(d["off1"]).cuda()
+        n = torch.from_numpy(d["n"].astype(np.int64)).cuda()
+        ooff = torch.zeros(9, dtype=torch.int64, device="cuda")
+        ooff[1:] = torch.cumsum(n, 0)
+        out = torch.empty(int(ooff[-1].item()), dtype=torch.complex64, device="cuda")
+        fn = lambda: ca.resample_arclength(raw, roff, ooff, out=out, ctx=ctx)  # noqa: E731
+        d2 = curves.ragged_pairs(26, 400)
+        raw2 = torch.view_as_complex(torch.from_numpy(d2["raw1"]).cuda()).contiguous()
+        roff2 = torch.from_numpy(d2["off1"]).cuda()
+        n2 = torch.from_numpy(d2["n"].astype(np.int64)).cuda()
+        ooff2 = torch.zeros(401, dtype=torch.int64, device="cuda")
+        ooff2[1:] = torch.cumsum(n2, 0)
+        grow = lambda: ca.resample_arclength(raw2, roff2, ooff2, ctx=ctx)  # noqa: E731
+    fn()
+    torch.cuda.synchronize()
+    eager = out.clone()
+    g = capture(fn)
+    grow()
+    torch.cuda.synchronize()
+    for r in range(3):
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), f"replay {r} after growth differs"
+    del g
+    torch.cuda.synchronize()
+    ctx.close()

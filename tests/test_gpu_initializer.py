@@ -1,4 +1,4 @@
-"""GPU parity of to_initializer (the elastic-solver hand-off of section 4)
+"""GPU parity of to_initializer (the elastic-solver hand-off of section 3)
 against the FP64 oracle's (t0, R(theta)) in the paper's notation."""
 import numpy as np
 import pytest

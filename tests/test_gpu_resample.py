@@ -162,3 +162,34 @@ def test_dense_tiles_and_mixed_node_placement(ca):
             note(f"dense/mixed curve {c} {mode}: node error {err:.3g}")
             assert err <= TOL_POS
             assert flags[c] == (ca.FLAG_CLOCKWISE if info["area"] < 0 else 0)
+
+
+@pytest.mark.parametrize("mode", ["spline", "linear"])
+def test_vertex_cap(ca, mode):
+    """Raw curves of exactly CA_RESAMPLE_MAX_RAW vertices are resampled (the
+    wave-per-curve kernel, and the general kernel when a duplicate vertex has
+    to be dropped); one vertex more gives CA_FLAG_UNSUPPORTED_N and zero
+    nodes."""
+    cap = ca.RESAMPLE_MAX_RAW
+    rng = np.random.default_rng(cap)
+    n = 1000
+
+    def ellipse(m):
+        t = np.sort(rng.uniform(0, 2 * np.pi, m))
+        return np.stack([1.3 * np.cos(t), 0.7 * np.sin(t)], -1).astype(np.float32)
+
+    full = ellipse(cap)
+    dup = full.copy()
+    dup[500] = dup[499]                    # a consecutive duplicate, dropped by cleaning
+    over = ellipse(cap + 1)
+    polys = [full, dup, over]
+    out, ooff, norms, flags = run(ca, polys, [n, n, n], mode)
+    m = rr.SPLINE if mode == "spline" else rr.LINEAR
+    for c in (0, 1):
+        assert flags[c] & ca.FLAG_UNSUPPORTED_N == 0
+        ref, _ = rr.resample(polys[c].astype(np.float64), n, m)
+        err = np.abs(out[ooff[c]:ooff[c + 1]] - ref).max()
+        note(f"cap {mode} curve {c}: max |dz| {err:.3g}")
+        assert err <= TOL_POS
+    assert flags[2] & ca.FLAG_UNSUPPORTED_N
+    assert np.all(out[ooff[2]:ooff[3]] == 0)

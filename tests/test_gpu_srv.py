@@ -1,4 +1,4 @@
-"""GPU parity of the SRV step of section 4 against the FP64 oracle.
+"""GPU parity of the SRV step of section 3 against the FP64 oracle.
 
 Stage 1: srv_transform (FP32) against oracle.srv_ref.srv on the same FP32
 nodes.  Stage 2: the (t0, R) step of Eq. (dist2-energy), align_batch on

@@ -283,3 +283,38 @@ def test_corrupt_cache_falls_back_to_defaults(ca, tmp_path, monkeypatch):
             v.close()
         ca._contexts.clear()
         ca._contexts.update(saved)
+
+
+def test_create_with_tune_cache_path(ca, tmp_path):
+    """ca_create loads a tuning file given by path (the C caller's route to the
+    tuned launches); a broken file fails the call and creates no context; NULL
+    keeps the defaults."""
+    src = ca.Context(0)
+    try:
+        ca.tune_set("team_grid", 256, 4, ctx=src)
+        ca.tune_set("block_plan", 2048, [4, 8, 8, 8], ctx=src)
+        path = str(tmp_path / "tune.json")
+        ca.tune_save(path, ctx=src)
+    finally:
+        src.close()
+    loaded = ca.Context(0, tune_file=path)
+    plain = ca.Context(0)
+    try:
+        assert ca.tune_get("team_grid", 256, ctx=loaded) == [4]
+        assert ca.tune_get("block_plan", 2048, ctx=loaded) == [4, 8, 8, 8]
+        assert ca.tune_get("team_grid", 256, ctx=plain) == [1]
+        broken = tmp_path / "broken.json"
+        broken.write_text(open(path).read().replace('"values": [4]', '"values": [-3]'))
+        with pytest.raises(ca.CurveAlignError) as e:
+            ca.Context(0, tune_file=str(broken))
+        assert e.value.status == ca.ERR_INVALID_ARG
+        with pytest.raises(ca.CurveAlignError):
+            ca.Context(0, tune_file=str(tmp_path / "missing.json"))
+        # the loaded radix schedule gives results within the acceptance rule
+        z1, z2 = inputs.batch(731, 24, 2048)
+        res = ca.to_numpy(ca.align_batch(gpu(z1), gpu(z2), ctx=loaded))
+        acc.check_batch(res, z1, z2)
+    finally:
+        torch.cuda.synchronize()
+        loaded.close()
+        plain.close()

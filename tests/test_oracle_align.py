@@ -402,7 +402,7 @@ def test_generator_template_truth():
 
 @pytest.mark.parametrize("n,m0,theta0", [(64, 16, 1.0), (200, 150, -2.2), (257, 1, 0.4)])
 def test_initializer_reproduces_curve_in_matrix_form(n, m0, theta0):
-    """Hand-off of section 4 in the matrix notation of section 2: with
+    """Hand-off of section 3 in the matrix notation of section 2: with
     beta2 built so that R(theta0) beta2(t + t0) = beta1(t) at t0 = m0 / n,
     the oracle returns exactly that t0 and R, and applying them to the nodes
     of beta2 reproduces beta1."""

@@ -1,4 +1,4 @@
-"""Pins for the SRV oracle (section 4): closed forms, invariances and the
+"""Pins for the SRV oracle (section 3): closed forms, invariances and the
 exact recovery of a known (t0, R) in Eq. (dist2-energy)."""
 import math
 
