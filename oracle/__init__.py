@@ -65,6 +65,9 @@ def lib():
                                              ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.oracle_align_batch_f32.restype = ctypes.c_int
+        L.oracle_check_batch_f32.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                             ctypes.c_int, ctypes.c_int] + [ctypes.c_void_p] * 9
+        L.oracle_check_batch_f32.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -142,6 +145,31 @@ def align_batch_f32(z1: np.ndarray, z2: np.ndarray, nthreads: int = 0):
                                         m.ctypes.data, th.ctypes.data, e.ctypes.data,
                                         t.ctypes.data)
     return m, th, e, t, used
+
+
+def check_batch_f32(z1: np.ndarray, z2: np.ndarray, shifts: np.ndarray, nthreads: int = 0):
+    """Slow method over a batch of complex64 pairs [B, n], plus each pair read
+    at a given correlation shift (start index (n - shift) mod n).
+
+    Returns a dict of arrays: m, theta_paper, E, T (the optimum, paper
+    notation), T2 (largest value over the other start indices), and at the
+    given shift T_at, theta_paper_at, E_at; plus "threads".
+    """
+    z1 = np.ascontiguousarray(z1, dtype=np.complex64)
+    z2 = np.ascontiguousarray(z2, dtype=np.complex64)
+    B, n = z1.shape
+    sh = np.ascontiguousarray(shifts, dtype=np.int32)
+    assert sh.shape == (B,)
+    out = {"m": np.empty(B, dtype=np.int32)}
+    for k in ("theta_paper", "E", "T", "T2", "T_at", "theta_paper_at", "E_at"):
+        out[k] = np.empty(B)
+    used = lib().oracle_check_batch_f32(z1.ctypes.data, z2.ctypes.data, B, n, int(nthreads), sh.ctypes.data,
+                                        out["m"].ctypes.data, out["theta_paper"].ctypes.data,
+                                        out["E"].ctypes.data, out["T"].ctypes.data, out["T2"].ctypes.data,
+                                        out["T_at"].ctypes.data, out["theta_paper_at"].ctypes.data,
+                                        out["E_at"].ctypes.data)
+    out["threads"] = used
+    return out
 
 
 def wrap_angle(a):

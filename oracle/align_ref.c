@@ -210,3 +210,59 @@ int oracle_align_batch_f32(const float* z1, const float* z2, int64_t num_pairs, 
 #endif
     return used;
 }
+
+/*
+ * The slow method over a batch of complex64 pairs (as oracle_align_batch_f32)
+ * that also evaluates each pair at a start index chosen elsewhere: for pair p
+ * the start index m_at = (n - shift_in[p]) mod n (shift_in holds correlation
+ * shifts s, the library's reporting form).  Outputs per pair: the best index
+ * and its value, angle and energy, the largest value over the other indices
+ * (t2_out), and at m_at the value, angle and energy of Eq. disc-energy
+ * (t_at, theta_at, e_at).  Nothing here changes what the slow method
+ * computes; the extra outputs are the same per-index quantities read at a
+ * second index.  Returns the number of threads used.
+ */
+int oracle_check_batch_f32(const float* z1, const float* z2, int64_t num_pairs, int n,
+                           int nthreads, const int32_t* shift_in, int32_t* m_out,
+                           double* theta_out, double* e_out, double* t_out, double* t2_out,
+                           double* t_at, double* theta_at, double* e_at)
+{
+    int used = 1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+    {
+#pragma omp single
+        used = omp_get_num_threads();
+#endif
+        double* b1 = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+        double* b2 = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+        double* T = (double*)malloc(sizeof(double) * (size_t)n);
+        double* H = (double*)malloc(sizeof(double) * (size_t)n);
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+        for (int64_t p = 0; p < num_pairs; ++p) {
+            const float* s1 = z1 + (size_t)p * 2 * (size_t)n;
+            const float* s2 = z2 + (size_t)p * 2 * (size_t)n;
+            for (int i = 0; i < 2 * n; ++i) { b1[i] = (double)s1[i]; b2[i] = (double)s2[i]; }
+            int m; double th, e, t;
+            oracle_align_pair(b1, b2, n, &m, &th, &e, &t, T, H);
+            m_out[p] = m; theta_out[p] = th; e_out[p] = e; t_out[p] = t;
+            double t2 = -1.0;
+            for (int k = 0; k < n; ++k)
+                if (k != m && T[k] > t2) t2 = T[k];
+            t2_out[p] = t2;
+            int sh = shift_in[p] % n;
+            if (sh < 0) sh += n;
+            const int ma = (n - sh) % n;
+            t_at[p] = T[ma];
+            theta_at[p] = H[ma];
+            e_at[p] = oracle_energy(b1, b2, n, ma, H[ma]);
+        }
+        free(b1); free(b2); free(T); free(H);
+#ifdef _OPENMP
+    }
+#endif
+    return used;
+}

@@ -366,6 +366,28 @@ def test_batch_matches_pairs():
         assert m[p] == r["m"] and th[p] == r["theta_paper"] and e[p] == r["E"]
 
 
+def test_check_batch_reads_the_slow_method_at_a_given_shift():
+    """check_batch_f32 (the benchmark's full-batch accuracy leg) returns the
+    slow method's optimum and, at any correlation shift s, the value, angle
+    and energy of start index (n - s) mod n, the same numbers the per-pair
+    functions give; T2 is the largest value over the other indices."""
+    rng = np.random.default_rng(11)
+    B, n = 5, 48
+    z1 = np.stack([random_curve(rng, n) for _ in range(B)]).astype(np.complex64)
+    z2 = np.stack([random_curve(rng, n) for _ in range(B)]).astype(np.complex64)
+    shifts = np.array([0, 1, 17, n - 1, 30], dtype=np.int32)
+    r = oracle.check_batch_f32(z1, z2, shifts, nthreads=2)
+    for p in range(B):
+        a, b = z1[p].astype(np.complex128), z2[p].astype(np.complex128)
+        ref = oracle.align_pair(a, b)
+        assert r["m"][p] == ref["m"] and r["E"][p] == ref["E"] and r["T"][p] == ref["T"]
+        T = ref["T_all"]
+        assert r["T2"][p] == np.max(np.delete(T, ref["m"]))
+        ma = (n - int(shifts[p])) % n
+        assert r["T_at"][p] == T[ma] and r["theta_paper_at"][p] == ref["theta_all"][ma]
+        assert r["E_at"][p] == oracle.energy(a, b, ma, ref["theta_all"][ma])
+
+
 def test_resampling_needed_for_nonuniform_sampling():
     """Analogue of the hippopede illustration: a copy of a curve sampled with
     nodes crowded in one part aligns badly as raw nodes and well after
