@@ -56,7 +56,9 @@ enum {
     CA_ERR_HIP = -3,           /* a HIP runtime call failed; see ca_last_error()  */
     CA_ERR_OOM = -4,           /* workspace allocation failed                    */
     CA_ERR_NO_DEVICE = -5,     /* no gfx950 device at the requested index        */
-    CA_ERR_INTERNAL = -6
+    CA_ERR_INTERNAL = -6,
+    CA_ERR_TOO_LARGE = -7      /* input exceeds the static scratch of an
+                                  allocation-free entry point                  */
 };
 
 /* Per-pair result: 32 bytes, 8-byte aligned. */
@@ -180,6 +182,26 @@ ca_status_t align_batch(ca_context_t ctx, const void* z1, const void* z2,
  */
 ca_status_t align_all_pairs(ca_context_t ctx, const void* curves, int32_t m, int32_t n,
                             ca_result_t* out_upper, const ca_options_t* opt, void* stream);
+
+/*
+ * align_all_pairs_noalloc -- align_all_pairs for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops and
+ * harnesses that forbid hipMalloc.  Same arguments, validation, kernels and
+ * results (bit for bit) as align_all_pairs; the per-curve spectra and norms
+ * live in a static device array of CA_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every device it runs on until the process ends, instead of
+ * context workspace.  The call allocates and frees nothing (the context's
+ * tables are built by ca_create).
+ *   Scratch needed: round_up(m * n * 8, 256) + m * 8 bytes (spectra, then
+ *   FP64 norms); a larger gallery (e.g. 4096 x 512 and 2048 x 1024 fit,
+ *   16384 x 128 does not) returns CA_ERR_TOO_LARGE and enqueues nothing.
+ *   Every call on one device shares that device's array and leaves the last
+ *   call's spectra in it: calls that overlap on one device (other streams,
+ *   other contexts or host threads) race and must be serialised by the caller.
+ */
+#define CA_NOALLOC_SCRATCH_BYTES (16 * 1024 * 1024 + 64 * 1024)
+ca_status_t align_all_pairs_noalloc(ca_context_t ctx, const void* curves, int32_t m, int32_t n,
+                                    ca_result_t* out_upper, const ca_options_t* opt, void* stream);
 
 /*
  * resample_arclength -- uniform arc-length resampling (section 2, Eq.

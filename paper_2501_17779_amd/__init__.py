@@ -31,6 +31,8 @@ ERR_UNSUPPORTED_N = -2
 ERR_HIP = -3
 ERR_OOM = -4
 ERR_NO_DEVICE = -5
+ERR_INTERNAL = -6
+ERR_TOO_LARGE = -7
 
 FLAG_NEAR_TIE = 1 << 0
 FLAG_RESCORED = 1 << 1
@@ -45,10 +47,12 @@ PRECISION = {"fp32": 0, "split_bf16": 1, "fp64": 2}
 RESCORE = {"top2": 0, "window": 1}
 RESAMPLE = {"spline": 0, "linear": 1}
 MAX_N = 4096
+NOALLOC_SCRATCH_BYTES = 16 * 1024 * 1024 + 64 * 1024   # static scratch of align_all_pairs_noalloc
 RESAMPLE_MAX_RAW = 32768   # raw vertices per curve accepted by resample_arclength
 
 EXPORTED = ("ca_create", "ca_destroy", "ca_status_string", "ca_last_error", "ca_n_supported",
-            "align_pair", "align_batch", "align_all_pairs", "resample_arclength", "to_initializer",
+            "align_pair", "align_batch", "align_all_pairs", "align_all_pairs_noalloc", "resample_arclength",
+            "to_initializer",
             "srv_transform", "ca_autotune", "ca_tune_get", "ca_tune_set", "ca_tune_save", "ca_tune_load")
 
 # launch-tuning knobs (ca_autotune / ca_tune_*)
@@ -96,6 +100,7 @@ def lib():
             L.align_pair.argtypes = [vp, vp, vp, i32, vp, vp, vp]
             L.align_batch.argtypes = [vp, vp, vp, vp, i32, i64, vp, vp, vp]
             L.align_all_pairs.argtypes = [vp, vp, i32, i32, vp, vp, vp]
+            L.align_all_pairs_noalloc.argtypes = [vp, vp, i32, i32, vp, vp, vp]
             L.resample_arclength.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, i32, vp]
             L.to_initializer.argtypes = [vp, vp, i32, vp, i64, vp, vp, vp]
             L.srv_transform.argtypes = [vp, vp, vp, i32, i64, vp, vp]
@@ -106,7 +111,7 @@ def lib():
             L.ca_tune_save.argtypes = [vp, ctypes.c_char_p]
             L.ca_tune_load.argtypes = [vp, ctypes.c_char_p, pi32]
             for name in ("ca_create", "ca_destroy", "align_pair", "align_batch",
-                         "align_all_pairs", "resample_arclength", "to_initializer", "srv_transform",
+                         "align_all_pairs", "align_all_pairs_noalloc", "resample_arclength", "to_initializer", "srv_transform",
                          "ca_autotune", "ca_tune_get", "ca_tune_set", "ca_tune_save", "ca_tune_load"):
                 getattr(L, name).restype = i32
             _lib = L
@@ -314,6 +319,28 @@ def align_all_pairs(curves, *, rescore="top2", theta_fp64=False, out=None, strea
     opt = _options("fp32", rescore, theta_fp64)
     _check(lib().align_all_pairs(ctx.handle, curves.data_ptr(), m, n, out.data_ptr(),
                                  ctypes.byref(opt), _stream_ptr(stream)))
+    return out
+
+
+def noalloc_scratch_bytes(m: int, n: int) -> int:
+    """Static scratch align_all_pairs_noalloc needs for an m x n gallery."""
+    return (m * n * 8 + 255) // 256 * 256 + m * 8
+
+
+def align_all_pairs_noalloc(curves, out, *, rescore="top2", theta_fp64=False, stream=None, ctx=None):
+    """align_all_pairs through the entry point that allocates nothing: the
+    caller passes the [m(m-1)/2, 32] uint8 output; the spectra live in the
+    library's static per-device scratch (calls on one device must not overlap)."""
+    import torch
+    _require(curves, "curves", (torch.complex64,), 2)
+    _require(out, "out", (torch.uint8,), 2)
+    m, n = curves.shape
+    if out.shape[0] < m * (m - 1) // 2 or out.shape[1] != RESULT_BYTES:
+        raise ValueError("out must be [m(m-1)/2, 32] uint8")
+    ctx = ctx or default_context(curves.device.index)
+    opt = _options("fp32", rescore, theta_fp64)
+    _check(lib().align_all_pairs_noalloc(ctx.handle, curves.data_ptr(), m, n, out.data_ptr(),
+                                         ctypes.byref(opt), _stream_ptr(stream)))
     return out
 
 

@@ -22,6 +22,20 @@ using ca::Plan;
 
 namespace {
 thread_local std::string g_err;
+
+// Scratch of align_all_pairs_noalloc: per-curve spectra, then FP64 norms.
+// Every device the library runs on holds its own copy at its own address, so
+// host code never passes the array's name to a kernel; it uses the device
+// address hipGetSymbolAddress returned for that device (noalloc_scratch_ptr).
+static __device__ __align__(256) unsigned char scratch[CA_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Byte offset of the norms in the scratch and the total size a gallery needs.
+int64_t noalloc_norms_offset(int64_t m, int64_t n) { return (m * n * 8 + 255) / 256 * 256; }
+int64_t noalloc_bytes(int64_t m, int64_t n) { return noalloc_norms_offset(m, n) + m * 8; }
 }  // namespace
 
 namespace ca {
@@ -343,6 +357,22 @@ ca_status_t ensure_bf16_tables(ca_context* c) {
     return CA_OK;
 }
 
+// Device address of the scratch array on `device`, looked up once per device
+// (the caller has made `device` current).
+ca_status_t noalloc_scratch_ptr(int device, void** ptr) {
+    if (device < 0 || device >= kMaxDevices) return fail(CA_ERR_NO_DEVICE, "device index above 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(CA_ERR_INTERNAL, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return CA_OK;
+}
+
 // Grows a context-owned workspace buffer to at least `need` bytes.  The
 // outgrown buffer is retired, not freed: a HIP graph captured earlier may
 // still hold its address, so it stays allocated until ca_destroy.
@@ -388,6 +418,7 @@ const char* ca_status_string(ca_status_t s) {
         case CA_ERR_OOM: return "out of device memory";
         case CA_ERR_NO_DEVICE: return "no gfx950 device";
         case CA_ERR_INTERNAL: return "internal error";
+        case CA_ERR_TOO_LARGE: return "input exceeds the static scratch";
         default: return "unknown status";
     }
 }
@@ -420,6 +451,10 @@ ca_status_t ca_create(ca_context_t* ctx, int device, const char* tune_cache_path
     if (colon != std::string::npos) c->arch.resize(colon);
     DeviceGuard g(device);
     ca_status_t st = ensure_tables(c, false);
+    // team tables and the scratch address now, so that the allocation-free
+    // entry point never needs to allocate or look anything up
+    if (st == CA_OK) st = ensure_team_tables(c);
+    if (st == CA_OK) st = noalloc_scratch_ptr(device, &c->noalloc_scratch);
     if (st == CA_OK && tune_cache_path) st = ca_tune_load(c, tune_cache_path, nullptr);
     if (st != CA_OK) {
         const std::string msg = g_err;
@@ -526,41 +561,87 @@ ca_status_t align_pair(ca_context_t c, const void* z1, const void* z2, int32_t n
     return align_batch(c, z1, z2, nullptr, n, 1, out, opt, stream);
 }
 
-ca_status_t align_all_pairs(ca_context_t c, const void* curves, int32_t m, int32_t n,
-                            ca_result_t* out_upper, const ca_options_t* opt, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Host validation shared by both all-pairs entry points (nothing is touched
+// on the context before it passes).
+ca_status_t check_all_pairs(ca_context_t c, const void* curves, int32_t m, int32_t n,
+                            const ca_result_t* out_upper, const ca_options_t* opt, ca_options_t& o,
+                            bool& nothing) {
+    nothing = false;
     if (!c) return fail(CA_ERR_INVALID_ARG, "context is NULL");
-    ca_options_t o;
     ca_status_t st = parse_opts(opt, o);
     if (st != CA_OK) return st;
     if (m < 0) return fail(CA_ERR_INVALID_ARG, "m < 0");
-    if (m < 2) return CA_OK;
+    if (m < 2) {
+        nothing = true;
+        return CA_OK;
+    }
     if (!curves || !out_upper) return fail(CA_ERR_INVALID_ARG, "curves and out_upper must be non-NULL");
     if (o.precision != CA_PREC_FP32) return fail(CA_ERR_INVALID_ARG, "align_all_pairs is FP32 only");
     if (!ca::allpairs_supported(n))
         return fail(CA_ERR_UNSUPPORTED_N, "align_all_pairs supports n in {64, 128, 256, 512, 1024}");
     const int64_t npairs = (int64_t)m * (m - 1) / 2;
     if (npairs > 0x7fffffffLL) return fail(CA_ERR_INVALID_ARG, "m*(m-1)/2 exceeds 2^31 - 1");
+    return CA_OK;
+}
+
+// Spectra and norms into (spec, norms), then the upper-triangle tiles.
+ca_status_t run_all_pairs(ca_context_t c, const void* curves, int32_t m, int32_t n, ca_result_t* out_upper,
+                          const ca_options_t& o, void* spec, double* norms, hipStream_t s) {
+    hipError_t e = ca::launch_spectra(curves, m, n, spec, norms, team_tw_for(c, n), s);
+    if (e != hipSuccess) return hip_fail(e, "spectra kernel launch");
+    e = ca::launch_allpairs(curves, spec, norms, m, n, out_upper, team_tw_for(c, n), o.rescore, o.theta_fp64,
+                            c->tune.allpairs_cols[team_key(n)], s);
+    if (e != hipSuccess) return hip_fail(e, "all-pairs kernel launch");
+    return CA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ca_status_t align_all_pairs(ca_context_t c, const void* curves, int32_t m, int32_t n,
+                            ca_result_t* out_upper, const ca_options_t* opt, void* stream) {
+    ca_options_t o;
+    bool nothing;
+    ca_status_t st = check_all_pairs(c, curves, m, n, out_upper, opt, o, nothing);
+    if (st != CA_OK || nothing) return st;
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
-    hipStream_t s = (hipStream_t)stream;
     st = ensure_tables(c, false);
     if (st != CA_OK) return st;
     st = ensure_team_tables(c);
     if (st != CA_OK) return st;
-    hipError_t e;
-    if (ca::allpairs_supported(n)) {
-        st = grow(c, &c->d_spec, &c->spec_bytes, (size_t)m * n * 2 * sizeof(float), "spectra workspace");
-        if (st != CA_OK) return st;
-        st = grow(c, (void**)&c->d_norms, &c->norms_bytes, (size_t)m * sizeof(double), "norms workspace");
-        if (st != CA_OK) return st;
-        e = ca::launch_spectra(curves, m, n, c->d_spec, c->d_norms, team_tw_for(c, n), s);
-        if (e != hipSuccess) return hip_fail(e, "spectra kernel launch");
-        e = ca::launch_allpairs(curves, c->d_spec, c->d_norms, m, n, out_upper, team_tw_for(c, n),
-                                o.rescore, o.theta_fp64, c->tune.allpairs_cols[team_key(n)], s);
-        if (e != hipSuccess) return hip_fail(e, "all-pairs kernel launch");
-        return CA_OK;
-    }
-    return fail(CA_ERR_UNSUPPORTED_N, "align_all_pairs supports n in {64, 128, 256, 512, 1024}");
+    st = grow(c, &c->d_spec, &c->spec_bytes, (size_t)m * n * 2 * sizeof(float), "spectra workspace");
+    if (st != CA_OK) return st;
+    st = grow(c, (void**)&c->d_norms, &c->norms_bytes, (size_t)m * sizeof(double), "norms workspace");
+    if (st != CA_OK) return st;
+    return run_all_pairs(c, curves, m, n, out_upper, o, c->d_spec, c->d_norms, (hipStream_t)stream);
+}
+
+ca_status_t align_all_pairs_noalloc(ca_context_t c, const void* curves, int32_t m, int32_t n,
+                                    ca_result_t* out_upper, const ca_options_t* opt, void* stream) {
+    ca_options_t o;
+    bool nothing;
+    ca_status_t st = check_all_pairs(c, curves, m, n, out_upper, opt, o, nothing);
+    if (st != CA_OK || nothing) return st;
+    const int64_t need = noalloc_bytes(m, n);
+    if (need > (int64_t)CA_NOALLOC_SCRATCH_BYTES)
+        return fail(CA_ERR_TOO_LARGE, "align_all_pairs_noalloc: a gallery of " + std::to_string(m) + " x " +
+                                          std::to_string(n) + " needs " + std::to_string(need) +
+                                          " bytes of scratch, above CA_NOALLOC_SCRATCH_BYTES = " +
+                                          std::to_string((long long)CA_NOALLOC_SCRATCH_BYTES));
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    // ca_create built the tables and looked the scratch up; nothing to allocate here
+    if (!c->noalloc_scratch || !team_tw_for(c, n))
+        return fail(CA_ERR_INTERNAL, "context set-up incomplete (team tables or scratch address missing)");
+    unsigned char* base = (unsigned char*)c->noalloc_scratch;
+    return run_all_pairs(c, curves, m, n, out_upper, o, base,
+                         (double*)(base + noalloc_norms_offset(m, n)), (hipStream_t)stream);
 }
 
 ca_status_t resample_arclength(ca_context_t c, const void* raw, const int64_t* raw_offsets,

@@ -63,6 +63,9 @@ struct ca_context {
     size_t spec_bytes = 0;
     double* d_norms = nullptr;
     size_t norms_bytes = 0;
+    // device address of the allocation-free entry point's static scratch on
+    // this context's device (looked up by ca_create)
+    void* noalloc_scratch = nullptr;
     // workspace buffers the context has outgrown: kept until ca_destroy,
     // since graphs captured before the growth still address them
     std::vector<void*> retired;

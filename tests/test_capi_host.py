@@ -66,8 +66,8 @@ int main(void) {
     printf("\"offsets\": [%zu, %zu, %zu, %zu, %zu, %zu],\n", offsetof(ca_result_t, shift),
            offsetof(ca_result_t, flags), offsetof(ca_result_t, theta), offsetof(ca_result_t, e0),
            offsetof(ca_result_t, err_est), offsetof(ca_result_t, gap));
-    printf("\"status\": [%d, %d, %d, %d, %d, %d],\n", CA_OK, CA_ERR_INVALID_ARG, CA_ERR_UNSUPPORTED_N,
-           CA_ERR_HIP, CA_ERR_OOM, CA_ERR_NO_DEVICE);
+    printf("\"status\": [%d, %d, %d, %d, %d, %d, %d, %d],\n", CA_OK, CA_ERR_INVALID_ARG, CA_ERR_UNSUPPORTED_N,
+           CA_ERR_HIP, CA_ERR_OOM, CA_ERR_NO_DEVICE, CA_ERR_INTERNAL, CA_ERR_TOO_LARGE);
     printf("\"flags\": [%u, %u, %u, %u, %u, %u, %u, %u],\n", (unsigned)CA_FLAG_NEAR_TIE,
            (unsigned)CA_FLAG_RESCORED, (unsigned)CA_FLAG_CAND_CAPPED, (unsigned)CA_FLAG_DEGENERATE,
            (unsigned)CA_FLAG_NONFINITE, (unsigned)CA_FLAG_THETA_FP64, (unsigned)CA_FLAG_UNSUPPORTED_N,
@@ -75,7 +75,8 @@ int main(void) {
     printf("\"prec\": [%d, %d, %d], \"rescore\": [%d, %d], \"resample\": [%d, %d], \"max_n\": %d,\n",
            CA_PREC_FP32, CA_PREC_SPLIT_BF16, CA_PREC_FP64, CA_RESCORE_TOP2, CA_RESCORE_WINDOW,
            CA_RESAMPLE_SPLINE, CA_RESAMPLE_LINEAR, CA_MAX_N);
-    printf("\"max_raw\": %d}\n", CA_RESAMPLE_MAX_RAW);
+    printf("\"max_raw\": %d, \"noalloc_bytes\": %lld}\n", CA_RESAMPLE_MAX_RAW,
+           (long long)CA_NOALLOC_SCRATCH_BYTES);
     return 0;
 }
 """
@@ -94,7 +95,8 @@ def test_header_layout_matches_binding(tmp_path):
     assert h["offsets"] == [dt.fields[f][1] for f in ("shift", "flags", "theta", "e0", "err_est", "gap")]
     assert h["options_size"] == ctypes.sizeof(ca._Options) == 16
     assert h["status"] == [ca.OK, ca.ERR_INVALID_ARG, ca.ERR_UNSUPPORTED_N, ca.ERR_HIP, ca.ERR_OOM,
-                           ca.ERR_NO_DEVICE]
+                           ca.ERR_NO_DEVICE, ca.ERR_INTERNAL, ca.ERR_TOO_LARGE]
+    assert h["noalloc_bytes"] == ca.NOALLOC_SCRATCH_BYTES
     assert h["flags"] == [ca.FLAG_NEAR_TIE, ca.FLAG_RESCORED, ca.FLAG_CAND_CAPPED, ca.FLAG_DEGENERATE,
                           ca.FLAG_NONFINITE, ca.FLAG_THETA_FP64, ca.FLAG_UNSUPPORTED_N, ca.FLAG_CLOCKWISE]
     assert h["prec"] == [ca.PRECISION[k] for k in ("fp32", "split_bf16", "fp64")]
@@ -144,7 +146,8 @@ def test_n_supported_predicate(L):
 
 def test_status_strings(L):
     seen = set()
-    for st in (ca.OK, ca.ERR_INVALID_ARG, ca.ERR_UNSUPPORTED_N, ca.ERR_HIP, ca.ERR_OOM, ca.ERR_NO_DEVICE, -6):
+    for st in (ca.OK, ca.ERR_INVALID_ARG, ca.ERR_UNSUPPORTED_N, ca.ERR_HIP, ca.ERR_OOM, ca.ERR_NO_DEVICE,
+               ca.ERR_INTERNAL, ca.ERR_TOO_LARGE):
         s = L.ca_status_string(st).decode()
         assert s and s not in seen
         seen.add(s)
@@ -161,6 +164,7 @@ def test_null_context_is_rejected_on_host(L):
     assert "NULL" in _last(L)
     assert L.align_batch(None, dummy, dummy, None, 64, 4, dummy, None, None) == ca.ERR_INVALID_ARG
     assert L.align_all_pairs(None, dummy, 8, 64, dummy, None, None) == ca.ERR_INVALID_ARG
+    assert L.align_all_pairs_noalloc(None, dummy, 8, 64, dummy, None, None) == ca.ERR_INVALID_ARG
     assert L.resample_arclength(None, dummy, dummy, 4, dummy, dummy, None, None, 0, None) == ca.ERR_INVALID_ARG
     assert L.to_initializer(None, dummy, 64, None, 4, dummy, dummy, None) == ca.ERR_INVALID_ARG
     assert L.srv_transform(None, dummy, None, 64, 4, dummy, None) == ca.ERR_INVALID_ARG
@@ -214,6 +218,19 @@ def test_argument_errors_before_device_work(L):
     assert L.align_all_pairs(ctx, p, -1, 64, p, ctypes.byref(ok), None) == ca.ERR_INVALID_ARG
     assert L.align_all_pairs(ctx, None, 8, 64, p, None, None) == ca.ERR_INVALID_ARG
     assert L.align_all_pairs(ctx, p, 65537, 64, p, None, None) == ca.ERR_INVALID_ARG   # > 2^31 - 1 pairs
+    # the allocation-free variant validates the same way, then checks the static scratch
+    for what, o in bad.items():
+        assert L.align_all_pairs_noalloc(ctx, p, 8, 64, p, ctypes.byref(o), None) == ca.ERR_INVALID_ARG
+        assert what in _last(L)
+    for n in (0, 96, 2048):
+        assert L.align_all_pairs_noalloc(ctx, p, 8, n, p, None, None) == ca.ERR_UNSUPPORTED_N, n
+    assert L.align_all_pairs_noalloc(ctx, None, 8, 64, p, None, None) == ca.ERR_INVALID_ARG
+    assert L.align_all_pairs_noalloc(ctx, p, 65537, 64, p, None, None) == ca.ERR_INVALID_ARG
+    for m, n in ((16384, 128), (4097, 1024), (65536, 64)):
+        assert ca.noalloc_scratch_bytes(m, n) > ca.NOALLOC_SCRATCH_BYTES
+        assert L.align_all_pairs_noalloc(ctx, p, m, n, p, None, None) == ca.ERR_TOO_LARGE, (m, n)
+        assert "CA_NOALLOC_SCRATCH_BYTES" in _last(L)
+    assert L.align_all_pairs_noalloc(ctx, None, 1, 64, None, None, None) == ca.OK
     assert L.resample_arclength(ctx, p, p, -1, p, p, None, None, 0, None) == ca.ERR_INVALID_ARG
     assert L.resample_arclength(ctx, p, p, 4, p, p, None, None, 2, None) == ca.ERR_INVALID_ARG
     assert L.resample_arclength(ctx, None, p, 4, p, p, None, None, 0, None) == ca.ERR_INVALID_ARG
