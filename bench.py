@@ -212,11 +212,14 @@ def full_batch_accuracy(z1, z2, res, nthreads=0):
     s0 = (n - r["m"]) % n
     near = gap < 1e-6
     mism = (~near) & (res["shift"] != s0)
+    # the acceptance rule: the oracle's shift, or at a near-tie a shift within 1e-6 of its value
+    outside = (res["shift"] != s0) & ((~near) | (excess > 1e-6))
     dth = np.abs(oracle.wrap_angle(res["theta"] - oracle.wrap_angle(-r["theta_paper_at"])))
     de = np.abs(res["e0"] - r["E_at"]) / np.maximum(r["E_at"], 1e-300)
     acc = {"pairs": int(B), "theta_err_max": float(dth.max()), "theta_err_mean": float(dth.mean()),
            "e0_rel_err_max": float(de.max()), "e0_rel_err_mean": float(de.mean()),
            "shift_mismatch_outside_near_ties": int(mism.sum()), "near_ties": int(near.sum()),
+           "outside_acceptance_rule": int(outside.sum()),
            "shift_equal_to_oracle": int((res["shift"] == s0).sum()),
            "shift_rel_excess_max": float(excess.max())}
     base = {"value": B / dt, "unit": "pairs/s", "cores": int(r["threads"]), "kind": "oracle",
@@ -280,13 +283,34 @@ def bench_batch(args, torch, ca):
         "roofline": {"bound": "hbm", "kernel": "k_align_team<1024>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
     }
+    # the same inputs through the split-BF16 MFMA path (the metric's second half)
+    res32 = ca.to_numpy(out)
+    out16 = ca.empty_results(B, dev)
+    ms16, _ = time_steps(lambda: ca.align_batch(z1, z2, precision="split_bf16", out=out16), args.steps,
+                         args.warmup, torch, graph=not args.no_graph)
+    mfma_flops = B * MFMA_FLOPS_PER_PAIR_1024
+    line["split_bf16"] = {
+        "value": B / (ms16 * 1e-3), "unit": "pairs/s", "ms_per_step": ms16, "speedup_vs_fp32": ms / ms16,
+        "dtype": "bf16x3 (fp32 accumulate, fp64 shift search and e0)",
+        "roofline": {"bound": "mfma", "kernel": "k_align_bf16_1k",
+                     "achieved": mfma_flops / (ms16 * 1e-3) / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": mfma_flops / (ms16 * 1e-3) / 1e12 / 2500.0,
+                     "hbm_frac": algo_bytes / (ms16 * 1e-3) / 1e9 / HBM_PEAK_GBS}}
     if not args.no_cpu_baseline:
-        res = ca.to_numpy(out)
-        acc, base = full_batch_accuracy(z1.cpu().numpy(), z2.cpu().numpy(), res)
+        z1h, z2h = z1.cpu().numpy(), z2.cpu().numpy()
+        acc, base = full_batch_accuracy(z1h, z2h, res32)
         line["cpu_baseline"] = base
         line["accuracy"] = {"fp32": acc}
+        acc16, _ = full_batch_accuracy(z1h, z2h, ca.to_numpy(out16))
+        line["accuracy"]["split_bf16"] = acc16
     line["paper_context"] = PAPER_TABLE1
     return line
+
+
+# MFMA work of the n = 1024 split-BF16 path per pair: three transforms x two
+# 32-point stages x (4 K-blocks x 2 output blocks x 3 split products) of
+# v_mfma_f32_32x32x16_bf16 (32 x 32 x 16 multiply-adds = 32,768 flops each).
+MFMA_FLOPS_PER_PAIR_1024 = 3 * 2 * 24 * 32 * 32 * 16 * 2
 
 
 HEADLINE_METRIC = "curve-pair alignments/sec at N=1024, FP32 vs split-BF16, err vs FP64 oracle"

@@ -76,7 +76,8 @@ typedef struct {
 enum {
     CA_FLAG_NEAR_TIE = 1u << 0,     /* best and runner-up |C| within 1e-6 relative   */
     CA_FLAG_RESCORED = 1u << 1,     /* more than one shift was re-scored in FP64     */
-    CA_FLAG_CAND_CAPPED = 1u << 2,  /* candidate window held more than 32 shifts     */
+    CA_FLAG_CAND_CAPPED = 1u << 2,  /* candidate window held more than 32 shifts (split-
+                                       BF16 n = 1024: more peaks than its FP64 searches) */
     CA_FLAG_DEGENERATE = 1u << 3,   /* a curve has zero norm; shift 0, theta 0,
                                        e0 = n1 + n2                                  */
     CA_FLAG_NONFINITE = 1u << 4,    /* NaN/Inf in the input; shift 0, theta 0, e0 NaN */
@@ -158,9 +159,17 @@ ca_status_t align_pair(ca_context_t ctx, const void* z1, const void* z2, int32_t
  *     [offsets[p], offsets[p+1]) of both z1 and z2; `n` is ignored.  A pair
  *     whose size is not supported gets CA_FLAG_UNSUPPORTED_N and is skipped.
  *   out: num_pairs results in device memory (pair order).
- *   precision SPLIT_BF16 requires a uniform batch with n == 128; it always
- *   re-scores the whole candidate window (its |C| error, ~1e-5 relative, is
- *   above the near-tie threshold), so options.rescore is ignored there.
+ *   precision SPLIT_BF16 requires a uniform batch with n == 128 or n == 1024
+ *   (DFT-matrix products on the matrix cores with BF16 hi/lo operand splits
+ *   and FP32 accumulation); its |C| error (~1e-5 relative) is above the
+ *   near-tie threshold, so the shift is always settled by FP64 correlations
+ *   and options.rescore is ignored: n = 128 re-scores every shift within
+ *   twice the split-BF16 error bound of the largest |C|; n = 1024 computes the
+ *   FP64 C at the vertex of a least-squares parabola through the split-BF16
+ *   |C|^2 near its peak and at its two neighbours, climbs to a local FP64
+ *   maximum, and climbs again from every separate peak whose split-BF16 |C|
+ *   could exceed that maximum (CA_FLAG_CAND_CAPPED when more than 8, or 16
+ *   for nearly circular shapes, were needed).
  * num_pairs == 0 is a no-op.
  */
 ca_status_t align_batch(ca_context_t ctx, const void* z1, const void* z2,

@@ -373,6 +373,49 @@ ca_status_t noalloc_scratch_ptr(int device, void** ptr) {
     return CA_OK;
 }
 
+// Per-lane operands of the n = 1024 split-BF16 kernel: for lane l = 32 h + c,
+// K-half q and element e, the entries of the 32-point DFT matrix at row
+// j = 16 q + 8 (e / 4) + 4 h + e % 4 and column c (Re, Im, -Im, each as BF16
+// hi and lo), then the twiddles w_1024^{row(g, h) c}, row(g, h) =
+// 8 (g / 4) + 4 h + g % 4, as float4 pairs (g = 2 i, 2 i + 1) at [i][l].
+ca_status_t ensure_bf16_1k_tables(ca_context* c) {
+    if (c->d_bf16_1k) return CA_OK;
+    std::vector<unsigned char> buf(ca::kBf16Tables1kBytes, 0);
+    uint16_t* kk = reinterpret_cast<uint16_t*>(buf.data());
+    const long double tp = 6.283185307179586476925286766559005768L;
+    for (int l = 0; l < 64; ++l) {
+        const int h = l / 32, col = l % 32;
+        for (int q = 0; q < 2; ++q)
+            for (int e = 0; e < 8; ++e) {
+                const int j = 16 * q + 8 * (e / 4) + 4 * h + (e % 4);
+                const long double a = tp * (long double)((j * col) % 32) / 32.0L;
+                const double re = (double)cosl(a), im = (double)-sinl(a);
+                const double v[3] = {re, im, -im};
+                for (int cls = 0; cls < 3; ++cls) {
+                    uint16_t hi, lo;
+                    split_bf16(v[cls], hi, lo);
+                    // lane block: k[q][cls][hl][e], 96 halves per lane
+                    kk[l * 96 + ((q * 3 + cls) * 2 + 0) * 8 + e] = hi;
+                    kk[l * 96 + ((q * 3 + cls) * 2 + 1) * 8 + e] = lo;
+                }
+            }
+    }
+    float* tw = reinterpret_cast<float*>(buf.data() + 64 * 192);
+    for (int i = 0; i < 8; ++i)
+        for (int l = 0; l < 64; ++l)
+            for (int u = 0; u < 2; ++u) {
+                const int g = 2 * i + u, h = l / 32, col = l % 32;
+                const int row = 8 * (g / 4) + 4 * h + (g % 4);
+                const long double a = tp * (long double)((row * col) % 1024) / 1024.0L;
+                tw[(i * 64 + l) * 4 + 2 * u] = (float)cosl(a);
+                tw[(i * 64 + l) * 4 + 2 * u + 1] = (float)-sinl(a);
+            }
+    if (hipMalloc(&c->d_bf16_1k, buf.size()) != hipSuccess) return fail(CA_ERR_OOM, "BF16 n = 1024 constants");
+    hipError_t e = hipMemcpy(c->d_bf16_1k, buf.data(), buf.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "BF16 n = 1024 constants upload");
+    return CA_OK;
+}
+
 // Grows a context-owned workspace buffer to at least `need` bytes.  The
 // outgrown buffer is retired, not freed: a HIP graph captured earlier may
 // still hold its address, so it stays allocated until ca_destroy.
@@ -477,6 +520,7 @@ ca_status_t ca_destroy(ca_context_t c) {
         for (void* p : c->d_team_tw)
             if (p) (void)hipFree(p);
         if (c->d_bf16) (void)hipFree(c->d_bf16);
+        if (c->d_bf16_1k) (void)hipFree(c->d_bf16_1k);
         if (c->d_rs) (void)hipFree(c->d_rs);
         if (c->d_slow) (void)hipFree(c->d_slow);
         if (c->d_bins) (void)hipFree(c->d_bins);
@@ -502,15 +546,19 @@ ca_status_t align_batch(ca_context_t c, const void* z1, const void* z2, const in
     if (!offsets && (n < 2 || n > CA_MAX_N)) return fail(CA_ERR_UNSUPPORTED_N, "n must be in [2, 4096]");
     if (!offsets && o.precision == CA_PREC_FP64 && transform_size(n) > kFp64MaxM)
         return fail(CA_ERR_UNSUPPORTED_N, "FP64 precision takes n with prime factors above 7 only up to 2048");
-    if (o.precision == CA_PREC_SPLIT_BF16 && (offsets || n != 128))
-        return fail(CA_ERR_UNSUPPORTED_N, "split-BF16 precision needs a uniform batch with n = 128");
+    if (o.precision == CA_PREC_SPLIT_BF16 && (offsets || (n != 128 && n != 1024)))
+        return fail(CA_ERR_UNSUPPORTED_N, "split-BF16 precision needs a uniform batch with n = 128 or 1024");
     std::lock_guard<std::mutex> lk(c->mu);
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
     st = ensure_tables(c, o.precision == CA_PREC_FP64);
     if (st != CA_OK) return st;
     hipError_t e;
-    if (o.precision == CA_PREC_SPLIT_BF16) {
+    if (o.precision == CA_PREC_SPLIT_BF16 && n == 1024) {
+        st = ensure_bf16_1k_tables(c);
+        if (st != CA_OK) return st;
+        e = ca::launch_align_bf16_1k(z1, z2, num_pairs, out, c->d_bf16_1k, o.theta_fp64, c->num_cus, s);
+    } else if (o.precision == CA_PREC_SPLIT_BF16) {
         st = ensure_bf16_tables(c);
         if (st != CA_OK) return st;
         e = ca::launch_align_bf16(z1, z2, num_pairs, out, c->d_bf16, o.theta_fp64, c->num_cus, s);

@@ -49,7 +49,8 @@ struct ca_context {
     void* d_tw32 = nullptr;   // float2 arena
     void* d_tw64 = nullptr;   // double2 arena
     void* d_team_tw[11] = {};  // per-pass team-engine twiddles, index log2(n)
-    void* d_bf16 = nullptr;    // split-BF16 per-lane constants (64 x 128 bytes)
+    void* d_bf16 = nullptr;    // split-BF16 per-lane constants, n = 128 (64 x 128 bytes)
+    void* d_bf16_1k = nullptr; // split-BF16 constants and twiddles, n = 1024
     // resampler scratch and the list of curves for the general kernel
     void* d_rs = nullptr;
     int64_t rs_slots = 0;

@@ -64,6 +64,13 @@ hipError_t launch_align_team(const void* z1, const void* z2, int n, int64_t num_
 // 16x16x32 MFMA A layout, and the stage-1 twiddles).
 hipError_t launch_align_bf16(const void* z1, const void* z2, int64_t num_pairs, ca_result_t* out,
                              const void* lane_consts, int theta64, int num_cus, hipStream_t s);
+// Split-BF16 MFMA path, n = 1024 (four-step 32 x 32 DFTs on the 32x32x16
+// MFMA).  tables: 64 per-lane blocks of 192 bytes (the 32-point DFT matrix
+// Re, Im and -Im parts as BF16 hi/lo operands) followed by the per-lane
+// twiddles w_1024^{row c} as 8 x 64 float4.
+constexpr int kBf16Tables1kBytes = 64 * 192 + 8 * 64 * 16;
+hipError_t launch_align_bf16_1k(const void* z1, const void* z2, int64_t num_pairs, ca_result_t* out,
+                                const void* tables, int theta64, int num_cus, hipStream_t s);
 
 // All-pairs: per-curve spectra, then the upper-triangle tile kernel with
 // tiles of (pairs per block) rows x `cols` columns.
