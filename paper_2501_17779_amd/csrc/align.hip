@@ -103,16 +103,23 @@ __global__ __launch_bounds__(256) void k_spectra(const cf* __restrict__ curves, 
     if (t == 0) norms[i] = q2 / N;
 }
 
-// Upper-triangle tiles: blockIdx.y picks TEAMS rows i, blockIdx.x a block of
-// `cols` columns j.  Each row's spectrum and nodes stay in registers; every
-// column's spectrum and nodes are staged once in LDS (double-buffered: the
-// next column is loaded while the current one is aligned) and shared by the
-// rows.
+// Upper-triangle tiles of TEAMS rows i and `cols` columns j over a persistent
+// grid of G blocks (a multiple of 8).  Workgroups are dealt to the 8 XCDs
+// round-robin by block id, so block b = 8 jb + x runs on XCD x; it takes the
+// column tiles tx = 8 u + x of its XCD (each XCD's L2 then holds only its own
+// columns' spectra and nodes) with u = k G8 + jb for even k and
+// u = k G8 + G8 - 1 - jb for odd k (G8 = G / 8): the work of a column tile
+// grows with its index, and the alternating order gives every block about the
+// same share.  For each of its column tiles a block walks every row tile that
+// holds a pair j > i.  Each row's
+// spectrum and nodes stay in registers; every column's spectrum and nodes are
+// staged once in LDS (double-buffered: the next column is loaded while the
+// current one is aligned) and shared by the rows.
 template <int N>
 __global__ __launch_bounds__(256, TeamCfg<N>::AW) void k_allpairs(const cf* __restrict__ curves, const cf* __restrict__ spec,
                                                   const double* __restrict__ norms, int m, int cols,
-                                                  ca_result_t* __restrict__ out, const cf* __restrict__ tw,
-                                                  int rescore, int theta64) {
+                                                  int tx_n, ca_result_t* __restrict__ out,
+                                                  const cf* __restrict__ tw, int rescore, int theta64) {
     constexpr int T = TeamCfg<N>::T;
     constexpr int R = N / T;
     constexpr int TEAMS = 256 / T;
@@ -127,16 +134,24 @@ __global__ __launch_bounds__(256, TeamCfg<N>::AW) void k_allpairs(const cf* __re
     __shared__ cf sz[2][ZS];
     __shared__ cf xbuf[TEAMS * PADN];
     __shared__ int cand_all[TEAMS * kCandCap];
-    const int i0 = blockIdx.y * TEAMS;
-    const int j0 = blockIdx.x * cols;
-    if (j0 >= m || j0 + cols - 1 <= i0) return;   // padding column tile, or no j > i in this tile
     load_twiddles<TeamCfg<N>::TW>(tws, tw);
     const int team = threadIdx.x / T;
     const int t = threadIdx.x % T;
-    const int i = i0 + team;
-    const bool row_ok = i < m;
     cf* lds = xbuf + team * PADN;
     int* cand = cand_all + team * kCandCap;
+    const int xcd = blockIdx.x & 7, jb = blockIdx.x >> 3, g8 = gridDim.x >> 3;
+    const int u_n = tx_n >> 3;
+    for (int k = 0; k * g8 < u_n; ++k) {
+    const int u = k * g8 + ((k & 1) ? g8 - 1 - jb : jb);
+    const int j0 = (8 * u + xcd) * cols;
+    if (u >= u_n || j0 >= m) continue;
+    // row tiles with a pair j > i: i0 <= j0 + cols - 2
+    const int ty_end = (j0 + cols - 2) / TEAMS + 1;
+    for (int ty = 0; ty < ty_end; ++ty) {
+    const int i0 = ty * TEAMS;
+    if (i0 >= m) break;
+    const int i = i0 + team;
+    const bool row_ok = i < m;
     cf Zi[R], zi[R];
     double ni = 0.0;
     if (row_ok) {
@@ -197,6 +212,8 @@ __global__ __launch_bounds__(256, TeamCfg<N>::AW) void k_allpairs(const cf* __re
         }
         if (j + 1 < jend) stash(cur ^ 1);
         __syncthreads();
+    }
+    }
     }
 }
 
@@ -263,17 +280,23 @@ static hipError_t launch_spectra_n(const void* curves, int m, void* spec, double
 template <int N>
 static hipError_t launch_allpairs_n(const void* curves, const void* spec, const double* norms, int m,
                                     ca_result_t* out, const void* tw, int rescore, int theta64, int cols,
-                                    hipStream_t s) {
-    constexpr int TEAMS = 256 / TeamCfg<N>::T;
+                                    int num_cus, hipStream_t s) {
     if (cols < 1) return hipErrorInvalidValue;
-    // Workgroups are dealt to the 8 XCDs round-robin by linear id x + y gx;
-    // with gx a multiple of 8 every column tile x lands on XCD x mod 8 for
-    // all row tiles y, so its spectra and nodes are reused from that XCD's L2
-    // (the padding columns exit at once).
-    const unsigned gx = (unsigned)(((m + cols - 1) / cols + 7) / 8 * 8);
-    dim3 grid(gx, (unsigned)((m + TEAMS - 1) / TEAMS));
-    hipLaunchKernelGGL((k_allpairs<N>), grid, dim3(256), 0, s, (const cf*)curves, (const cf*)spec,
-                       norms, m, cols, out, (const cf*)tw, rescore, theta64);
+    // persistent grid: the occupancy limit on every CU, a multiple of 8 (one
+    // share per XCD), at most one block per column tile
+    static int per_cu = -1;
+    if (per_cu < 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_allpairs<N>, 256, 0) != hipSuccess || nb < 1)
+            nb = 1;
+        per_cu = nb;
+    }
+    const int tx_n = ((m + cols - 1) / cols + 7) / 8 * 8;
+    int64_t grid = (int64_t)num_cus * per_cu;
+    grid = (grid + 7) / 8 * 8;
+    if (grid > tx_n) grid = tx_n;
+    hipLaunchKernelGGL((k_allpairs<N>), dim3((unsigned)grid), dim3(256), 0, s, (const cf*)curves, (const cf*)spec,
+                       norms, m, cols, tx_n, out, (const cf*)tw, rescore, theta64);
     return hipGetLastError();
 }
 
@@ -291,13 +314,13 @@ hipError_t launch_spectra(const void* curves, int m, int n, void* spec, double* 
 
 hipError_t launch_allpairs(const void* curves, const void* spec, const double* norms, int m, int n,
                            ca_result_t* out, const void* tw, int rescore, int theta64, int cols,
-                           hipStream_t s) {
+                           int num_cus, hipStream_t s) {
     switch (n) {
-        case 64: return launch_allpairs_n<64>(curves, spec, norms, m, out, tw, rescore, theta64, cols, s);
-        case 128: return launch_allpairs_n<128>(curves, spec, norms, m, out, tw, rescore, theta64, cols, s);
-        case 256: return launch_allpairs_n<256>(curves, spec, norms, m, out, tw, rescore, theta64, cols, s);
-        case 512: return launch_allpairs_n<512>(curves, spec, norms, m, out, tw, rescore, theta64, cols, s);
-        case 1024: return launch_allpairs_n<1024>(curves, spec, norms, m, out, tw, rescore, theta64, cols, s);
+        case 64: return launch_allpairs_n<64>(curves, spec, norms, m, out, tw, rescore, theta64, cols, num_cus, s);
+        case 128: return launch_allpairs_n<128>(curves, spec, norms, m, out, tw, rescore, theta64, cols, num_cus, s);
+        case 256: return launch_allpairs_n<256>(curves, spec, norms, m, out, tw, rescore, theta64, cols, num_cus, s);
+        case 512: return launch_allpairs_n<512>(curves, spec, norms, m, out, tw, rescore, theta64, cols, num_cus, s);
+        case 1024: return launch_allpairs_n<1024>(curves, spec, norms, m, out, tw, rescore, theta64, cols, num_cus, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -642,7 +642,7 @@ ca_status_t run_all_pairs(ca_context_t c, const void* curves, int32_t m, int32_t
     hipError_t e = ca::launch_spectra(curves, m, n, spec, norms, team_tw_for(c, n), s);
     if (e != hipSuccess) return hip_fail(e, "spectra kernel launch");
     e = ca::launch_allpairs(curves, spec, norms, m, n, out_upper, team_tw_for(c, n), o.rescore, o.theta_fp64,
-                            c->tune.allpairs_cols[team_key(n)], s);
+                            c->tune.allpairs_cols[team_key(n)], c->num_cus, s);
     if (e != hipSuccess) return hip_fail(e, "all-pairs kernel launch");
     return CA_OK;
 }

@@ -73,12 +73,13 @@ hipError_t launch_align_bf16_1k(const void* z1, const void* z2, int64_t num_pair
                                 const void* tables, int theta64, int num_cus, hipStream_t s);
 
 // All-pairs: per-curve spectra, then the upper-triangle tile kernel with
-// tiles of (pairs per block) rows x `cols` columns.
+// tiles of (pairs per block) rows x `cols` columns over a persistent grid
+// (the occupancy limit on every CU).
 hipError_t launch_spectra(const void* curves, int m, int n, void* spectra, double* norms,
                           const void* tw, hipStream_t s);
 hipError_t launch_allpairs(const void* curves, const void* spectra, const double* norms, int m,
                            int n, ca_result_t* out, const void* tw, int rescore, int theta64,
-                           int cols, hipStream_t s);
+                           int cols, int num_cus, hipStream_t s);
 bool allpairs_supported(int n);
 
 // Hand-off records -> (t0*, R*) in the paper's notation.

@@ -376,7 +376,7 @@ ca_status_t autotune(ca_context* c, int knob, int key, hipStream_t s, float& bes
         if (knob == CA_TUNE_ALLPAIRS_COLS) {
             auto launch = [&]() {
                 return ca::launch_allpairs(z1.p, spec.p, (const double*)norms.p, m, n, (ca_result_t*)out.p,
-                                           team_tw_for(c, n), CA_RESCORE_TOP2, 0, v[0], s);
+                                           team_tw_for(c, n), CA_RESCORE_TOP2, 0, v[0], c->num_cus, s);
             };
             return time_launch(launch, s, t, ms);
         }
