@@ -405,13 +405,21 @@ def bench_ragged(args, torch, ca, snap=True):
     half = int(off[-1].item())
     out = ca.empty_results(B, dev)
 
-    def resample():
-        ca.resample_arclength(raw, roff, ooff, out=nodes, with_norms=False, with_flags=False)
+    def resample(stream=None):
+        ca.resample_arclength(raw, roff, ooff, out=nodes, with_norms=False, with_flags=False, stream=stream)
 
-    def align():
-        ca.align_batch(nodes[:half], nodes[half:], offsets=off, out=out)
+    def align(stream=None):
+        ca.align_batch(nodes[:half], nodes[half:], offsets=off, out=out, stream=stream)
 
-    ms, (ms_rs, ms_al) = time_parts([resample, align], args.steps, args.warmup, torch, graph=not args.no_graph)
+    # each call in a graph of its own, an event after each: the parts' times
+    ms_parts, (ms_rs, ms_al) = time_parts([resample, align], args.steps, args.warmup, torch,
+                                          graph=not args.no_graph)
+    # the step: both calls recorded in one library-owned graph, one launch per step
+    if args.no_graph:
+        ms, _ = time_steps(lambda: (resample(), align()), args.steps, args.warmup, torch)
+    else:
+        lg = ca.capture(lambda st: (resample(st), align(st)))
+        ms, _ = time_steps(lg.launch, args.steps, args.warmup, torch)
     # dominant kernel: the resampler (reads every raw vertex and both offset
     # arrays, writes every node)
     algo = raw.numel() * 8 + total * 8 + 2 * (2 * B + 1) * 8
@@ -422,7 +430,9 @@ def bench_ragged(args, torch, ca, snap=True):
     line = base_line(args, B / (ms * 1e-3), "pairs/s", ms, "f32",
                      {"workload": wl, "pairs": B, "raw_vertices": int(raw.numel()), "nodes": total,
                       "n_7smooth": bool(snap)})
-    line["parts_ms"] = {"resample_arclength": ms_rs, "align_batch_ragged": ms_al}
+    line["parts_ms"] = {"resample_arclength": ms_rs, "align_batch_ragged": ms_al,
+                        "note": "each call in its own graph with events between (sum %.3f ms); ms_per_step "
+                                "is one library graph (ca_graph_begin/end) of both calls" % ms_parts}
     traffic = traffic_for("k_resample_fast", sources_digest(["resample.hip", "common.hpp"]), 1.0)
     line["roofline"] = {"bound": "hbm", "kernel": "k_resample_fast", "achieved": achieved,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

@@ -284,6 +284,32 @@ ca_status_t srv_transform(ca_context_t ctx, const void* curves, const int64_t* o
                           int64_t count, void* q_out, void* stream);
 
 /*
+ * Library-owned HIP graphs: a whole step of the method (for example the
+ * resampling of a ragged batch's raw polygons followed by its alignment, or
+ * an all-pairs matrix) recorded once and replayed as one graph launch
+ * (section 2's pipeline: Eq. arc-length-param, then Algorithm 2).
+ *   ca_graph_begin -- opens a capture on a stream the context owns (default
+ *     priority) and returns it in *capture_stream (host handle, a
+ *     hipStream_t).  Issue the calls to record with that stream, with the
+ *     device buffers the replays will use; nothing they enqueue runs before a
+ *     launch.  The capture is in relaxed mode: workspace a call needs is
+ *     allocated at capture time and kept by the context, as for eager calls.
+ *   ca_graph_end -- closes the capture and instantiates it into *graph.  A
+ *     call that failed during the capture fails ca_graph_end with
+ *     CA_ERR_INVALID_ARG (the capture is discarded).
+ *   ca_graph_launch -- replays the graph on `stream` (NULL = default stream),
+ *     stream-ordered like any call; the recorded pointers and sizes are fixed,
+ *     the buffers' contents are read at replay time.
+ *   ca_graph_destroy -- releases the graph (NULL is a no-op).
+ * One capture per context at a time; the context must outlive its graphs.
+ */
+typedef struct ca_graph* ca_graph_t;
+ca_status_t ca_graph_begin(ca_context_t ctx, void** capture_stream);
+ca_status_t ca_graph_end(ca_context_t ctx, ca_graph_t* graph);
+ca_status_t ca_graph_launch(ca_graph_t graph, void* stream);
+ca_status_t ca_graph_destroy(ca_graph_t graph);
+
+/*
  * Launch tuning.  The kernels above take a few launch choices at run time;
  * each context holds one value per (knob, key), starting from defaults that
  * need no tuning.  A choice changes how work is scheduled, never what is

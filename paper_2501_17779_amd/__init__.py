@@ -53,7 +53,7 @@ RESAMPLE_MAX_RAW = 32768   # raw vertices per curve accepted by resample_arcleng
 EXPORTED = ("ca_create", "ca_destroy", "ca_status_string", "ca_last_error", "ca_n_supported",
             "align_pair", "align_batch", "align_all_pairs", "align_all_pairs_noalloc", "resample_arclength",
             "to_initializer",
-            "srv_transform", "ca_autotune", "ca_tune_get", "ca_tune_set", "ca_tune_save", "ca_tune_load")
+            "srv_transform", "ca_graph_begin", "ca_graph_end", "ca_graph_launch", "ca_graph_destroy", "ca_autotune", "ca_tune_get", "ca_tune_set", "ca_tune_save", "ca_tune_load")
 
 # launch-tuning knobs (ca_autotune / ca_tune_*)
 TUNE_KNOBS = {"team_grid": 0, "allpairs_cols": 1, "block_plan": 2, "block_grid": 3, "block_threads": 4}
@@ -104,6 +104,10 @@ def lib():
             L.resample_arclength.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, i32, vp]
             L.to_initializer.argtypes = [vp, vp, i32, vp, i64, vp, vp, vp]
             L.srv_transform.argtypes = [vp, vp, vp, i32, i64, vp, vp]
+            L.ca_graph_begin.argtypes = [vp, ctypes.POINTER(vp)]
+            L.ca_graph_end.argtypes = [vp, ctypes.POINTER(vp)]
+            L.ca_graph_launch.argtypes = [vp, vp]
+            L.ca_graph_destroy.argtypes = [vp]
             pi32 = ctypes.POINTER(i32)
             L.ca_autotune.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_float), vp]
             L.ca_tune_get.argtypes = [vp, i32, i32, pi32, pi32]
@@ -112,6 +116,7 @@ def lib():
             L.ca_tune_load.argtypes = [vp, ctypes.c_char_p, pi32]
             for name in ("ca_create", "ca_destroy", "align_pair", "align_batch",
                          "align_all_pairs", "align_all_pairs_noalloc", "resample_arclength", "to_initializer", "srv_transform",
+                         "ca_graph_begin", "ca_graph_end", "ca_graph_launch", "ca_graph_destroy",
                          "ca_autotune", "ca_tune_get", "ca_tune_set", "ca_tune_save", "ca_tune_load"):
                 getattr(L, name).restype = i32
             _lib = L
@@ -171,6 +176,48 @@ def default_context(device: int | None = None) -> Context:
                 warnings.warn(f"tuning cache {path} not loaded ({e}); using default launch choices")
         _contexts[dev] = ctx
     return _contexts[dev]
+
+
+class Graph:
+    """A HIP graph the library recorded (ca_graph_begin / ca_graph_end):
+    `launch(stream=None)` replays it on a torch stream (current by default)."""
+
+    def __init__(self, handle, ctx):
+        self.handle = handle
+        self.ctx = ctx        # the context must outlive the graph
+
+    def launch(self, stream=None):
+        _check(lib().ca_graph_launch(self.handle, _stream_ptr(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ca_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def capture(fn, *, ctx=None, device=None):
+    """Record the library calls fn(stream) makes on the capture stream into a
+    library-owned HIP graph.  fn receives a torch ExternalStream to pass as the
+    `stream=` argument of every call it makes."""
+    import torch
+    ctx = ctx or default_context(device)
+    torch.cuda.synchronize()
+    h = ctypes.c_void_p()
+    _check(lib().ca_graph_begin(ctx.handle, ctypes.byref(h)))
+    stream = torch.cuda.ExternalStream(h.value, device=torch.device("cuda", ctx.device))
+    g = ctypes.c_void_p()
+    try:
+        fn(stream)
+    finally:
+        st = lib().ca_graph_end(ctx.handle, ctypes.byref(g))
+    _check(st)
+    return Graph(g, ctx)
 
 
 def _knob(knob) -> int:

@@ -22,6 +22,9 @@ using ca::Plan;
 
 namespace {
 thread_local std::string g_err;
+// context whose ca_graph_begin capture is open on this thread: an entry point
+// that fails meanwhile marks the capture as failed
+thread_local ca_context* g_capturing = nullptr;
 
 // Scratch of align_all_pairs_noalloc: per-curve spectra, then FP64 norms.
 // Every device the library runs on holds its own copy at its own address, so
@@ -43,10 +46,12 @@ namespace host {
 
 ca_status_t fail(ca_status_t st, const std::string& msg) {
     g_err = msg;
+    if (g_capturing) g_capturing->capture_failed = true;
     return st;
 }
 ca_status_t hip_fail(hipError_t e, const char* what) {
     g_err = std::string(what) + ": " + hipGetErrorString(e);
+    if (g_capturing) g_capturing->capture_failed = true;
     return CA_ERR_HIP;
 }
 
@@ -513,7 +518,13 @@ ca_status_t ca_destroy(ca_context_t c) {
     if (!c) return CA_OK;
     {
         DeviceGuard g(c->device);
+        if (c->capturing) {
+            hipGraph_t gr = nullptr;
+            if (hipStreamEndCapture(c->cap_stream, &gr) == hipSuccess && gr) (void)hipGraphDestroy(gr);
+            if (g_capturing == c) g_capturing = nullptr;
+        }
         (void)hipDeviceSynchronize();
+        if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
         if (c->d_plans) (void)hipFree(c->d_plans);
         if (c->d_tw32) (void)hipFree(c->d_tw32);
         if (c->d_tw64) (void)hipFree(c->d_tw64);
@@ -529,6 +540,70 @@ ca_status_t ca_destroy(ca_context_t c) {
         for (void* p : c->retired) (void)hipFree(p);
     }
     delete c;
+    return CA_OK;
+}
+
+ca_status_t ca_graph_begin(ca_context_t c, void** capture_stream) {
+    if (!c || !capture_stream) return fail(CA_ERR_INVALID_ARG, "context and capture_stream must be non-NULL");
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->capturing) return fail(CA_ERR_INVALID_ARG, "a capture is already open on this context");
+    DeviceGuard g(c->device);
+    hipError_t e;
+    if (!c->cap_stream && (e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "capture stream");
+    if ((e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed)) != hipSuccess)
+        return hip_fail(e, "hipStreamBeginCapture");
+    c->capturing = true;
+    c->capture_failed = false;
+    g_capturing = c;
+    *capture_stream = (void*)c->cap_stream;
+    return CA_OK;
+}
+
+ca_status_t ca_graph_end(ca_context_t c, ca_graph_t* graph) {
+    if (!c || !graph) return fail(CA_ERR_INVALID_ARG, "context and graph must be non-NULL");
+    *graph = nullptr;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (!c->capturing) return fail(CA_ERR_INVALID_ARG, "no capture is open on this context");
+    DeviceGuard g(c->device);
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &gr);
+    c->capturing = false;
+    if (g_capturing == c) g_capturing = nullptr;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    if (c->capture_failed) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return fail(CA_ERR_INVALID_ARG, "a call failed during the capture; the capture was discarded");
+    }
+    hipGraphExec_t x = nullptr;
+    if ((e = hipGraphInstantiate(&x, gr, nullptr, nullptr, 0)) != hipSuccess) {
+        (void)hipGraphDestroy(gr);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    ca_graph* h = new ca_graph();
+    h->device = c->device;
+    h->graph = gr;
+    h->exec = x;
+    *graph = h;
+    return CA_OK;
+}
+
+ca_status_t ca_graph_launch(ca_graph_t h, void* stream) {
+    if (!h) return fail(CA_ERR_INVALID_ARG, "graph is NULL");
+    DeviceGuard g(h->device);
+    const hipError_t e = hipGraphLaunch(h->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return CA_OK;
+}
+
+ca_status_t ca_graph_destroy(ca_graph_t h) {
+    if (!h) return CA_OK;
+    {
+        DeviceGuard g(h->device);
+        if (h->exec) (void)hipGraphExecDestroy(h->exec);
+        if (h->graph) (void)hipGraphDestroy(h->graph);
+    }
+    delete h;
     return CA_OK;
 }
 

@@ -64,6 +64,10 @@ struct ca_context {
     size_t spec_bytes = 0;
     double* d_norms = nullptr;
     size_t norms_bytes = 0;
+    // library-owned capture stream of ca_graph_begin / ca_graph_end
+    hipStream_t cap_stream = nullptr;
+    bool capturing = false;
+    bool capture_failed = false;
     // device address of the allocation-free entry point's static scratch on
     // this context's device (looked up by ca_create)
     void* noalloc_scratch = nullptr;
@@ -71,6 +75,13 @@ struct ca_context {
     // since graphs captured before the growth still address them
     std::vector<void*> retired;
     ca::host::Tuning tune;
+};
+
+// A HIP graph recorded by ca_graph_begin / ca_graph_end.
+struct ca_graph {
+    int device = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace ca {

@@ -170,6 +170,13 @@ def test_null_context_is_rejected_on_host(L):
     assert L.srv_transform(None, dummy, None, 64, 4, dummy, None) == ca.ERR_INVALID_ARG
     assert L.ca_create(None, 0, None) == ca.ERR_INVALID_ARG
     assert L.ca_destroy(None) == ca.OK
+    h = ctypes.c_void_p()
+    assert L.ca_graph_begin(None, ctypes.byref(h)) == ca.ERR_INVALID_ARG
+    assert L.ca_graph_begin(dummy, None) == ca.ERR_INVALID_ARG
+    assert L.ca_graph_end(None, ctypes.byref(h)) == ca.ERR_INVALID_ARG
+    assert L.ca_graph_end(dummy, None) == ca.ERR_INVALID_ARG
+    assert L.ca_graph_launch(None, None) == ca.ERR_INVALID_ARG
+    assert L.ca_graph_destroy(None) == ca.OK
 
 
 def test_create_without_gpu_reports_no_device(L):

@@ -169,3 +169,83 @@ def test_graph_survives_workspace_growth(ca, kind):
     del g
     torch.cuda.synchronize()
     ctx.close()
+
+
+def _ragged_raw(seed, B):
+    from synth import curves
+    d = curves.ragged_pairs(seed, B)
+    raw = torch.view_as_complex(torch.from_numpy(np.concatenate([d["raw1"], d["raw2"]])).cuda()).contiguous()
+    off2 = d["off2"][1:] + d["off1"][-1]
+    roff = torch.from_numpy(np.concatenate([d["off1"], off2])).cuda()
+    n = np.concatenate([d["n"], d["n"]]).astype(np.int64)
+    ooff = torch.zeros(2 * B + 1, dtype=torch.int64, device="cuda")
+    ooff[1:] = torch.cumsum(torch.from_numpy(n).cuda(), 0)
+    return raw, roff, ooff
+
+
+def test_library_graph_ragged_pipeline(ca):
+    """ca_graph_begin/end record GPU resampling of a ragged batch's raw
+    polygons and its alignment as one library-owned graph; replays with eager
+    work in between reproduce the eager nodes and records bit for bit."""
+    print("[gpu] library graph: resample + ragged alignment", flush=True)
+    B = 40
+    raw, roff, ooff = _ragged_raw(31, B)
+    total = int(ooff[-1].item())
+    half = int(ooff[B].item())
+    nodes = torch.empty(total, dtype=torch.complex64, device="cuda")
+    off = ooff[: B + 1].contiguous()
+    out = ca.empty_results(B, "cuda")
+
+    def step(stream=None):
+        ca.resample_arclength(raw, roff, ooff, out=nodes, with_norms=False, with_flags=False, stream=stream)
+        ca.align_batch(nodes[:half], nodes[half:], offsets=off, out=out, stream=stream)
+
+    step()
+    torch.cuda.synchronize()
+    want_nodes, want = nodes.clone(), out.clone()
+    g = ca.capture(step)
+    for r in range(4):
+        nodes.zero_()
+        out.zero_()
+        junk = torch.randn(1 << 16, device="cuda").sum()
+        g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(nodes, want_nodes) and torch.equal(out, want), f"replay {r} differs"
+        del junk
+    g.close()
+
+
+def test_library_graph_all_pairs_noalloc(ca):
+    """The allocation-free all-pairs entry point recorded in a library graph
+    (the use it is meant for) replays to the eager records of align_all_pairs."""
+    print("[gpu] library graph: align_all_pairs_noalloc", flush=True)
+    g_in = torch.from_numpy(inputs.gallery(32, 50, 512)).cuda()
+    want = ca.align_all_pairs(g_in)
+    out = torch.zeros_like(want)
+    torch.cuda.synchronize()
+    g = ca.capture(lambda st: ca.align_all_pairs_noalloc(g_in, out, stream=st))
+    for r in range(3):
+        out.zero_()
+        g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(out, want), f"replay {r} differs"
+    g.close()
+
+
+def test_library_graph_failed_call_discards_capture(ca):
+    """A call that fails during a capture (here an unsupported n) makes
+    ca_graph_end fail, and the context captures normally afterwards."""
+    z = torch.zeros(4, 5000, dtype=torch.complex64, device="cuda")
+    with pytest.raises(ca.CurveAlignError) as e:
+        ca.capture(lambda st: ca.align_batch(z, z, stream=st))
+    assert e.value.status in (ca.ERR_UNSUPPORTED_N, ca.ERR_INVALID_ARG)
+    a, b = inputs.batch(33, 8, 256)
+    z1, z2 = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    want = ca.align_batch(z1, z2)
+    out = torch.zeros_like(want)
+    torch.cuda.synchronize()
+    g = ca.capture(lambda st: ca.align_batch(z1, z2, out=out, stream=st))
+    g.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(out, want)
+    g.close()
