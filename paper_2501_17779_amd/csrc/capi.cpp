@@ -77,6 +77,7 @@ int transform_size(int n) {
 // then the odd primes.
 std::vector<int> default_radices(int n) {
     std::vector<int> r;
+    if (n < 2) return r;   // no schedule (and no endless division of 0 by 8)
     int m = n;
     while (m % 8 == 0) { r.push_back(8); m /= 8; }
     if (m % 4 == 0) { r.push_back(4); m /= 4; }

@@ -622,6 +622,8 @@ ca_status_t ca_tune_get(ca_context_t c, int32_t knob, int32_t key, int32_t* valu
     if (!c) return fail(CA_ERR_INVALID_ARG, "context is NULL");
     if (!values || !count) return fail(CA_ERR_INVALID_ARG, "values and count must be non-NULL");
     if (knob < 0 || knob >= kKnobs) return fail(CA_ERR_INVALID_ARG, "unknown tuning knob");
+    if (knob == CA_TUNE_BLOCK_PLAN && (key < 2 || key > kMaxM || !smooth7_size(key)))
+        return fail(CA_ERR_INVALID_ARG, "block_plan key must be a 7-smooth size in [2, 8192]");
     std::vector<int> probe = knob == CA_TUNE_BLOCK_PLAN ? default_radices(key) : std::vector<int>{1};
     if (knob == CA_TUNE_ALLPAIRS_COLS) probe = {64};
     if (knob == CA_TUNE_BLOCK_THREADS) probe = {256};

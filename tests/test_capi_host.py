@@ -285,7 +285,8 @@ def test_tuning_arguments_rejected_on_host(L):
     for knob, key in ((0, 96), (1, 2048), (2, 11), (2, 16384), (2, 1)):
         assert L.ca_autotune(ctx, knob, key, None, None) == ca.ERR_UNSUPPORTED_N, (knob, key)
     assert L.ca_autotune(ctx, 3, 5, None, None) == ca.ERR_INVALID_ARG
-    for knob, key in ((0, 96), (1, 2048), (2, 11), (3, 5), (3, -1)):
+    # (block_plan keys 0 and -8 once ran an endless default schedule: found by the sanitizer fuzz)
+    for knob, key in ((0, 96), (1, 2048), (2, 11), (3, 5), (3, -1), (2, 0), (2, -8), (2, 1), (2, 16384)):
         assert L.ca_tune_get(ctx, knob, key, vals, ctypes.byref(cnt)) == ca.ERR_INVALID_ARG, (knob, key)
     # values outside the header's ranges
     def setv(knob, key, *v):
