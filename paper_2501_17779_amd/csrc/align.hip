@@ -104,21 +104,23 @@ __global__ __launch_bounds__(256) void k_spectra(const cf* __restrict__ curves, 
 }
 
 // Upper-triangle tiles of TEAMS rows i and `cols` columns j over a persistent
-// grid of G blocks (a multiple of 8).  Workgroups are dealt to the 8 XCDs
-// round-robin by block id, so block b = 8 jb + x runs on XCD x; it takes the
-// column tiles tx = 8 u + x of its XCD (each XCD's L2 then holds only its own
-// columns' spectra and nodes) with u = k G8 + jb for even k and
-// u = k G8 + G8 - 1 - jb for odd k (G8 = G / 8): the work of a column tile
-// grows with its index, and the alternating order gives every block about the
-// same share.  For each of its column tiles a block walks every row tile that
-// holds a pair j > i.  Each row's
-// spectrum and nodes stay in registers; every column's spectrum and nodes are
+// grid of G blocks: block b takes the tiles t = b, b + G, b + 2 G, ... of the
+// row-major tile grid (row tile t / tx_n, column tile t % tx_n; tx_n, the
+// padded column-tile count, and G are multiples of 8, and G / 8 is odd) and
+// skips at once the tiles without a pair j > i.  All blocks advance through
+// the grid together, so the rows in use at any time are those of one or two
+// row tiles (they stay in L2); workgroups are dealt to the 8 XCDs round-robin
+// by block id, so column tile x is always aligned on XCD x mod 8 and its
+// spectra and nodes are re-read from that XCD's L2; with G / 8 odd a block's
+// column tiles run through every residue (the work of a column tile grows with
+// its index, so a block held to a few column tiles would get an uneven share).
+// Each row's spectrum and nodes stay in registers; every column's spectrum and nodes are
 // staged once in LDS (double-buffered: the next column is loaded while the
 // current one is aligned) and shared by the rows.
 template <int N>
 __global__ __launch_bounds__(256, TeamCfg<N>::AW) void k_allpairs(const cf* __restrict__ curves, const cf* __restrict__ spec,
                                                   const double* __restrict__ norms, int m, int cols,
-                                                  int tx_n, ca_result_t* __restrict__ out,
+                                                  int tx_n, int64_t tiles, ca_result_t* __restrict__ out,
                                                   const cf* __restrict__ tw, int rescore, int theta64) {
     constexpr int T = TeamCfg<N>::T;
     constexpr int R = N / T;
@@ -139,17 +141,10 @@ __global__ __launch_bounds__(256, TeamCfg<N>::AW) void k_allpairs(const cf* __re
     const int t = threadIdx.x % T;
     cf* lds = xbuf + team * PADN;
     int* cand = cand_all + team * kCandCap;
-    const int xcd = blockIdx.x & 7, jb = blockIdx.x >> 3, g8 = gridDim.x >> 3;
-    const int u_n = tx_n >> 3;
-    for (int k = 0; k * g8 < u_n; ++k) {
-    const int u = k * g8 + ((k & 1) ? g8 - 1 - jb : jb);
-    const int j0 = (8 * u + xcd) * cols;
-    if (u >= u_n || j0 >= m) continue;
-    // row tiles with a pair j > i: i0 <= j0 + cols - 2
-    const int ty_end = (j0 + cols - 2) / TEAMS + 1;
-    for (int ty = 0; ty < ty_end; ++ty) {
-    const int i0 = ty * TEAMS;
-    if (i0 >= m) break;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int i0 = (int)(tile / tx_n) * TEAMS;
+    const int j0 = (int)(tile % tx_n) * cols;
+    if (j0 >= m || j0 + cols - 1 <= i0) continue;   // padding column tile, or no j > i in this tile
     const int i = i0 + team;
     const bool row_ok = i < m;
     cf Zi[R], zi[R];
@@ -212,7 +207,6 @@ __global__ __launch_bounds__(256, TeamCfg<N>::AW) void k_allpairs(const cf* __re
         }
         if (j + 1 < jend) stash(cur ^ 1);
         __syncthreads();
-    }
     }
     }
 }
@@ -282,8 +276,8 @@ static hipError_t launch_allpairs_n(const void* curves, const void* spec, const 
                                     ca_result_t* out, const void* tw, int rescore, int theta64, int cols,
                                     int num_cus, hipStream_t s) {
     if (cols < 1) return hipErrorInvalidValue;
-    // persistent grid: the occupancy limit on every CU, a multiple of 8 (one
-    // share per XCD), at most one block per column tile
+    // persistent grid: at most the occupancy limit on every CU, a multiple of
+    // 8 with an odd multiplier (see the kernel)
     static int per_cu = -1;
     if (per_cu < 0) {
         int nb = 0;
@@ -291,12 +285,16 @@ static hipError_t launch_allpairs_n(const void* curves, const void* spec, const 
             nb = 1;
         per_cu = nb;
     }
+    constexpr int TEAMS = 256 / TeamCfg<N>::T;
     const int tx_n = ((m + cols - 1) / cols + 7) / 8 * 8;
-    int64_t grid = (int64_t)num_cus * per_cu;
-    grid = (grid + 7) / 8 * 8;
-    if (grid > tx_n) grid = tx_n;
+    const int64_t tiles = (int64_t)tx_n * ((m + TEAMS - 1) / TEAMS);
+    int64_t g8 = (int64_t)num_cus * per_cu / 8;
+    if (g8 < 1) g8 = 1;
+    if (g8 % 2 == 0) --g8;                 // odd: a block visits every column-tile residue
+    int64_t grid = 8 * g8;
+    if (grid > tiles) grid = tiles;
     hipLaunchKernelGGL((k_allpairs<N>), dim3((unsigned)grid), dim3(256), 0, s, (const cf*)curves, (const cf*)spec,
-                       norms, m, cols, tx_n, out, (const cf*)tw, rescore, theta64);
+                       norms, m, cols, tx_n, tiles, out, (const cf*)tw, rescore, theta64);
     return hipGetLastError();
 }
 
