@@ -26,8 +26,11 @@ __global__ __launch_bounds__(256, 2) void k_align_team(const cf* __restrict__ z1
     constexpr int R = N / T;
     constexpr int TEAMS = 256 / T;
     constexpr int PADN = team_padn<N>();
-    // per team: the FFT exchange area, later two copies of curve 2's nodes
-    constexpr int BUF = PADN > 2 * N ? PADN : 2 * N;
+    // per team: the FFT exchange area, later two copies of curve 2's nodes;
+    // with several teams in a wave the areas are 8 entries (16 banks) apart
+    // beyond their size, so the teams of a half-wave do not meet on the same
+    // LDS banks (every area size here is a multiple of the bank count)
+    constexpr int BUF = (PADN > 2 * N ? PADN : 2 * N) + (T < 64 ? 8 : 0);
     __shared__ cf tws[TeamCfg<N>::TW];
     __shared__ cf lds_all[TEAMS * BUF];
     __shared__ int cand_all[TEAMS * kCandCap];
@@ -80,14 +83,15 @@ __global__ __launch_bounds__(256) void k_spectra(const cf* __restrict__ curves, 
     constexpr int R = N / T;
     constexpr int TEAMS = 256 / T;
     constexpr int PADN = team_padn<N>();
+    constexpr int BUF = PADN + (T < 64 ? 8 : 0);    // team areas 16 banks apart (see k_align_team)
     __shared__ cf tws[TeamCfg<N>::TW];
-    __shared__ cf lds_all[TEAMS * PADN];
+    __shared__ cf lds_all[TEAMS * BUF];
     load_twiddles<TeamCfg<N>::TW>(tws, tw);
     const int team = threadIdx.x / T;
     const int t = threadIdx.x % T;
     const int64_t i = (int64_t)blockIdx.x * TEAMS + team;
     if (i >= m) return;
-    cf* lds = lds_all + team * PADN;
+    cf* lds = lds_all + team * BUF;
     const cf* z = curves + i * N;
     cf v[R];
     double q2 = 0.0;
@@ -134,12 +138,13 @@ __global__ __launch_bounds__(256, TeamCfg<N>::AW) void k_allpairs(const cf* __re
     constexpr int ZS = ZL == kZTwice ? 2 * N : PADN;
     __shared__ cf sZ[2][N];
     __shared__ cf sz[2][ZS];
-    __shared__ cf xbuf[TEAMS * PADN];
+    constexpr int XB = PADN + (T < 64 ? 8 : 0);     // team areas 16 banks apart (see k_align_team)
+    __shared__ cf xbuf[TEAMS * XB];
     __shared__ int cand_all[TEAMS * kCandCap];
     load_twiddles<TeamCfg<N>::TW>(tws, tw);
     const int team = threadIdx.x / T;
     const int t = threadIdx.x % T;
-    cf* lds = xbuf + team * PADN;
+    cf* lds = xbuf + team * XB;
     int* cand = cand_all + team * kCandCap;
     for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int i0 = (int)(tile / tx_n) * TEAMS;

@@ -1,23 +1,18 @@
-// Split-BF16 MFMA path for n = 128 (the precision variant of Algorithm 2).
-//
-// Each DFT of length 128 is computed as two DFT-matrix products on the
-// matrix cores, with n = 8 n1 + n2 and k = k1 + 16 k2:
-//   stage 1:  Y[k1][n2]  = sum_n1 W16[k1][n1] x[8 n1 + n2]          (16-point DFTs)
-//   twiddle:  Y'[k1][n2] = Y[k1][n2] w_128^{n2 k1}                  (FP32, VALU)
-//   stage 2:  X[k1 + 16 k2] = sum_n2 W8[k2][n2] Y'[k1][n2]          (8-point DFTs)
-// Complex products are written as real GEMMs ([Re; Im] stacked).  Operands are
-// split into BF16 pairs, a = a_hi + a_lo with a_hi = bf16(a) and
-// a_lo = bf16(a - a_hi), and each product keeps the three leading terms
+// Split-BF16 MFMA paths (the precision variant of Algorithm 2), n = 128 and
+// n = 1024.  Every DFT runs as DFT-matrix products on the matrix cores with the
+// operands split into BF16 pairs, a = a_hi + a_lo with a_hi = bf16(a) and
+// a_lo = bf16(a - a_hi), keeping the three leading terms of each product
 //   A B ~ A_hi B_hi + A_hi B_lo + A_lo B_hi
-// accumulated in FP32 by v_mfma_f32_16x16x32_bf16.  The DFT matrices are
-// split on the host from FP64 values.  As in the FP32 path the correlation is
-// D = DFT(conj(Z1) Z2) = n conj(C); the epilogue (candidate window with the
-// split-BF16 error bound, FP64 re-scoring, theta, e0) is shared.
-//
-// A wave processes two pairs at a time (a stage-1 product covers 16 columns
-// = 2 pairs x 8 values of n2).  MFMA operand layouts (16x16x32, lane l,
-// element e, accumulator r):  A[l % 16][8 (l / 16) + e],
-// B[8 (l / 16) + e][l % 16],  D[4 (l / 16) + r][l % 16].
+// accumulated in FP32.  Complex products are real GEMMs: with the data as the
+// A operand, [Pr | Pi] = [Ar | Ai] [[Fr, Fi], [-Fi, Fr]]; with the data as the
+// B operand the same block matrix (the DFT matrices are symmetric) is the A
+// operand.  Both stages of a transform read the previous stage's accumulators
+// in place: the data is the A operand where the contraction index is the
+// lane's row and the B operand where it is in-lane, and the K index of every
+// K-block is read in the accumulator-row order, so no value moves between
+// lanes or through LDS inside the three transforms.  The DFT matrices are split
+// on the host from FP64 values; twiddles between the stages are FP32.  As in
+// the FP32 path the correlation is D = DFT(conj(Z1) Z2) = n conj(C).
 #include "epilogue.hpp"
 #include "launch.hpp"
 
@@ -25,13 +20,6 @@ namespace ca {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-struct Bf16Lane {
-    bf16x8 s1[4];   // stage-1 A for lane l: Re-block hi, Re-block lo, Im-block hi, Im-block lo
-    bf16x8 s2[2];   // stage-2 A: [W_hi | W_hi] and [W_lo | 0] (K = 32 covers hi and lo B halves)
-    cf tw[4];       // w_128^{n2 k1} for the lane's four stage-1 outputs
-};
-static_assert(sizeof(Bf16Lane) == 128, "per-lane constant block");
 
 constexpr int kBN = 128;
 constexpr int kBPad = team_padn<kBN>();
@@ -65,131 +53,148 @@ __device__ __forceinline__ f32x4 mma(bf16x8 a, bf16x8 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// DFT of length 128 of two pairs' signals.  src(p, n, comp) reads component
-// comp (0 real, 1 imaginary) of element n of pair p; the result is written
-// with dst(p, k, comp, value) in natural order k.
-template <class Src, class Dst>
-__device__ __forceinline__ void dft128x2(Src src, Dst dst, cf* ys, const Bf16Lane& c, int l) {
-    // stage 1: B rows = (Re n1 0..15, Im n1 0..15), columns = (pair, n2)
-    {
-        const int j = l & 15, p = j >> 3, n2 = j & 7;
-        const int comp = l >> 5, n1b = 8 * ((l >> 4) & 1);
-        float v[8];
+// ----------------------------------------------------------------- n = 128
+// Two pairs per wave, v_mfma_f32_16x16x32_bf16.  Lane l (g = l / 16, c = l % 16)
+// holds operand A element e as A[c][8 g + e], operand B element e as
+// B[8 g + e][c] and accumulator r as D[4 g + r][c].  K slot (g, e) is read as
+// part e / 4 (real, imaginary) of index 4 g + e % 4 (16-point stages), or of
+// pair g / 2 and index 4 (g % 2) + e % 4 (8-point stages, whose constant is
+// block-diagonal in the pair).  With x_P[8 n1 + n2] the nodes of pair P:
+//   forward stage 1 (data = A, row c = (P = c / 8, n2 = c % 8), K = n1):
+//       Y_P[k1][n2] = sum_n1 W16^{n1 k1} x_P[8 n1 + n2]; lane column k1 = c,
+//       rows (P, n2) = 4 g + r, i.e. P = g / 2, n2 = 4 (g % 2) + r
+//   twiddle w_128^{n2 k1}
+//   forward stage 2 (data = B, K = (P, n2)): X_P[k1 + 16 k2] =
+//       sum_n2 W8^{n2 k2} Y'_P[k1][n2]; lane column k1 = c, rows (P, k2)
+// The correlation transform of Q = conj(X1) X2 (index m = m1 + 16 m2 with
+// m1 = c in the lane's column and m2 = 4 (g % 2) + r in its rows) takes the
+// slow index first:
+//   stage 1 (data = A, row m1 = c, K = (P, m2)): U_P[m1][s1] =
+//       sum_m2 W8^{m2 s1} Q_P[m1 + 16 m2]; lane column (P, s1) = c, rows m1 = 4 g + r
+//   twiddle w_128^{m1 s1}
+//   stage 2 (data = B, K = m1): D_P[s1 + 8 s2] = sum_m1 W16^{m1 s2} U'_P[m1][s1];
+//       lane column (P, s1) = c, rows s2 = 4 g + r.
+// The two constants (the 16-point matrix and the block-diagonal 8-point one,
+// each as a real and an imaginary output block in BF16 hi and lo) are the same
+// registers for all six stages.  D is then written to LDS in natural order and
+// the shared epilogue (candidate window with the split-BF16 error bound,
+// FP64 re-scoring, theta, e0) runs with one team of 32 lanes per pair.
+struct Bf16Lane {
+    bf16x8 k1[2][2];   // 16-point matrix: [output part][hi, lo]
+    bf16x8 k2[2][2];   // block-diagonal 8-point matrix: [output part][hi, lo]
+    cf twf[4];         // w_128^{(4 (g % 2) + r) c}
+    cf twt[4];         // w_128^{(4 g + r) (c % 8)}
+};
+static_assert(sizeof(Bf16Lane) == 192, "per-lane constant block");
+
+template <bool DATA_A>
+__device__ __forceinline__ void stage128(const float (&in)[8], const bf16x8 (&K)[2][2], cf (&outv)[4]) {
+    bf16x8 dh, dl;
+    split8(in, dh, dl);
+    f32x4 acc[2];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = src(p, 8 * (n1b + e) + n2, comp);
-        bf16x8 bh, bl;
-        split8(v, bh, bl);
-        f32x4 yr = {0.0f, 0.0f, 0.0f, 0.0f}, yi = {0.0f, 0.0f, 0.0f, 0.0f};
-        yr = mma(c.s1[0], bh, yr);
-        yr = mma(c.s1[0], bl, yr);
-        yr = mma(c.s1[1], bh, yr);
-        yi = mma(c.s1[2], bh, yi);
-        yi = mma(c.s1[2], bl, yi);
-        yi = mma(c.s1[3], bh, yi);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int k1 = 4 * (l >> 4) + r;
-            ys[p * kBN + k1 * 8 + n2] = mul(cf{yr[r], yi[r]}, c.tw[r]);
+    for (int ob = 0; ob < 2; ++ob) {
+        acc[ob] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        if constexpr (DATA_A) {
+            acc[ob] = mma(dh, K[ob][0], acc[ob]);
+            acc[ob] = mma(dh, K[ob][1], acc[ob]);
+            acc[ob] = mma(dl, K[ob][0], acc[ob]);
+        } else {
+            acc[ob] = mma(K[ob][0], dh, acc[ob]);
+            acc[ob] = mma(K[ob][1], dh, acc[ob]);
+            acc[ob] = mma(K[ob][0], dl, acc[ob]);
         }
     }
-    wave_lds_sync();
-    // stage 2 (one pair per product): B rows = (Re n2 hi, Im n2 hi, Re n2 lo, Im n2 lo), columns = k1
 #pragma unroll
-    for (int pp = 0; pp < 2; ++pp) {
-        const int k1 = l & 15, comp = (l >> 4) & 1, half = l >> 5;
-        const float* yc = reinterpret_cast<const float*>(ys + pp * kBN + k1 * 8) + comp;
-        float u[8];
+    for (int r = 0; r < 4; ++r) outv[r] = cf{acc[0][r], acc[1][r]};
+}
+
+// operand elements of the next stage from a lane's four complex values
+__device__ __forceinline__ void ops4(const cf (&v)[4], float (&o)[8]) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) u[e] = yc[2 * e];
-        bf16x8 bh, bl;
-        split8(u, bh, bl);
-        const bf16x8 b = half ? bl : bh;
-        f32x4 x = {0.0f, 0.0f, 0.0f, 0.0f};
-        x = mma(c.s2[0], b, x);
-        x = mma(c.s2[1], b, x);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = 4 * (l >> 4) + r;      // row: Re X[k2 = i] for i < 8, Im X[k2 = i - 8] otherwise
-            dst(pp, k1 + 16 * (i & 7), i >> 3, x[r]);
-        }
+    for (int r = 0; r < 4; ++r) {
+        o[r] = v[r].x;
+        o[4 + r] = v[r].y;
     }
-    wave_lds_sync();
+}
+
+// Forward DFT of two pairs' curves (x0: pair 0, x1: pair 1, NULL: zeros).
+__device__ __forceinline__ void fwd128(const cf* x0, const cf* x1, const Bf16Lane& k, int g, int c, cf (&X)[4]) {
+    const cf* x = (c >> 3) ? x1 : x0;
+    const int n2 = c & 7;
+    float op[8];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const cf v = x ? x[8 * (4 * g + e) + n2] : cf{0.0f, 0.0f};
+        op[e] = v.x;
+        op[4 + e] = v.y;
+    }
+    cf y[4];
+    stage128<true>(op, k.k1, y);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) y[r] = mul(y[r], k.twf[r]);
+    ops4(y, op);
+    stage128<false>(op, k.k2, X);
 }
 
 __global__ __launch_bounds__(256, 2) void k_align_bf16(const cf* __restrict__ z1, const cf* __restrict__ z2,
                                                        int64_t num_pairs, ca_result_t* __restrict__ out,
                                                        const Bf16Lane* __restrict__ cst, int theta64) {
-    __shared__ cf s_z[4][2][2][kBPad];    // [wave][pair][curve] nodes, padded layout
-    __shared__ cf s_w[4][2][2][kBN];      // [wave][pair][signal] spectra / correlation
-    __shared__ cf s_y[4][2][kBN];         // stage-1 outputs
+    __shared__ cf s_zt[4][2][2 * kBN];    // [wave][pair] curve 2's nodes twice (FP64 re-scoring)
+    __shared__ cf s_d[4][2][kBN + 8];     // [wave][pair] D in natural order
     __shared__ int s_cand[4][2][kCandCap];
-    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const Bf16Lane c = cst[l];
-    cf* ys = &s_y[wv][0][0];
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+    const Bf16Lane k = cst[l];
+    const int p = l >> 5, t = l & 31;     // epilogue: team p (pair) of 32 lanes
+    cf* zt = s_zt[wv][p];
     const int64_t groups = (num_pairs + 1) / 2;
-    for (int64_t g = (int64_t)blockIdx.x * 4 + wv; g < groups; g += (int64_t)gridDim.x * 4) {
-        const int64_t p0 = 2 * g;
+    for (int64_t grp = (int64_t)blockIdx.x * 4 + wv; grp < groups; grp += (int64_t)gridDim.x * 4) {
+        const int64_t p0 = 2 * grp;
         const bool has1 = p0 + 1 < num_pairs;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int idx = l + 64 * i;            // pair (idx >> 8), curve (idx >> 7) & 1, node idx & 127
-            const int p = idx >> 8, cv = (idx >> 7) & 1, n = idx & (kBN - 1);
-            cf val = {0.0f, 0.0f};
-            if (p == 0 || has1) val = (cv ? z2 : z1)[(p0 + p) * kBN + n];
-            s_z[wv][p][cv][lpad<kBN>(n)] = val;
-        }
-        wave_lds_sync();
-        // FP64 norms, one team of 32 lanes per pair
-        const int p = l >> 5, t = l & 31;
-        double q1 = 0.0, q2 = 0.0;
+        const cf* a0p = z1 + p0 * kBN;
+        const cf* b0p = z2 + p0 * kBN;
+        const cf* a1p = has1 ? a0p + kBN : nullptr;
+        const cf* b1p = has1 ? b0p + kBN : nullptr;
+        // the epilogue's team layout: curve 1 in registers, curve 2 twice in LDS
+        const bool mine = p == 0 || has1;
         cf a0[4];
+        double q1 = 0.0, q2 = 0.0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            a0[q] = s_z[wv][p][0][lpad<kBN>(t + 32 * q)];
-            const cf b = s_z[wv][p][1][lpad<kBN>(t + 32 * q)];
-            q1 = fma((double)a0[q].x, (double)a0[q].x, fma((double)a0[q].y, (double)a0[q].y, q1));
-            q2 = fma((double)b.x, (double)b.x, fma((double)b.y, (double)b.y, q2));
+            const cf va = mine ? (p ? a1p : a0p)[t + 32 * q] : cf{0.0f, 0.0f};
+            const cf vb = mine ? (p ? b1p : b0p)[t + 32 * q] : cf{0.0f, 0.0f};
+            a0[q] = va;
+            zt[t + 32 * q] = vb;
+            zt[kBN + t + 32 * q] = vb;
+            q1 = fma((double)va.x, (double)va.x, fma((double)va.y, (double)va.y, q1));
+            q2 = fma((double)vb.x, (double)vb.x, fma((double)vb.y, (double)vb.y, q2));
         }
         const double n1 = team_sum<32>(q1) / kBN, n2 = team_sum<32>(q2) / kBN;
-        for (int cv = 0; cv < 2; ++cv) {
-            dft128x2([&](int pp, int n, int comp) {
-                         return reinterpret_cast<const float*>(&s_z[wv][pp][cv][lpad<kBN>(n)])[comp];
-                     },
-                     [&](int pp, int k, int comp, float v) {
-                         float* w = reinterpret_cast<float*>(&s_w[wv][pp][cv][k]);
-                         w[comp] = v;
-                     },
-                     ys, c, l);
-        }
+        cf X1[4], X2[4];
+        fwd128(a0p, a1p, k, g, c, X1);
+        fwd128(b0p, b1p, k, g, c, X2);
+        cf Q[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int idx = l + 64 * i, pp = idx >> 7, k = idx & (kBN - 1);
-            s_w[wv][pp][0][k] = cjmul(s_w[wv][pp][0][k], s_w[wv][pp][1][k]);
-        }
+        for (int r = 0; r < 4; ++r) Q[r] = cjmul(X1[r], X2[r]);
+        float op[8];
+        ops4(Q, op);
+        cf u[4];
+        stage128<true>(op, k.k2, u);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) u[r] = mul(u[r], k.twt[r]);
+        ops4(u, op);
+        cf D[4];
+        stage128<false>(op, k.k1, D);
+        // D_P[s1 + 8 s2] with P = c / 8, s1 = c % 8, s2 = 4 g + r
+#pragma unroll
+        for (int r = 0; r < 4; ++r) s_d[wv][c >> 3][(c & 7) + 8 * (4 * g + r)] = D[r];
         wave_lds_sync();
-        dft128x2([&](int pp, int n, int comp) { return reinterpret_cast<const float*>(&s_w[wv][pp][0][n])[comp]; },
-                 [&](int pp, int k, int comp, float v) {
-                     float* w = reinterpret_cast<float*>(&s_w[wv][pp][1][k]);
-                     w[comp] = v;
-                 },
-                 ys, c, l);
         cf d[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) d[q] = s_w[wv][p][1][t + 32 * q];
-        wave_lds_sync();
-        // curve 2's nodes twice over the pair's spectra area (read into d
-        // above), so the re-scoring reads them at constant offsets
-        cf* zt = &s_w[wv][p][0][0];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const cf b = s_z[wv][p][1][lpad<kBN>(t + 32 * q)];
-            zt[t + 32 * q] = b;
-            zt[kBN + t + 32 * q] = b;
-        }
-        wave_lds_sync();
+        for (int q = 0; q < 4; ++q) d[q] = s_d[wv][p][t + 32 * q];
         const ca_result_t res = team_epilogue<kBN, 32, kZTwice>(d, a0, zt, s_cand[wv][p], t, n1, n2,
                                                                 CA_RESCORE_WINDOW, theta64, kBf16U);
-        if (t == 0 && (p == 0 || has1)) out[p0 + p] = res;
+        if (t == 0 && mine) out[p0 + p] = res;
         wave_lds_sync();
     }
 }

@@ -318,43 +318,51 @@ void split_bf16(double w, uint16_t& hi, uint16_t& lo) {
     lo = bf16_rne((float)(w - bf16_value(hi)));
 }
 
-// Per-lane operands of the n = 128 split-BF16 kernel (layout of Bf16Lane).
+// Per-lane operands of the n = 128 split-BF16 kernel (layout of Bf16Lane):
+// for lane l = 16 g + c and element e (part e / 4, index i = e % 4), the
+// 16-point DFT matrix at (4 g + i, c) and the 8-point one at
+// (4 (g % 2) + i, c % 8) when pair g / 2 equals pair c / 8 (else 0), each as
+// the real-GEMM entry of output part ob (Re, Im) in BF16 hi and lo; then the
+// twiddles w_128^{(4 (g % 2) + r) c} and w_128^{(4 g + r) (c % 8)}.
 ca_status_t ensure_bf16_tables(ca_context* c) {
     if (c->d_bf16) return CA_OK;
     struct Lane {
-        uint16_t s1[4][8];
-        uint16_t s2[2][8];
-        float tw[4][2];
+        uint16_t k1[2][2][8];
+        uint16_t k2[2][2][8];
+        float twf[4][2];
+        float twt[4][2];
     };
-    static_assert(sizeof(Lane) == 128, "lane block");
+    static_assert(sizeof(Lane) == 192, "lane block");
     std::vector<Lane> lanes(64);
     const long double tp = 6.283185307179586476925286766559005768L;
-    auto wr = [&](int a, int b, int m) { return (double)cosl(tp * (long double)((a * b) % m) / m); };
-    auto wi = [&](int a, int b, int m) { return (double)-sinl(tp * (long double)((a * b) % m) / m); };
+    // real-GEMM entry of W_M^{n k} for input part `part` and output part ob
+    auto wentry = [&](int M, int n, int k, int part, int ob) {
+        const long double a = tp * (long double)((n * k) % M) / (long double)M;
+        const double re = (double)cosl(a), im = (double)-sinl(a);
+        if (part == 0) return ob == 0 ? re : im;
+        return ob == 0 ? -im : re;
+    };
     for (int l = 0; l < 64; ++l) {
-        const int i = l % 16;
-        for (int e = 0; e < 8; ++e) {
-            const int k = 8 * (l / 16) + e;
-            // stage 1: rows k1 = i; columns (Re n1 0..15, Im n1 0..15)
-            const int n1 = k & 15;
-            const double are = k < 16 ? wr(i, n1, 16) : -wi(i, n1, 16);
-            const double aim = k < 16 ? wi(i, n1, 16) : wr(i, n1, 16);
-            split_bf16(are, lanes[l].s1[0][e], lanes[l].s1[1][e]);
-            split_bf16(aim, lanes[l].s1[2][e], lanes[l].s1[3][e]);
-            // stage 2: rows (Re k2 0..7, Im k2 0..7); columns (Re n2 0..7, Im n2 0..7), twice
-            const int kk = k & 15, n2 = kk & 7, k2 = i & 7;
-            double a2;
-            if (i < 8) a2 = kk < 8 ? wr(k2, n2, 8) : -wi(k2, n2, 8);
-            else a2 = kk < 8 ? wi(k2, n2, 8) : wr(k2, n2, 8);
-            uint16_t h, lo;
-            split_bf16(a2, h, lo);
-            lanes[l].s2[0][e] = h;
-            lanes[l].s2[1][e] = k < 16 ? lo : (uint16_t)0;
-        }
+        const int g = l / 16, col = l % 16;
+        for (int ob = 0; ob < 2; ++ob)
+            for (int e = 0; e < 8; ++e) {
+                const int part = e / 4, i = e % 4;
+                uint16_t hi, lo;
+                split_bf16(wentry(16, 4 * g + i, col, part, ob), hi, lo);
+                lanes[l].k1[ob][0][e] = hi;
+                lanes[l].k1[ob][1][e] = lo;
+                const bool same_pair = (g / 2) == (col / 8);
+                split_bf16(same_pair ? wentry(8, 4 * (g % 2) + i, col % 8, part, ob) : 0.0, hi, lo);
+                lanes[l].k2[ob][0][e] = hi;
+                lanes[l].k2[ob][1][e] = lo;
+            }
         for (int r = 0; r < 4; ++r) {
-            const int n2 = l % 8, k1 = 4 * (l / 16) + r;
-            lanes[l].tw[r][0] = (float)wr(n2, k1, 128);
-            lanes[l].tw[r][1] = (float)wi(n2, k1, 128);
+            const long double af = tp * (long double)(((4 * (g % 2) + r) * col) % 128) / 128.0L;
+            const long double at = tp * (long double)(((4 * g + r) * (col % 8)) % 128) / 128.0L;
+            lanes[l].twf[r][0] = (float)cosl(af);
+            lanes[l].twf[r][1] = (float)-sinl(af);
+            lanes[l].twt[r][0] = (float)cosl(at);
+            lanes[l].twt[r][1] = (float)-sinl(at);
         }
     }
     if (hipMalloc(&c->d_bf16, sizeof(Lane) * 64) != hipSuccess) return fail(CA_ERR_OOM, "BF16 constants");

@@ -59,9 +59,10 @@ hipError_t launch_align_team(const void* z1, const void* z2, int n, int64_t num_
                              ca_result_t* out, const void* tw, int rescore, int theta64,
                              int num_cus, int grid_mult, hipStream_t s);
 
-// Split-BF16 MFMA path, n = 128.  lane_consts: 64 per-lane blocks of 128
-// bytes (stage-1 and stage-2 DFT matrices as BF16 hi/lo operands in the
-// 16x16x32 MFMA A layout, and the stage-1 twiddles).
+// Split-BF16 MFMA path, n = 128, two pairs per wave.  lane_consts: 64
+// per-lane blocks of 192 bytes (the 16-point DFT matrix and the
+// pair-block-diagonal 8-point one as BF16 hi/lo operands of the 16x16x32
+// MFMA, and the twiddles of both transform kinds).
 hipError_t launch_align_bf16(const void* z1, const void* z2, int64_t num_pairs, ca_result_t* out,
                              const void* lane_consts, int theta64, int num_cus, hipStream_t s);
 // Split-BF16 MFMA path, n = 1024 (four-step 32 x 32 DFTs on the 32x32x16
