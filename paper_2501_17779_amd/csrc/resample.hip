@@ -16,7 +16,12 @@
 // extension truncated kRsW knots to either side (forward elimination from the
 // left end, backward elimination from the right end, meeting at the chunk's
 // right edge, then back substitution): the truncation changes M by at most
-// ~0.268^kRsW relative, far below FP32 rounding for kRsW = 12.
+// ~0.268^W relative for a window of W knots.  A node moves by h^2 / 6 times
+// the change of the moments around it (h the chord parameter step), so even
+// a relative change of 1e-3 moves nodes far less than FP32 rounding of the
+// curve when h is small: the general kernel uses W = kRsW = 12 (3e-7), the
+// fast kernel W = kFtW = 6 (3.7e-4) for curves of at least kFtBigM = 256
+// vertices (h <= 1/256) and W = 12 below.
 #include <math.h>
 
 #include <type_traits>
@@ -353,8 +358,10 @@ __global__ __launch_bounds__(kRsNT) void k_resample(const cf* __restrict__ raw, 
 // segment (a binary search over the tile's knots only for tiles with many
 // nodes per knot).  Pass 3 centres the nodes and accumulates their norm.
 constexpr int kFtC = 7;                    // knots per lane in the local solve
+constexpr int kFtW = 6;                    // solve window on each side, curves of >= kFtBigM vertices
+constexpr int kFtBigM = 256;
 constexpr int kFtK = 64 * kFtC;            // knots per tile
-constexpr int kFtH = kRsW + 1;             // halo on each side
+constexpr int kFtH = kRsW + 1;             // halo on each side (the widest window + 1)
 constexpr int kFtP = kFtK + 2 * kFtH;      // staged knots
 constexpr int kFtSegMax = 24;              // most nodes per lane for lane-owned segments
 // Per-knot LDS arrays are not padded: the local solve and the scan give lane
@@ -593,64 +600,72 @@ __global__ __launch_bounds__(64, 3) void k_resample_fast(const cf* __restrict__ 
         }
         wave_lds_sync();
         if (mode == CA_RESAMPLE_SPLINE) {
-            // local solve for knots [kFtC lane, kFtC (lane + 1)): window kRsW each side
-            float al[kFtC];
-            cf de[kFtC];
-            const int i0 = kFtH + kFtC * lane;           // staged index of the chunk's first knot
-            float hprev = sH[kp(i0 - kRsW - 1)];
-            float alpha = 0.0f;
-            cf delta = {0.0f, 0.0f};
+            // local solve for knots [kFtC lane, kFtC (lane + 1)), window W each
+            // side: W = kFtW for curves of at least kFtBigM vertices (parameter
+            // step h <= 1/kFtBigM), the full halo otherwise (the truncation
+            // reaches the nodes through h^2)
+            auto solve = [&](auto win) {
+                constexpr int W = decltype(win)::value;
+                float al[kFtC];
+                cf de[kFtC];
+                const int i0 = kFtH + kFtC * lane;           // staged index of the chunk's first knot
+                float hprev = sH[kp(i0 - W - 1)];
+                float alpha = 0.0f;
+                cf delta = {0.0f, 0.0f};
 #pragma unroll
-            for (int i = 0; i < kRsW + kFtC; ++i) {
-                const int j = i0 - kRsW + i;
-                const float hj = sH[kp(j)];
-                const cf d = sR[kp(j)];
-                const float b = 2.0f * (hprev + hj);
-                if (i == 0) {
-                    alpha = b;
-                    delta = d;
-                } else {
-                    const float f = hprev * frcp(alpha);
-                    alpha = b - f * hprev;
-                    delta = {d.x - f * delta.x, d.y - f * delta.y};
+                for (int i = 0; i < W + kFtC; ++i) {
+                    const int j = i0 - W + i;
+                    const float hj = sH[kp(j)];
+                    const cf d = sR[kp(j)];
+                    const float b = 2.0f * (hprev + hj);
+                    if (i == 0) {
+                        alpha = b;
+                        delta = d;
+                    } else {
+                        const float f = hprev * frcp(alpha);
+                        alpha = b - f * hprev;
+                        delta = {d.x - f * delta.x, d.y - f * delta.y};
+                    }
+                    hprev = hj;
+                    if (i >= W) { al[i - W] = alpha; de[i - W] = delta; }
                 }
-                hprev = hj;
-                if (i >= kRsW) { al[i - kRsW] = alpha; de[i - kRsW] = delta; }
-            }
-            const int e = i0 + kFtC;
-            float beta = 0.0f, anext = 0.0f;
-            cf eps = {0.0f, 0.0f};
+                const int e = i0 + kFtC;
+                float beta = 0.0f, anext = 0.0f;
+                cf eps = {0.0f, 0.0f};
 #pragma unroll
-            for (int i = kRsW - 1; i >= 0; --i) {
-                const int j = e + i;
-                const float hj = sH[kp(j)], hjm = sH[kp(j - 1)];
-                const cf d = sR[kp(j)];
-                const float b = 2.0f * (hjm + hj);
-                if (i == kRsW - 1) {
-                    beta = b;
-                    eps = d;
-                } else {
-                    const float g = hj * frcp(beta);
-                    beta = b - g * anext;
-                    eps = {d.x - g * eps.x, d.y - g * eps.y};
+                for (int i = W - 1; i >= 0; --i) {
+                    const int j = e + i;
+                    const float hj = sH[kp(j)], hjm = sH[kp(j - 1)];
+                    const cf d = sR[kp(j)];
+                    const float b = 2.0f * (hjm + hj);
+                    if (i == W - 1) {
+                        beta = b;
+                        eps = d;
+                    } else {
+                        const float g = hj * frcp(beta);
+                        beta = b - g * anext;
+                        eps = {d.x - g * eps.x, d.y - g * eps.y};
+                    }
+                    anext = hjm;
                 }
-                anext = hjm;
-            }
-            const float ae = sH[kp(e - 1)];
-            const float aL = al[kFtC - 1];
-            const cf dL = de[kFtC - 1];
-            const float iaL = frcp(aL);
-            const float iden = frcp(beta - ae * ae * iaL);
-            cf Mn = {(eps.x - ae * dL.x * iaL) * iden, (eps.y - ae * dL.y * iaL) * iden};
-            wave_lds_sync();                   // every right-hand side is read before moments overwrite them
+                const float ae = sH[kp(e - 1)];
+                const float aL = al[kFtC - 1];
+                const cf dL = de[kFtC - 1];
+                const float iaL = frcp(aL);
+                const float iden = frcp(beta - ae * ae * iaL);
+                cf Mn = {(eps.x - ae * dL.x * iaL) * iden, (eps.y - ae * dL.y * iaL) * iden};
+                wave_lds_sync();                   // every right-hand side is read before moments overwrite them
 #pragma unroll
-            for (int i = kFtC - 1; i >= 0; --i) {
-                const float cj = sH[kp(i0 + i)];
-                const float ia = frcp(al[i]);
-                const cf Mi = {(de[i].x - cj * Mn.x) * ia, (de[i].y - cj * Mn.y) * ia};
-                sM[kp(kFtC * lane + i)] = Mi;
-                Mn = Mi;
-            }
+                for (int i = kFtC - 1; i >= 0; --i) {
+                    const float cj = sH[kp(i0 + i)];
+                    const float ia = frcp(al[i]);
+                    const cf Mi = {(de[i].x - cj * Mn.x) * ia, (de[i].y - cj * Mn.y) * ia};
+                    sM[kp(kFtC * lane + i)] = Mi;
+                    Mn = Mi;
+                }
+            };
+            if (M >= kFtBigM) solve(std::integral_constant<int, kFtW>{});
+            else solve(std::integral_constant<int, kRsW>{});
         }
         wave_lds_sync();
         // output nodes with arc length in [carry, carry + span) (up to N on the last tile)
