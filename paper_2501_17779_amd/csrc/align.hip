@@ -330,9 +330,9 @@ hipError_t launch_allpairs(const void* curves, const void* spec, const double* n
 
 // -------------------------------------------------------------- block engine
 // Persistent kernels, one pair per workgroup at a time; each launch serves
-// one size class of transform sizes with NT threads and LDS for MMAX values
-// per signal: a whole uniform batch, or the list that k_blk_bin built for the
-// class in a ragged batch.
+// one size class of transform sizes with NT threads and LDS for one signal of
+// MMAX values (the other spectrum waits in registers): a whole uniform batch,
+// or the list that k_blk_bin built for the class in a ragged batch.
 //
 // A 7-smooth n is transformed at size M = n.  Any other n uses the plan's
 // 7-smooth M >= 2n: with a = z1 followed by zeros and b = (z2, z2, zeros),
@@ -441,8 +441,17 @@ __device__ __forceinline__ void block_top2(V b1, int i1, V b2, int i2, V& bv, in
     bv = v; bi = iv; cv = c; ci = ic;
 }
 
+// Waves per SIMD each block-engine kernel is compiled for: the most its
+// registers allow without spilling.
+template <typename T, int NT, int MMAX> constexpr int blk_waves() {
+    if (sizeof(T) == 8) return MMAX >= 4096 ? 1 : 2;
+    if (MMAX <= 2048) return 4;
+    if (MMAX == 4096) return NT == 512 ? 4 : 3;
+    return NT == 512 ? 2 : 1;
+}
+
 template <typename T, int NT, int MMAX>
-__global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1, const cpx<T>* __restrict__ z2,
+__global__ __launch_bounds__(NT, (blk_waves<T, NT, MMAX>())) void k_align_blk(const cpx<T>* __restrict__ z1, const cpx<T>* __restrict__ z2,
                                                   const int64_t* __restrict__ offsets, int n_uniform,
                                                   int64_t num_pairs, ca_result_t* __restrict__ out,
                                                   const Plan* __restrict__ plans,
@@ -450,8 +459,8 @@ __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1,
                                                   const int* __restrict__ list_count, const int* __restrict__ list) {
     // the plan's twiddles are staged in LDS where the table is small
     constexpr bool kTwLds = MMAX * sizeof(cpx<T>) <= 16384;
+    constexpr int HN = MMAX / NT;        // spectrum values of curve 2 held per thread
     __shared__ cpx<T> A[MMAX];
-    __shared__ cpx<T> B[MMAX];
     __shared__ cpx<T> TWL[kTwLds ? MMAX : 1];
     __shared__ double red[4 * (NT / 64)];
     __shared__ int clist[kCandCap + 1];
@@ -472,33 +481,40 @@ __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1,
         const cpx<T>* tw = arena + p.tw_off;
         if constexpr (kTwLds) {
             for (int k = threadIdx.x; k < M - 1; k += NT) TWL[k] = tw[k];
-            tw = TWL;                        // visible after the barrier of block_sum2 below
+            tw = TWL;                        // first read after the barrier of the first pass
         }
         const cpx<T>* pa = z1 + off;
         const cpx<T>* pb = z2 + off;
         const bool padded = M != n;
         const int base = M - n;              // D index of shift 0
         const int nb = padded ? 2 * n : n;   // extent of b
+        const cpx<T> zero = {T(0), T(0)};
 
-        double q1 = 0.0, q2 = 0.0;
-        for (int k = threadIdx.x; k < M; k += NT) {
-            const cpx<T> zero = {T(0), T(0)};
-            const cpx<T> a = k < n ? pa[k] : zero;
-            const cpx<T> b = k < nb ? pb[k < n ? k : k - n] : zero;
-            A[k] = a;
-            B[k] = b;
-            if (k < n) {
-                q1 = fma((double)a.x, (double)a.x, fma((double)a.y, (double)a.y, q1));
-                q2 = fma((double)b.x, (double)b.x, fma((double)b.y, (double)b.y, q2));
-            }
+        // One signal buffer: the spectrum of b is computed first and held in
+        // registers (thread t keeps entries t + NT i), then the spectrum of a
+        // takes the buffer and is multiplied in place by conj(.) b, then that
+        // product is transformed.  Both first passes read the nodes from
+        // global memory.
+        const double q2 = blk_fft_load<NT, MMAX>(A, p, tw, n, [&](int k) {
+            return k < nb ? pb[k < n ? k : k - n] : zero;
+        });
+        cpx<T> h[HN];
+#pragma unroll
+        for (int i = 0; i < HN; ++i) {
+            const int k = threadIdx.x + i * NT;
+            h[i] = k < M ? A[k] : zero;
         }
-        block_sum2<NT>(q1, q2, red);                    // synchronises
-        const double n1 = q1 / n, n2 = q2 / n;
-        blk_fft2<NT, MMAX>(A, B, p, tw);
-        for (int k = threadIdx.x; k < M; k += NT) A[k] = cjmul(A[k], B[k]);
+        const double q1 = blk_fft_load<NT, MMAX>(A, p, tw, n, [&](int k) { return k < n ? pa[k] : zero; });
+#pragma unroll
+        for (int i = 0; i < HN; ++i) {
+            const int k = threadIdx.x + i * NT;
+            if (k < M) A[k] = cjmul(A[k], h[i]);
+        }
         __syncthreads();
         blk_fft<NT, MMAX>(A, p, tw);
-        for (int k = threadIdx.x; k < n; k += NT) B[k] = pb[k];   // z2 again, for re-scoring
+        double s1 = q1, s2 = q2;
+        block_sum2<NT>(s1, s2, red);
+        const double n1 = s1 / n, n2 = s2 / n;
 
         // largest |D|^2 and runner-up in one scan: per thread the two
         // largest (smallest shift first on equal values), then one reduction
@@ -531,7 +547,7 @@ __global__ __launch_bounds__(NT) void k_align_blk(const cpx<T>* __restrict__ z1,
                 for (int k = threadIdx.x; k < n; k += NT) {
                     int idx = k - c;
                     if (idx < 0) idx += n;
-                    const cpx<T> a = pa[k], b = B[idx];
+                    const cpx<T> a = pa[k], b = pb[idx];
                     const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
                     re = fma(ax, bx, fma(ay, by, re));
                     im = fma(ay, bx, fma(-ax, by, im));
@@ -596,9 +612,10 @@ static hipError_t launch_blk_class(const BlkArgs& a, int cls, hipStream_t s) {
 }
 
 // Size classes by transform size: (64 threads, M <= 512), (128, <= 1024),
-// (256, <= 2048), (256 or, FP32, 512, <= 4096) and, FP32 only, (512 or 256,
-// <= 8192); the FP32 thread counts of the two large classes are tuning choices.  A uniform
-// batch launches its one class; a ragged batch is binned on the device first.
+// (256, <= 2048), (FP32: 512 or 256, FP64: 256, <= 4096) and, FP32 only,
+// (512 or 256, <= 8192); the FP32 thread counts of the two large classes are
+// tuning choices.  A uniform batch launches its one class; a ragged batch is
+// binned on the device first.
 template <typename T>
 static hipError_t launch_blk(const BlkArgs& a, hipStream_t s) {
     const int lo = a.offsets ? 0 : a.m_uniform, hi = a.offsets ? a.m_cap : a.m_uniform;

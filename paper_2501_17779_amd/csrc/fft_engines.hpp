@@ -98,41 +98,28 @@ __device__ __forceinline__ void blk_pass(cpx<T>* buf, int n, int ns, const cpx<T
     }
 }
 
-// The same pass on two buffers, sharing twiddles and barriers.
-template <int R, int NT, int NMAX, typename T>
-__device__ __forceinline__ void blk_pass2(cpx<T>* b1, cpx<T>* b2, int n, int ns, const cpx<T>* __restrict__ tw) {
+// The first pass of a transform (stride 1: no twiddles) with its inputs
+// taken from load(k), 0 <= k < n, instead of the buffer.  Returns the FP64 sum
+// of |x_k|^2 over k < nsum (every input is read exactly once).  Its barrier
+// orders its writes after every earlier read of buf.
+template <int R, int NT, int NMAX, typename T, typename Load>
+__device__ __forceinline__ double blk_pass_first(cpx<T>* buf, int n, int nsum, Load load) {
     constexpr int UM = (NMAX / R + NT - 1) / NT;
     const int nb = n / R;
-    const float inv_ns = 1.0f / (float)ns;
-    int kk[UM];
-    cpx<T> f[UM][R - 1];
-#pragma unroll
-    for (int u = 0; u < UM; ++u) {
-        const int j = threadIdx.x + u * NT;
-        kk[u] = 0;
-        if (j < nb && ns > 1) {
-            kk[u] = mod_small(j, ns, inv_ns);
-#pragma unroll
-            for (int r = 1; r < R; ++r) f[u][r - 1] = tw[(r - 1) * ns + kk[u]];
-        }
-    }
-    __syncthreads();
-    cpx<T> v[UM][R], w[UM][R];
+    cpx<T> v[UM][R];
+    double q = 0.0;
 #pragma unroll
     for (int u = 0; u < UM; ++u) {
         const int j = threadIdx.x + u * NT;
         if (j < nb) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) { v[u][r] = b1[j + r * nb]; w[u][r] = b2[j + r * nb]; }
-            if (ns > 1) {
-#pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    v[u][r] = mul(v[u][r], f[u][r - 1]);
-                    w[u][r] = mul(w[u][r], f[u][r - 1]);
-                }
+            for (int r = 0; r < R; ++r) {
+                const int k = j + r * nb;
+                v[u][r] = load(k);
+                if (k < nsum)
+                    q = fma((double)v[u][r].x, (double)v[u][r].x, fma((double)v[u][r].y, (double)v[u][r].y, q));
             }
             dft<R>(v[u]);
-            dft<R>(w[u]);
         }
     }
     __syncthreads();
@@ -140,12 +127,11 @@ __device__ __forceinline__ void blk_pass2(cpx<T>* b1, cpx<T>* b2, int n, int ns,
     for (int u = 0; u < UM; ++u) {
         const int j = threadIdx.x + u * NT;
         if (j < nb) {
-            const int k = kk[u];
-            const int base = (j - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) { b1[base + r * ns] = v[u][r]; b2[base + r * ns] = w[u][r]; }
+            for (int r = 0; r < R; ++r) buf[j * R + r] = v[u][r];
         }
     }
+    return q;
 }
 
 // Radix 16 is compiled only into the kernels of the large size classes (it
@@ -153,35 +139,12 @@ __device__ __forceinline__ void blk_pass2(cpx<T>* b1, cpx<T>* b2, int n, int ns,
 // transform sizes above kBlkR16Min / 2.
 constexpr int kBlkR16Min = 4096;
 
+// Passes first..npass-1 of a plan, the earlier passes having left stride ns
+// and used the twiddles before tw; ends with a barrier.
 template <int NT, int NMAX, typename T>
-__device__ void blk_fft2(cpx<T>* b1, cpx<T>* b2, const Plan& p, const cpx<T>* __restrict__ tw) {
-    int ns = 1;
-    for (int i = 0; i < p.npass; ++i) {
-        const int r = p.radix[i];
-        switch (r) {
-            case 2: blk_pass2<2, NT, NMAX>(b1, b2, p.n, ns, tw); break;
-            case 3: blk_pass2<3, NT, NMAX>(b1, b2, p.n, ns, tw); break;
-            case 4: blk_pass2<4, NT, NMAX>(b1, b2, p.n, ns, tw); break;
-            case 5: blk_pass2<5, NT, NMAX>(b1, b2, p.n, ns, tw); break;
-            case 7: blk_pass2<7, NT, NMAX>(b1, b2, p.n, ns, tw); break;
-            case 16:
-                if constexpr (NMAX >= kBlkR16Min) {
-                    blk_pass2<16, NT, NMAX>(b1, b2, p.n, ns, tw);
-                    break;
-                }
-                [[fallthrough]];
-            default: blk_pass2<8, NT, NMAX>(b1, b2, p.n, ns, tw); break;
-        }
-        tw += (r - 1) * ns;
-        ns *= r;
-    }
-    __syncthreads();
-}
-
-template <int NT, int NMAX, typename T>
-__device__ void blk_fft(cpx<T>* buf, const Plan& p, const cpx<T>* __restrict__ tw) {
-    int ns = 1;
-    for (int i = 0; i < p.npass; ++i) {
+__device__ __forceinline__ void blk_fft_passes(cpx<T>* buf, const Plan& p, const cpx<T>* __restrict__ tw,
+                                               int first, int ns) {
+    for (int i = first; i < p.npass; ++i) {
         const int r = p.radix[i];
         switch (r) {
             case 2: blk_pass<2, NT, NMAX>(buf, p.n, ns, tw); break;
@@ -201,6 +164,38 @@ __device__ void blk_fft(cpx<T>* buf, const Plan& p, const cpx<T>* __restrict__ t
         ns *= r;
     }
     __syncthreads();
+}
+
+// The transform of the signal in buf, in place; ends with a barrier.
+template <int NT, int NMAX, typename T>
+__device__ __forceinline__ void blk_fft(cpx<T>* buf, const Plan& p, const cpx<T>* __restrict__ tw) {
+    blk_fft_passes<NT, NMAX>(buf, p, tw, 0, 1);
+}
+
+// The transform of the signal load(k), 0 <= k < p.n, into buf: the first
+// pass reads its inputs through load, the others work in place.  Returns the
+// FP64 sum of |x_k|^2 over k < nsum; ends with a barrier.
+template <int NT, int NMAX, typename T, typename Load>
+__device__ __forceinline__ double blk_fft_load(cpx<T>* buf, const Plan& p, const cpx<T>* __restrict__ tw,
+                                               int nsum, Load load) {
+    const int r = p.radix[0];
+    double q;
+    switch (r) {
+        case 2: q = blk_pass_first<2, NT, NMAX, T>(buf, p.n, nsum, load); break;
+        case 3: q = blk_pass_first<3, NT, NMAX, T>(buf, p.n, nsum, load); break;
+        case 4: q = blk_pass_first<4, NT, NMAX, T>(buf, p.n, nsum, load); break;
+        case 5: q = blk_pass_first<5, NT, NMAX, T>(buf, p.n, nsum, load); break;
+        case 7: q = blk_pass_first<7, NT, NMAX, T>(buf, p.n, nsum, load); break;
+        case 16:
+            if constexpr (NMAX >= kBlkR16Min) {
+                q = blk_pass_first<16, NT, NMAX, T>(buf, p.n, nsum, load);
+                break;
+            }
+            [[fallthrough]];
+        default: q = blk_pass_first<8, NT, NMAX, T>(buf, p.n, nsum, load); break;
+    }
+    blk_fft_passes<NT, NMAX>(buf, p, tw + (r - 1), 1, r);
+    return q;
 }
 
 // ------------------------------------------------------------------- team engine
