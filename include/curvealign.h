@@ -337,8 +337,9 @@ ca_status_t ca_graph_destroy(ca_graph_t graph);
  *                           4096, 8192)                     1..8, or 0 for one block per pair
  *                                                           (default 1)
  *   CA_TUNE_BLOCK_THREADS   size class 3 or 4            1: threads per block of the FP32
- *                                                           class kernel, 256 or 512 (default
- *                                                           512 for both; FP64 keeps 256)
+ *                                                           class kernel, 256 or 512 (defaults
+ *                                                           256 for class 3, 512 for class 4;
+ *                                                           FP64 keeps 256)
  *
  * ca_tune_set and ca_tune_load change the tables the kernels read: they
  * synchronise the device first and must not be called while work of this

@@ -457,8 +457,9 @@ __global__ __launch_bounds__(NT, (blk_waves<T, NT, MMAX>())) void k_align_blk(co
                                                   const Plan* __restrict__ plans,
                                                   const cpx<T>* __restrict__ arena, int rescore, int theta64,
                                                   const int* __restrict__ list_count, const int* __restrict__ list) {
-    // the plan's twiddles are staged in LDS where the table is small
-    constexpr bool kTwLds = MMAX * sizeof(cpx<T>) <= 16384;
+    // the plan's twiddles are staged in LDS where the table is small, or
+    // where the registers allow one block per CU anyway
+    constexpr bool kTwLds = MMAX * sizeof(cpx<T>) <= 16384 || blk_waves<T, NT, MMAX>() * 256 / NT <= 1;
     constexpr int HN = MMAX / NT;        // spectrum values of curve 2 held per thread
     __shared__ cpx<T> A[MMAX];
     __shared__ cpx<T> TWL[kTwLds ? MMAX : 1];
@@ -612,9 +613,9 @@ static hipError_t launch_blk_class(const BlkArgs& a, int cls, hipStream_t s) {
 }
 
 // Size classes by transform size: (64 threads, M <= 512), (128, <= 1024),
-// (256, <= 2048), (FP32: 512 or 256, FP64: 256, <= 4096) and, FP32 only,
-// (512 or 256, <= 8192); the FP32 thread counts of the two large classes are
-// tuning choices.  A uniform batch launches its one class; a ragged batch is
+// (256, <= 2048), (256 or, FP32, 512, <= 4096) and, FP32 only, (512 or 256,
+// <= 8192); the FP32 thread counts of the two large classes are tuning
+// choices.  A uniform batch launches its one class; a ragged batch is
 // binned on the device first.
 template <typename T>
 static hipError_t launch_blk(const BlkArgs& a, hipStream_t s) {
