@@ -365,24 +365,13 @@ constexpr int kFtH = kRsW + 1;             // halo on each side (the widest wind
 constexpr int kFtP = kFtK + 2 * kFtH;      // staged knots
 constexpr int kFtSegMax = 24;              // most nodes per lane for lane-owned segments
 // Per-knot LDS arrays are not padded: the local solve and the scan give lane
-// l the knots [7 l, 7 l + 7), a stride coprime to the bank count.  Complex
-// per-knot values are stored as two float planes kFtY apart (real parts,
-// then imaginary parts), so those stride-7 accesses stay one bank per lane
-// (8-byte elements would put two lanes on every bank pair) and each complex
-// value is still one two-address LDS instruction.  The spline moments share
-// the right-hand sides' array (the solve's sweeps read every right-hand side
-// before the back substitution writes a moment), which with 7 knots per lane
-// keeps a wave's LDS at ~12 KB: three waves per SIMD.
+// l the knots [7 l, 7 l + 7), a stride coprime to the bank count.  The
+// spline moments share the right-hand sides' array (the solve's sweeps read
+// every right-hand side before the back substitution writes a moment), which
+// with 7 knots per lane keeps a wave's LDS at ~11 KB: three waves per SIMD.
 constexpr int kFtPP = kFtP;
 constexpr int kFtKP = kFtK + 1;
-constexpr int kFtY = 512;
-static_assert(kFtPP <= kFtY && kFtKP <= kFtY, "plane offset");
 __device__ __forceinline__ int kp(int i) { return i; }
-__device__ __forceinline__ cf lds_get(const float* a, int i) { return {a[i], a[i + kFtY]}; }
-__device__ __forceinline__ void lds_put(float* a, int i, cf v) {
-    a[i] = v.x;
-    a[i + kFtY] = v.y;
-}
 
 __device__ __forceinline__ int wrapm(int i, int m) {
     while (i < 0) i += m;
@@ -436,11 +425,11 @@ __global__ __launch_bounds__(64, 3) void k_resample_fast(const cf* __restrict__ 
                                                       cf* __restrict__ out, double* __restrict__ norms,
                                                       uint32_t* __restrict__ flags, int mode,
                                                       int* __restrict__ slow_count, int* __restrict__ slow_list) {
-    __shared__ float sP[2 * kFtY];
+    __shared__ cf sP[kFtPP];
     __shared__ float sH[kFtPP];
-    __shared__ float sR[2 * kFtY];
+    __shared__ cf sR[kFtPP > kFtKP ? kFtPP : kFtKP];
     __shared__ float sS[kFtKP];
-    float* const sM = sR;                      // moments over the right-hand sides
+    cf* const sM = sR;                         // moments over the right-hand sides
     const int64_t c = blockIdx.x;
     if (c >= num_curves) return;
     const int lane = threadIdx.x;
@@ -554,7 +543,7 @@ __global__ __launch_bounds__(64, 3) void k_resample_fast(const cf* __restrict__ 
                 const cf q = (u + 1 < kStage && lane == 63) ? rot[u + 1 < kStage ? u + 1 : u] : rot[u];
                 const float dx = q.x - pre[u].x, dy = q.y - pre[u].y;
                 const float h = fsqrt(dx * dx + dy * dy);
-                if (kInside || i < kFtP) lds_put(sP, kpl + kp(64 * u), pre[u]);
+                if (kInside || i < kFtP) sP[kpl + kp(64 * u)] = pre[u];
                 if (kInside || i < kFtP - 1) sH[kpl + kp(64 * u)] = h;
                 if constexpr (kSpline) {
                     const float ih = frcp(h);
@@ -562,7 +551,7 @@ __global__ __launch_bounds__(64, 3) void k_resample_fast(const cf* __restrict__ 
                     const cf dr = wave_ror1(d);
                     const cf dm = lane == 0 ? dmprev : dr;
                     if ((u > 0 || i >= 1) && (kInside || i < kFtP - 1))
-                        lds_put(sR, kpl + kp(64 * u), cf{6.0f * (d.x - dm.x), 6.0f * (d.y - dm.y)});
+                        sR[kpl + kp(64 * u)] = {6.0f * (d.x - dm.x), 6.0f * (d.y - dm.y)};
                     dmprev = dr;
                 }
             }
@@ -627,7 +616,7 @@ __global__ __launch_bounds__(64, 3) void k_resample_fast(const cf* __restrict__ 
                 for (int i = 0; i < W + kFtC; ++i) {
                     const int j = i0 - W + i;
                     const float hj = sH[kp(j)];
-                    const cf d = lds_get(sR, kp(j));
+                    const cf d = sR[kp(j)];
                     const float b = 2.0f * (hprev + hj);
                     if (i == 0) {
                         alpha = b;
@@ -647,7 +636,7 @@ __global__ __launch_bounds__(64, 3) void k_resample_fast(const cf* __restrict__ 
                 for (int i = W - 1; i >= 0; --i) {
                     const int j = e + i;
                     const float hj = sH[kp(j)], hjm = sH[kp(j - 1)];
-                    const cf d = lds_get(sR, kp(j));
+                    const cf d = sR[kp(j)];
                     const float b = 2.0f * (hjm + hj);
                     if (i == W - 1) {
                         beta = b;
@@ -671,7 +660,7 @@ __global__ __launch_bounds__(64, 3) void k_resample_fast(const cf* __restrict__ 
                     const float cj = sH[kp(i0 + i)];
                     const float ia = frcp(al[i]);
                     const cf Mi = {(de[i].x - cj * Mn.x) * ia, (de[i].y - cj * Mn.y) * ia};
-                    lds_put(sM, kp(kFtC * lane + i), Mi);
+                    sM[kp(kFtC * lane + i)] = Mi;
                     Mn = Mi;
                 }
             };
@@ -731,10 +720,10 @@ __global__ __launch_bounds__(64, 3) void k_resample_fast(const cf* __restrict__ 
             const float hj = sH[kp(kFtH + j)];
             const float bb = u - sS[kp(j)];
             const float aa = hj - bb;
-            const cf qj = lds_get(sP, kp(kFtH + j)), qp = lds_get(sP, kp(kFtH + j + 1));
+            const cf qj = sP[kp(kFtH + j)], qp = sP[kp(kFtH + j + 1)];
             cf z;
             if (mode == CA_RESAMPLE_SPLINE) {
-                const cf mj = lds_get(sM, kp(j)), mp = lds_get(sM, kp(j + 1));
+                const cf mj = sM[kp(j)], mp = sM[kp(j + 1)];
                 const float ih = frcp(hj);
                 const float ca = aa * aa * aa * ih * (1.0f / 6.0f);
                 const float cb = bb * bb * bb * ih * (1.0f / 6.0f);
