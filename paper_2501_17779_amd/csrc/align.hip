@@ -461,6 +461,7 @@ __global__ __launch_bounds__(NT, (blk_waves<T, NT, MMAX>())) void k_align_blk(co
     // where the registers allow one block per CU anyway
     constexpr bool kTwLds = MMAX * sizeof(cpx<T>) <= 16384 || blk_waves<T, NT, MMAX>() * 256 / NT <= 1;
     constexpr int HN = MMAX / NT;        // spectrum values of curve 2 held per thread
+    constexpr int kRsU = HN < 4 ? HN : 4;  // node pairs per thread in flight in the re-scoring
     __shared__ cpx<T> A[MMAX];
     __shared__ cpx<T> TWL[kTwLds ? MMAX : 1];
     __shared__ double red[4 * (NT / 64)];
@@ -481,7 +482,20 @@ __global__ __launch_bounds__(NT, (blk_waves<T, NT, MMAX>())) void k_align_blk(co
         const Plan& p = plans[n];
         const cpx<T>* tw = arena + p.tw_off;
         if constexpr (kTwLds) {
-            for (int k = threadIdx.x; k < M - 1; k += NT) TWL[k] = tw[k];
+            // four loads in flight per thread, then their stores
+            for (int k0 = 0; k0 < M - 1; k0 += 4 * NT) {
+                cpx<T> tv[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int k = k0 + threadIdx.x + i * NT;
+                    tv[i] = tw[k < M - 1 ? k : 0];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int k = k0 + threadIdx.x + i * NT;
+                    if (k < M - 1) TWL[k] = tv[i];
+                }
+            }
             tw = TWL;                        // first read after the barrier of the first pass
         }
         const cpx<T>* pa = z1 + off;
@@ -497,7 +511,8 @@ __global__ __launch_bounds__(NT, (blk_waves<T, NT, MMAX>())) void k_align_blk(co
         // product is transformed.  Both first passes read the nodes from
         // global memory.
         const double q2 = blk_fft_load<NT, MMAX>(A, p, tw, n, [&](int k) {
-            return k < nb ? pb[k < n ? k : k - n] : zero;
+            const cpx<T> x = pb[k < nb ? (k < n ? k : k - n) : 0];
+            return k < nb ? x : zero;
         });
         cpx<T> h[HN];
 #pragma unroll
@@ -505,7 +520,10 @@ __global__ __launch_bounds__(NT, (blk_waves<T, NT, MMAX>())) void k_align_blk(co
             const int k = threadIdx.x + i * NT;
             h[i] = k < M ? A[k] : zero;
         }
-        const double q1 = blk_fft_load<NT, MMAX>(A, p, tw, n, [&](int k) { return k < n ? pa[k] : zero; });
+        const double q1 = blk_fft_load<NT, MMAX>(A, p, tw, n, [&](int k) {
+            const cpx<T> x = pa[k < n ? k : 0];
+            return k < n ? x : zero;
+        });
 #pragma unroll
         for (int i = 0; i < HN; ++i) {
             const int k = threadIdx.x + i * NT;
@@ -544,14 +562,28 @@ __global__ __launch_bounds__(NT, (blk_waves<T, NT, MMAX>())) void k_align_blk(co
                                 (padded ? 1.4142135623730951 : 1.0);
             Pick pk;
             auto rescore_one = [&](int c) {
+                // kRsU node pairs in flight per thread before their products
+                // (indices past n read node 0 and add zero); the terms are
+                // summed in the order k = t, t + NT, ...
                 double re = 0.0, im = 0.0;
-                for (int k = threadIdx.x; k < n; k += NT) {
-                    int idx = k - c;
-                    if (idx < 0) idx += n;
-                    const cpx<T> a = pa[k], b = pb[idx];
-                    const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
-                    re = fma(ax, bx, fma(ay, by, re));
-                    im = fma(ay, bx, fma(-ax, by, im));
+                for (int k0 = 0; k0 < n; k0 += kRsU * NT) {
+                    cpx<T> av[kRsU], bw[kRsU];
+#pragma unroll
+                    for (int i = 0; i < kRsU; ++i) {
+                        const int k = k0 + threadIdx.x + i * NT;
+                        int idx = k - c;
+                        if (idx < 0) idx += n;
+                        av[i] = pa[k < n ? k : 0];
+                        bw[i] = pb[k < n ? idx : 0];
+                    }
+#pragma unroll
+                    for (int i = 0; i < kRsU; ++i) {
+                        const bool in = k0 + threadIdx.x + i * NT < n;
+                        const double ax = in ? (double)av[i].x : 0.0, ay = in ? (double)av[i].y : 0.0;
+                        const double bx = bw[i].x, by = bw[i].y;
+                        re = fma(ax, bx, fma(ay, by, re));
+                        im = fma(ay, bx, fma(-ax, by, im));
+                    }
                 }
                 block_sum2<NT>(re, im, red);
                 pk.offer(c, re, im);

@@ -99,14 +99,21 @@ __device__ __forceinline__ void blk_pass(cpx<T>* buf, int n, int ns, const cpx<T
 }
 
 // The first pass of a transform (stride 1: no twiddles) with its inputs
-// taken from load(k), 0 <= k < n, instead of the buffer.  Returns the FP64 sum
-// of |x_k|^2 over k < nsum (every input is read exactly once).  Its barrier
-// orders its writes after every earlier read of buf.
+// taken from load(k) instead of the buffer.  load is called for every
+// 0 <= k < UM NT + (R - 1) n / R, branch-free and before any value is used (so
+// all the loads are in flight together); it must accept any such k and return
+// the input x_k for k < n (values for larger k are not used).  Returns the
+// FP64 sum of |x_k|^2 over k < nsum.  Its barrier orders its writes after
+// every earlier read of buf.
 template <int R, int NT, int NMAX, typename T, typename Load>
 __device__ __forceinline__ double blk_pass_first(cpx<T>* buf, int n, int nsum, Load load) {
     constexpr int UM = (NMAX / R + NT - 1) / NT;
     const int nb = n / R;
     cpx<T> v[UM][R];
+#pragma unroll
+    for (int u = 0; u < UM; ++u)
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[u][r] = load((int)threadIdx.x + u * NT + r * nb);
     double q = 0.0;
 #pragma unroll
     for (int u = 0; u < UM; ++u) {
@@ -114,10 +121,9 @@ __device__ __forceinline__ double blk_pass_first(cpx<T>* buf, int n, int nsum, L
         if (j < nb) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const int k = j + r * nb;
-                v[u][r] = load(k);
-                if (k < nsum)
-                    q = fma((double)v[u][r].x, (double)v[u][r].x, fma((double)v[u][r].y, (double)v[u][r].y, q));
+                const double x = v[u][r].x, y = v[u][r].y;
+                const double s = fma(x, x, y * y);
+                q += (j + r * nb < nsum) ? s : 0.0;
             }
             dft<R>(v[u]);
         }
