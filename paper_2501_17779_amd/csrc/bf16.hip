@@ -120,12 +120,17 @@ __device__ __forceinline__ void ops4(const cf (&v)[4], float (&o)[8]) {
 
 // Forward DFT of two pairs' curves (x0: pair 0, x1: pair 1, NULL: zeros).
 __device__ __forceinline__ void fwd128(const cf* x0, const cf* x1, const Bf16Lane& k, int g, int c, cf (&X)[4]) {
-    const cf* x = (c >> 3) ? x1 : x0;
+    // unconditional loads (a missing pair 1 reads pair 0 and is zeroed)
+    const bool zero = (c >> 3) && !x1;
+    const cf* x = ((c >> 3) && x1) ? x1 : x0;
     const int n2 = c & 7;
+    cf lv[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) lv[e] = x[8 * (4 * g + e) + n2];
     float op[8];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const cf v = x ? x[8 * (4 * g + e) + n2] : cf{0.0f, 0.0f};
+        const cf v = zero ? cf{0.0f, 0.0f} : lv[e];
         op[e] = v.x;
         op[4 + e] = v.y;
     }
@@ -159,10 +164,20 @@ __global__ __launch_bounds__(256, 2) void k_align_bf16(const cf* __restrict__ z1
         const bool mine = p == 0 || has1;
         cf a0[4];
         double q1 = 0.0, q2 = 0.0;
+        // loads unconditional (a missing second pair reads the first one's
+        // nodes and zeroes them), so all eight are in flight together
+        const cf* ap = (p && has1) ? a1p : a0p;
+        const cf* bp = (p && has1) ? b1p : b0p;
+        cf la[4], lb[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const cf va = mine ? (p ? a1p : a0p)[t + 32 * q] : cf{0.0f, 0.0f};
-            const cf vb = mine ? (p ? b1p : b0p)[t + 32 * q] : cf{0.0f, 0.0f};
+            la[q] = ap[t + 32 * q];
+            lb[q] = bp[t + 32 * q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const cf va = mine ? la[q] : cf{0.0f, 0.0f};
+            const cf vb = mine ? lb[q] : cf{0.0f, 0.0f};
             a0[q] = va;
             zt[t + 32 * q] = vb;
             zt[kBN + t + 32 * q] = vb;
