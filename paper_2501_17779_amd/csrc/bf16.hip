@@ -54,7 +54,7 @@ __device__ __forceinline__ f32x4 mma(bf16x8 a, bf16x8 b, f32x4 c) {
 }
 
 // ----------------------------------------------------------------- n = 128
-// Two pairs per wave, v_mfma_f32_16x16x32_bf16.  Lane l (g = l / 16, c = l % 16)
+// Two pairs per MFMA group, v_mfma_f32_16x16x32_bf16.  Lane l (g = l / 16, c = l % 16)
 // holds operand A element e as A[c][8 g + e], operand B element e as
 // B[8 g + e][c] and accumulator r as D[4 g + r][c].  K slot (g, e) is read as
 // part e / 4 (real, imaginary) of index 4 g + e % 4 (16-point stages), or of
@@ -78,7 +78,8 @@ __device__ __forceinline__ f32x4 mma(bf16x8 a, bf16x8 b, f32x4 c) {
 // each as a real and an imaginary output block in BF16 hi and lo) are the same
 // registers for all six stages.  D is then written to LDS in natural order and
 // the shared epilogue (candidate window with the split-BF16 error bound,
-// FP64 re-scoring, theta, e0) runs with one team of 32 lanes per pair.
+// FP64 re-scoring, theta, e0) runs with one team of 16 lanes per pair, over
+// the two groups of a wave.
 struct Bf16Lane {
     bf16x8 k1[2][2];   // 16-point matrix: [output part][hi, lo]
     bf16x8 k2[2][2];   // block-diagonal 8-point matrix: [output part][hi, lo]
@@ -119,10 +120,13 @@ __device__ __forceinline__ void ops4(const cf (&v)[4], float (&o)[8]) {
 }
 
 // Forward DFT of two pairs' curves (x0: pair 0, x1: pair 1, NULL: zeros).
-__device__ __forceinline__ void fwd128(const cf* x0, const cf* x1, const Bf16Lane& k, int g, int c, cf (&X)[4]) {
-    // unconditional loads (a missing pair 1 reads pair 0 and is zeroed)
-    const bool zero = (c >> 3) && !x1;
-    const cf* x = ((c >> 3) && x1) ? x1 : x0;
+// The loads are unconditional: a missing curve reads the valid curve `any`
+// and is zeroed.
+__device__ __forceinline__ void fwd128(const cf* x0, const cf* x1, const cf* any, const Bf16Lane& k, int g, int c,
+                                       cf (&X)[4]) {
+    const cf* xs = (c >> 3) ? x1 : x0;
+    const bool zero = !xs;
+    const cf* x = xs ? xs : any;
     const int n2 = c & 7;
     cf lv[4];
 #pragma unroll
@@ -142,73 +146,86 @@ __device__ __forceinline__ void fwd128(const cf* x0, const cf* x1, const Bf16Lan
     stage128<false>(op, k.k2, X);
 }
 
-__global__ __launch_bounds__(256, 2) void k_align_bf16(const cf* __restrict__ z1, const cf* __restrict__ z2,
+// Four pairs per wave: two MFMA groups of two pairs fill the D buffers, then
+// the epilogue runs with one team of 16 lanes per pair, so its reductions
+// span 16 lanes and its per-pair scalar work (square roots, arc tangent, the
+// result) is shared by four pairs.
+constexpr int kBPW = 4;             // pairs per wave
+constexpr int kBT = 64 / kBPW;      // epilogue team
+constexpr int kBR = kBN / kBT;      // values per lane in the epilogue
+
+__global__ __launch_bounds__(256, 3) void k_align_bf16(const cf* __restrict__ z1, const cf* __restrict__ z2,
                                                        int64_t num_pairs, ca_result_t* __restrict__ out,
                                                        const Bf16Lane* __restrict__ cst, int theta64) {
-    __shared__ cf s_zt[4][2][2 * kBN];    // [wave][pair] curve 2's nodes twice (FP64 re-scoring)
-    __shared__ cf s_d[4][2][kBN + 8];     // [wave][pair] D in natural order
-    __shared__ int s_cand[4][2][kCandCap];
+    __shared__ cf s_zt[4][kBPW][2 * kBN];    // [wave][pair] curve 2's nodes twice (FP64 re-scoring)
+    __shared__ cf s_d[4][kBPW][kBN + 8];     // [wave][pair] D in natural order
+    __shared__ int s_cand[4][kBPW][kCandCap];
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c = l & 15;
     const Bf16Lane k = cst[l];
-    const int p = l >> 5, t = l & 31;     // epilogue: team p (pair) of 32 lanes
+    const int p = l / kBT, t = l % kBT;      // epilogue: team p (pair p0 + p)
     cf* zt = s_zt[wv][p];
-    const int64_t groups = (num_pairs + 1) / 2;
+    const int64_t groups = (num_pairs + kBPW - 1) / kBPW;
     for (int64_t grp = (int64_t)blockIdx.x * 4 + wv; grp < groups; grp += (int64_t)gridDim.x * 4) {
-        const int64_t p0 = 2 * grp;
-        const bool has1 = p0 + 1 < num_pairs;
-        const cf* a0p = z1 + p0 * kBN;
-        const cf* b0p = z2 + p0 * kBN;
-        const cf* a1p = has1 ? a0p + kBN : nullptr;
-        const cf* b1p = has1 ? b0p + kBN : nullptr;
-        // the epilogue's team layout: curve 1 in registers, curve 2 twice in LDS
-        const bool mine = p == 0 || has1;
-        cf a0[4];
-        double q1 = 0.0, q2 = 0.0;
-        // loads unconditional (a missing second pair reads the first one's
-        // nodes and zeroes them), so all eight are in flight together
-        const cf* ap = (p && has1) ? a1p : a0p;
-        const cf* bp = (p && has1) ? b1p : b0p;
-        cf la[4], lb[4];
+        const int64_t p0 = kBPW * grp;
+        const int np = (int)(num_pairs - p0 < kBPW ? num_pairs - p0 : kBPW);   // pairs in the group
+        const bool mine = p < np;
+        // the epilogue's team layout: curve 1 in registers, curve 2 twice in
+        // LDS; loads unconditional (a missing pair reads pair p0's nodes and
+        // zeroes them), so all of them are in flight together
+        const int64_t pl = mine ? p0 + p : p0;
+        const cf* ap = z1 + pl * kBN;
+        const cf* bp = z2 + pl * kBN;
+        cf la[kBR], lb[kBR];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            la[q] = ap[t + 32 * q];
-            lb[q] = bp[t + 32 * q];
+        for (int q = 0; q < kBR; ++q) {
+            la[q] = ap[t + kBT * q];
+            lb[q] = bp[t + kBT * q];
         }
+        cf a0[kBR];
+        double q1 = 0.0, q2 = 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < kBR; ++q) {
             const cf va = mine ? la[q] : cf{0.0f, 0.0f};
             const cf vb = mine ? lb[q] : cf{0.0f, 0.0f};
             a0[q] = va;
-            zt[t + 32 * q] = vb;
-            zt[kBN + t + 32 * q] = vb;
+            zt[t + kBT * q] = vb;
+            zt[kBN + t + kBT * q] = vb;
             q1 = fma((double)va.x, (double)va.x, fma((double)va.y, (double)va.y, q1));
             q2 = fma((double)vb.x, (double)vb.x, fma((double)vb.y, (double)vb.y, q2));
         }
-        const double n1 = team_sum<32>(q1) / kBN, n2 = team_sum<32>(q2) / kBN;
-        cf X1[4], X2[4];
-        fwd128(a0p, a1p, k, g, c, X1);
-        fwd128(b0p, b1p, k, g, c, X2);
-        cf Q[4];
+        const double n1 = team_sum<kBT>(q1) / kBN, n2 = team_sum<kBT>(q2) / kBN;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Q[r] = cjmul(X1[r], X2[r]);
-        float op[8];
-        ops4(Q, op);
-        cf u[4];
-        stage128<true>(op, k.k2, u);
+        for (int h = 0; h < kBPW / 2; ++h) {
+            // MFMA group h: pairs p0 + 2 h (rows c < 8) and p0 + 2 h + 1
+            const cf* a0p = 2 * h < np ? z1 + (p0 + 2 * h) * kBN : nullptr;
+            const cf* b0p = 2 * h < np ? z2 + (p0 + 2 * h) * kBN : nullptr;
+            const cf* a1p = 2 * h + 1 < np ? z1 + (p0 + 2 * h + 1) * kBN : nullptr;
+            const cf* b1p = 2 * h + 1 < np ? z2 + (p0 + 2 * h + 1) * kBN : nullptr;
+            cf X1[4], X2[4];
+            fwd128(a0p, a1p, ap, k, g, c, X1);
+            fwd128(b0p, b1p, bp, k, g, c, X2);
+            cf Q[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) u[r] = mul(u[r], k.twt[r]);
-        ops4(u, op);
-        cf D[4];
-        stage128<false>(op, k.k1, D);
-        // D_P[s1 + 8 s2] with P = c / 8, s1 = c % 8, s2 = 4 g + r
+            for (int r = 0; r < 4; ++r) Q[r] = cjmul(X1[r], X2[r]);
+            float op[8];
+            ops4(Q, op);
+            cf u[4];
+            stage128<true>(op, k.k2, u);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) s_d[wv][c >> 3][(c & 7) + 8 * (4 * g + r)] = D[r];
+            for (int r = 0; r < 4; ++r) u[r] = mul(u[r], k.twt[r]);
+            ops4(u, op);
+            cf D[4];
+            stage128<false>(op, k.k1, D);
+            // D_P[s1 + 8 s2] with P = 2 h + c / 8, s1 = c % 8, s2 = 4 g + r
+#pragma unroll
+            for (int r = 0; r < 4; ++r) s_d[wv][2 * h + (c >> 3)][(c & 7) + 8 * (4 * g + r)] = D[r];
+        }
         wave_lds_sync();
-        cf d[4];
+        cf d[kBR];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) d[q] = s_d[wv][p][t + 32 * q];
-        const ca_result_t res = team_epilogue<kBN, 32, kZTwice>(d, a0, zt, s_cand[wv][p], t, n1, n2,
-                                                                CA_RESCORE_WINDOW, theta64, kBf16U);
+        for (int q = 0; q < kBR; ++q) d[q] = s_d[wv][p][t + kBT * q];
+        const ca_result_t res = team_epilogue<kBN, kBT, kZTwice, true>(d, a0, zt, s_cand[wv][p], t, n1, n2,
+                                                                       CA_RESCORE_WINDOW, theta64, kBf16U);
         if (t == 0 && mine) out[p0 + p] = res;
         wave_lds_sync();
     }
@@ -759,7 +776,7 @@ static int bf16_blocks_per_cu() {
 
 hipError_t launch_align_bf16(const void* z1, const void* z2, int64_t num_pairs, ca_result_t* out,
                              const void* lane_consts, int theta64, int num_cus, hipStream_t s) {
-    const int64_t groups = (num_pairs + 1) / 2;
+    const int64_t groups = (num_pairs + kBPW - 1) / kBPW;
     int64_t blocks = (groups + 3) / 4;
     const int64_t cap = (int64_t)num_cus * bf16_blocks_per_cu();
     if (blocks > cap) blocks = cap;

@@ -266,9 +266,12 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
     wave_lds_sync();
     Pick pk;
     int k = 0;
-    if (FUSE2 && cnt >= 2) {
-        // the first two candidates in one pass: curve 1's nodes converted once
-        const int c0 = cand[0], c1 = cand[1];
+    // with FUSE2 the candidates are re-scored two per pass: curve 1's nodes
+    // are converted once per pass and the two dependency chains (candidate
+    // read, node reads, products, team sums) overlap; each candidate's terms
+    // are summed in the same order as alone
+    for (; FUSE2 && k + 1 < cnt; k += 2) {
+        const int c0 = cand[k], c1 = cand[k + 1];
         double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
@@ -286,7 +289,6 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
         im1 = team_sum<T>(im1);
         pk.offer(c0, re0, im0);
         pk.offer(c1, re1, im1);
-        k = 2;
     }
     for (; k < cnt; ++k) {
         const int c = cand[k];
