@@ -88,6 +88,22 @@ def traffic_for(kernel_key: str, digest: str, per_launch_units: float):
     return float(e["bytes_per_unit"]) * per_launch_units
 
 
+def valu_issue_for(kernel_key: str, digest: str, per_launch_units: float, ms: float):
+    """Fraction of the VALU issue cycles the kernel's wave instructions fill
+    over a launch of ms milliseconds: VALU wave instructions per unit from the
+    committed counter summary (taken on the current sources, else None) x 4
+    cycles, over 1024 SIMDs at the nominal 2.4 GHz."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    e = d.get(kernel_key)
+    if not e or e.get("sources") != digest or "valu_per_unit" not in e:
+        return None
+    return float(e["valu_per_unit"]) * per_launch_units * 4.0 / (ms * 1e-3 * 2.4e9 * 1024)
+
+
 def graphed(fn, torch):
     """Capture one call of fn (its kernel launches) in a HIP graph; returns a
     replay function.  The first eager call builds the library's tables."""
@@ -281,7 +297,8 @@ def bench_batch(args, torch, ca):
         "config": {"workload": "batch of 65536 curve pairs, n=1024 nodes, FP32, top-2 FP64 re-scoring",
                    "pairs": B, "n": n, "rescore": "top2"},
         "roofline": {"bound": "hbm", "kernel": "k_align_team<1024>", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "valu_issue": valu_issue_for("k_align_team_1024", sources_digest(ALIGN_SOURCES), B, ms)},
     }
     # the same inputs through the split-BF16 MFMA path (the metric's second half)
     res32 = ca.to_numpy(out)
@@ -372,7 +389,8 @@ def bench_allpairs(args, torch, ca):
     traffic = traffic_for("k_allpairs_512", sources_digest(ALIGN_SOURCES), P)
     line["roofline"] = {"bound": "alu", "kernel": "k_allpairs<512>", "achieved": achieved,
                         "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": achieved / VALU_FP32_PEAK_TFLOPS, "traffic": traffic}
+                        "frac": achieved / VALU_FP32_PEAK_TFLOPS, "traffic": traffic,
+                        "valu_issue": valu_issue_for("k_allpairs_512", sources_digest(ALIGN_SOURCES), P, ms)}
     if not args.no_cpu_baseline:
         gh = g.cpu().numpy()
         ii, jj = np.triu_indices(M, 1)
@@ -436,7 +454,9 @@ def bench_ragged(args, torch, ca, snap=True):
     traffic = traffic_for("k_resample_fast", sources_digest(["resample.hip", "common.hpp"]), 1.0)
     line["roofline"] = {"bound": "hbm", "kernel": "k_resample_fast", "achieved": achieved,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                        "traffic": traffic}
+                        "traffic": traffic,
+                        "valu_issue": valu_issue_for("k_resample_fast", sources_digest(["resample.hip", "common.hpp"]),
+                                                     1.0, ms_rs) if snap else None}
     return line
 
 
@@ -506,7 +526,9 @@ def bench_small_batch(args, torch, ca):
     line["speedup_vs_fp32"] = ms32 / ms16
     traffic = traffic_for("k_align_bf16", sources_digest(["bf16.hip"] + ALIGN_SOURCES[1:]), B)
     line["roofline"] = {"bound": "mfma", "kernel": "k_align_bf16", "achieved": achieved, "peak": 2500.0,
-                        "unit": "TFLOP/s", "frac": achieved / 2500.0, "traffic": traffic}
+                        "unit": "TFLOP/s", "frac": achieved / 2500.0, "traffic": traffic,
+                        "valu_issue": valu_issue_for("k_align_bf16", sources_digest(["bf16.hip"] + ALIGN_SOURCES[1:]),
+                                                     B, ms16)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_batch(lambda k: (r1[:k].cpu().numpy(), r2[:k].cpu().numpy()), B, n,
                                                   args.cpu_seconds)
@@ -545,7 +567,8 @@ def bench_srv(args, torch, ca):
     achieved = algo / (ms_al * 1e-3) / 1e9
     line["roofline"] = {"bound": "hbm", "kernel": "k_align_team<1024>", "achieved": achieved,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                        "traffic": traffic_for("k_align_team_1024", sources_digest(ALIGN_SOURCES), B)}
+                        "traffic": traffic_for("k_align_team_1024", sources_digest(ALIGN_SOURCES), B),
+                        "valu_issue": valu_issue_for("k_align_team_1024", sources_digest(ALIGN_SOURCES), B, ms_al)}
     srv_gbs = 2 * B * n * 16 / (ms_srv * 1e-3) / 1e9
     line["srv_roofline"] = {"bound": "hbm", "kernel": "k_srv", "achieved": srv_gbs, "peak": HBM_PEAK_GBS,
                             "unit": "GB/s", "frac": srv_gbs / HBM_PEAK_GBS,
