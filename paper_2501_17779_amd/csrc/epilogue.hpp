@@ -157,17 +157,10 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
         re = team_sum<T>(re);
         im = team_sum<T>(im);
     };
-    // the path's own C at the chosen shift: arg C = atan2(-Im D, Re D)
-    auto theta_at = [&](int shift) {
-        const int qs = shift / T, ls = shift % T;
-        cf sel = d[0];
-#pragma unroll
-        for (int q = 1; q < R; ++q)
-            if (q == qs) sel = d[q];
-        sel.x = __shfl(sel.x, ls, T);
-        sel.y = __shfl(sel.y, ls, T);
-        return (double)wrap_pi(atan2f(-sel.y, sel.x));
-    };
+    // theta in FP32 from the FP64 re-scored C at the chosen shift (every lane
+    // holds it: no selection of the transform's value across registers and
+    // lanes, and no less accurate than arg of the transform's C)
+    auto theta_of = [](const Pick& pk) { return (double)wrap_pi(atan2f((float)pk.im, (float)pk.re)); };
 
     ca_result_t res;
     if (OWN_N1 && rescore != CA_RESCORE_WINDOW) {
@@ -196,7 +189,7 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
             dot64(ci, re, im);
             pk.offer(ci, re, im);
         }
-        finish(res, pk, N, n1, n2, d1, d2, epsD, false, theta_at(pk.shift), theta64);
+        finish(res, pk, N, n1, n2, d1, d2, epsD, false, theta_of(pk), theta64);
         return res;
     }
     if (OWN_N1) {
@@ -297,7 +290,7 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
         pk.offer(c, re, im);
     }
     wave_lds_sync();
-    finish(res, pk, N, n1, n2, d1, d2, epsD, capped, theta_at(pk.shift), theta64);
+    finish(res, pk, N, n1, n2, d1, d2, epsD, capped, theta_of(pk), theta64);
     return res;
 }
 
