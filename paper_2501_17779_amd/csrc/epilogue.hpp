@@ -248,16 +248,22 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
             }
         }
     }
+    Pick pk;
     if (rescore != CA_RESCORE_WINDOW || cnt == 0) {
-        const int ci = two ? runner_up() : bi;
-        if (t == 0) {
-            cand[0] = bi;
-            cand[1] = ci;
+        // top two: the best shift, and the runner-up when the two are within
+        // the bound; both are team-uniform, so no candidate list is needed
+        double re, im;
+        dot64(bi, re, im);
+        pk.offer(bi, re, im);
+        if (two) {
+            const int ci = runner_up();
+            dot64(ci, re, im);
+            pk.offer(ci, re, im);
         }
-        cnt = two ? 2 : 1;
+        finish(res, pk, N, n1, n2, d1, d2, epsD, capped, theta_of(pk), theta64);
+        return res;
     }
     wave_lds_sync();
-    Pick pk;
     int k = 0;
     // with FUSE2 the candidates are re-scored two per pass: curve 1's nodes
     // are converted once per pass and the two dependency chains (candidate
