@@ -218,6 +218,24 @@ def test_theta_from_fp64(ca):
     acc.check_batch(res, z1, z2, theta_tol=1e-6)
 
 
+@pytest.mark.parametrize("n", [128, 1024])
+@pytest.mark.parametrize("rescore", ["top2", "window"])
+def test_team_theta_from_rescored_c(ca, n, rescore):
+    """The team kernels take theta as an FP32 arc tangent of the FP64 re-scored
+    C at the chosen shift: same shift as the FP64-theta run, angle within FP32
+    rounding of the FP64 arc tangent (C's parts rounded to FP32: ~6e-8 rad,
+    atan2f's error a few ulps more)."""
+    z1, z2 = inputs.batch(48 + n, 64, n)
+    a = run_batch(ca, z1, z2, rescore=rescore)
+    b = run_batch(ca, z1, z2, rescore=rescore, theta_fp64=True)
+    assert np.array_equal(a["shift"], b["shift"])
+    assert np.all(b["flags"] & ca.FLAG_THETA_FP64) and not np.any(a["flags"] & ca.FLAG_THETA_FP64)
+    d = np.abs(np.angle(np.exp(1j * (a["theta"] - b["theta"]))))
+    note(f"n={n} {rescore}: max |theta - theta_fp64| = {d.max():.3g}")
+    assert d.max() < 5e-7
+    assert np.array_equal(a["e0"], b["e0"])
+
+
 def test_determinism(ca):
     z1, z2 = inputs.batch(47, 256, 1024)
     a = run_batch(ca, z1, z2)
