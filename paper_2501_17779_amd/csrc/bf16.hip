@@ -376,17 +376,26 @@ __device__ __forceinline__ int node1k(int q, int e, int h, int c) {
 }
 
 // Forward DFT of 1024 nodes: returns X[c + 32 row(g, h)] in (acc[0][g], acc[1][g]).
-__device__ __forceinline__ void fwd1k(const cf* __restrict__ x, const bf16x8 (&K)[2][3][2], const float4* tws,
-                                      int l, f32x16 (&acc)[2]) {
+// A lane's nodes for the first stage: slot 8 q + e holds node node1k(q, e, h, c).
+__device__ __forceinline__ void load1k(const cf* __restrict__ x, int l, cf (&v)[16]) {
     const int h = l >> 5, c = l & 31;
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[8 * q + e] = x[node1k(q, e, h, c)];
+}
+
+// Forward DFT of 1024 nodes (a lane's slots from load1k): returns
+// X[c + 32 row(g, h)] in (acc[0][g], acc[1][g]).
+__device__ __forceinline__ void fwd1k(const cf (&v)[16], const bf16x8 (&K)[2][3][2], const float4* tws, int l,
+                                      f32x16 (&acc)[2]) {
     float op[4][8];
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const cf v = x[node1k(q, e, h, c)];
-            op[q][e] = v.x;
-            op[2 + q][e] = v.y;
+            op[q][e] = v[8 * q + e].x;
+            op[2 + q][e] = v[8 * q + e].y;
         }
     dft32_stage<true>(op, K, acc);
     twiddle_to_ops(acc, tws, l, op);
@@ -423,16 +432,22 @@ __global__ __launch_bounds__(256, 2) void k_align_bf16_1k(const cf* __restrict__
             for (int k = 0; k < 3; ++k)
 #pragma unroll
                 for (int u = 0; u < 2; ++u) K[q][k][u] = kl->k[q][k][u];
-        // curve 2's nodes twice in LDS for the shifted FP64 reads
+        // both curves' nodes requested together; curve 2's also go twice to
+        // LDS for the shifted FP64 reads
+        cf xa[16], xb[16];
+        load1k(pa, l, xa);
+        load1k(pb, l, xb);
 #pragma unroll
-        for (int i = 0; i < kB1k / 64; ++i) {
-            const cf v = pb[l + 64 * i];
-            zt[l + 64 * i] = v;
-            zt[kB1k + l + 64 * i] = v;
-        }
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int node = node1k(q, e, h, c);
+                zt[node] = xb[8 * q + e];
+                zt[kB1k + node] = xb[8 * q + e];
+            }
         f32x16 X1[2], acc[2];
-        fwd1k(pa, K, s_tw, l, X1);
-        fwd1k(pb, K, s_tw, l, acc);
+        fwd1k(xa, K, s_tw, l, X1);
+        fwd1k(xb, K, s_tw, l, acc);
         // P = conj(X1) X2 as the correlation transform's first operands
         float op[4][8];
 #pragma unroll
@@ -444,6 +459,10 @@ __global__ __launch_bounds__(256, 2) void k_align_bf16_1k(const cf* __restrict__
         dft32_stage<true>(op, K, acc);
         twiddle_to_ops(acc, s_tw, l, op);
         dft32_stage<false>(op, K, acc);
+        // curve 1 again (its nodes in the first stage's slots) for the FP64
+        // sums, requested before the peak search so the loads overlap it
+        cf a0[16];
+        load1k(pa, l, a0);
         // acc[.][g] = D[s] = n conj C(s), s = c + 32 row(g, h)
         auto yat = [&](int g) { return acc[0][g] * acc[0][g] + acc[1][g] * acc[1][g]; };
         float bvl = -1.0f;
@@ -484,12 +503,6 @@ __global__ __launch_bounds__(256, 2) void k_align_bf16_1k(const cf* __restrict__
         float v = cco < 0.0f ? -bco / (2.0f * cco) : 0.0f;
         if (!(fabsf(v) <= 0.5f * kLocalW)) v = 0.0f;
         int sc = (sb + (int)rintf(v)) & (kB1k - 1);
-        // reload curve 1 (its nodes in the first stage's slots) for the FP64 sums
-        cf a0[16];
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int e = 0; e < 8; ++e) a0[8 * q + e] = pa[node1k(q, e, h, c)];
         wave_lds_sync();
         // FP64 C at sc - 1, sc, sc + 1 (times n), curve norms in the same pass
         double cre[3] = {0.0, 0.0, 0.0}, cim[3] = {0.0, 0.0, 0.0}, q1 = 0.0, q2 = 0.0;
