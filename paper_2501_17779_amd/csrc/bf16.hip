@@ -119,24 +119,28 @@ __device__ __forceinline__ void ops4(const cf (&v)[4], float (&o)[8]) {
     }
 }
 
-// Forward DFT of two pairs' curves (x0: pair 0, x1: pair 1, NULL: zeros).
-// The loads are unconditional: a missing curve reads the valid curve `any`
-// and is zeroed.
-__device__ __forceinline__ void fwd128(const cf* x0, const cf* x1, const cf* any, const Bf16Lane& k, int g, int c,
-                                       cf (&X)[4]) {
+// A lane's first-stage nodes of two pairs' curves (x0: pair 0, x1: pair 1,
+// NULL: zeros).  The loads are unconditional: a missing curve reads the valid
+// curve `any` and is zeroed.
+__device__ __forceinline__ void load128(const cf* x0, const cf* x1, const cf* any, int g, int c, cf (&lv)[4]) {
     const cf* xs = (c >> 3) ? x1 : x0;
-    const bool zero = !xs;
     const cf* x = xs ? xs : any;
     const int n2 = c & 7;
-    cf lv[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) lv[e] = x[8 * (4 * g + e) + n2];
+    if (!xs) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) lv[e] = cf{0.0f, 0.0f};
+    }
+}
+
+// Forward DFT of two pairs' curves from the nodes load128 gave.
+__device__ __forceinline__ void fwd128(const cf (&lv)[4], const Bf16Lane& k, cf (&X)[4]) {
     float op[8];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const cf v = zero ? cf{0.0f, 0.0f} : lv[e];
-        op[e] = v.x;
-        op[4 + e] = v.y;
+        op[e] = lv[e].x;
+        op[4 + e] = lv[e].y;
     }
     cf y[4];
     stage128<true>(op, k.k1, y);
@@ -181,6 +185,17 @@ __global__ __launch_bounds__(256, 3) void k_align_bf16(const cf* __restrict__ z1
             la[q] = ap[t + kBT * q];
             lb[q] = bp[t + kBT * q];
         }
+        // the transforms' operands of both MFMA groups, requested with them
+        cf x1v[kBPW / 2][4], x2v[kBPW / 2][4];
+#pragma unroll
+        for (int h = 0; h < kBPW / 2; ++h) {
+            const cf* a0p = 2 * h < np ? z1 + (p0 + 2 * h) * kBN : nullptr;
+            const cf* b0p = 2 * h < np ? z2 + (p0 + 2 * h) * kBN : nullptr;
+            const cf* a1p = 2 * h + 1 < np ? z1 + (p0 + 2 * h + 1) * kBN : nullptr;
+            const cf* b1p = 2 * h + 1 < np ? z2 + (p0 + 2 * h + 1) * kBN : nullptr;
+            load128(a0p, a1p, ap, g, c, x1v[h]);
+            load128(b0p, b1p, bp, g, c, x2v[h]);
+        }
         cf a0[kBR];
         double q1 = 0.0, q2 = 0.0;
 #pragma unroll
@@ -197,13 +212,9 @@ __global__ __launch_bounds__(256, 3) void k_align_bf16(const cf* __restrict__ z1
 #pragma unroll
         for (int h = 0; h < kBPW / 2; ++h) {
             // MFMA group h: pairs p0 + 2 h (rows c < 8) and p0 + 2 h + 1
-            const cf* a0p = 2 * h < np ? z1 + (p0 + 2 * h) * kBN : nullptr;
-            const cf* b0p = 2 * h < np ? z2 + (p0 + 2 * h) * kBN : nullptr;
-            const cf* a1p = 2 * h + 1 < np ? z1 + (p0 + 2 * h + 1) * kBN : nullptr;
-            const cf* b1p = 2 * h + 1 < np ? z2 + (p0 + 2 * h + 1) * kBN : nullptr;
             cf X1[4], X2[4];
-            fwd128(a0p, a1p, ap, k, g, c, X1);
-            fwd128(b0p, b1p, bp, k, g, c, X2);
+            fwd128(x1v[h], k, X1);
+            fwd128(x2v[h], k, X2);
             cf Q[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) Q[r] = cjmul(X1[r], X2[r]);
