@@ -48,19 +48,13 @@ __global__ __launch_bounds__(256, 2) void k_align_team(const cf* __restrict__ z1
         cf v[R], w[R], a0[R], b0[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) { v[q] = pa[t + T * q]; w[q] = pb[t + T * q]; }
-        // n2 here; n1 in the epilogue, which converts curve 1's nodes anyway
-        double q2 = 0.0;
+        // both norms in the epilogue, which converts both curves' nodes anyway
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-            a0[q] = v[q]; b0[q] = w[q];
-            const double bx = w[q].x, by = w[q].y;
-            q2 = fma(bx, bx, fma(by, by, q2));
-        }
+        for (int q = 0; q < R; ++q) { a0[q] = v[q]; b0[q] = w[q]; }
         team_fft2<N, T>(v, w, lds, tws, t);
 #pragma unroll
         for (int q = 0; q < R; ++q) v[q] = cjmul(v[q], w[q]);
         team_fft<N, T>(v, lds, tws, t);
-        const double n2 = team_sum<T>(q2) / N;
         // z2 nodes, twice, for the shifted FP64 dot products
 #pragma unroll
         for (int q = 0; q < R; ++q) {
@@ -68,7 +62,7 @@ __global__ __launch_bounds__(256, 2) void k_align_team(const cf* __restrict__ z1
             lds[N + t + T * q] = b0[q];
         }
         wave_lds_sync();
-        const ca_result_t res = team_epilogue<N, T, kZTwice, true, true>(v, a0, lds, cand, t, 0.0, n2, rescore, theta64);
+        const ca_result_t res = team_epilogue<N, T, kZTwice, true, true>(v, a0, lds, cand, t, 0.0, 0.0, rescore, theta64);
         if (t == 0) out[pair] = res;
         wave_lds_sync();
     }

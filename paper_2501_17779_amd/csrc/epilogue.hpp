@@ -96,12 +96,13 @@ enum { kZPad = 0, kZTwice = 1 };
 // Epilogue of one pair held by a team: d[q] = D[t + T q] (D = n conj C),
 // a0[q] = z1[t + T q] (FP32 nodes of curve 1), zb = LDS copy of curve 2's
 // nodes in layout ZL, cand = the team's candidate list in LDS.
-// With OWN_N1 the n1 argument is ignored and n1 = (1/n) sum |z1|^2 is formed
-// here from a0: under the top-two rule in the pass that re-scores the best
-// shift, whose FP64 conversions of curve 1's nodes it shares (same terms in
-// the same order as a separate pass, so the same value).
+// With OWN_NORMS the n1 and n2 arguments are ignored and n1 = (1/n) sum |z1|^2
+// and n2 = (1/n) sum |z2|^2 are formed here: under the top-two rule in the
+// pass that re-scores the best shift, whose FP64 conversions of both curves'
+// nodes they share (n2 then sums curve 2's nodes in the shifted order that
+// pass reads them).
 // Returns the finished result (every lane).
-template <int N, int T, int ZL = kZPad, bool FUSE2 = false, bool OWN_N1 = false>
+template <int N, int T, int ZL = kZPad, bool FUSE2 = false, bool OWN_NORMS = false>
 __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const cf (&a0)[N / T],
                                                      const cf* zb, int* cand, int t, double n1, double n2,
                                                      int rescore, int theta64,
@@ -163,21 +164,23 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
     auto theta_of = [](const Pick& pk) { return (double)wrap_pi(atan2f((float)pk.im, (float)pk.re)); };
 
     ca_result_t res;
-    if (OWN_N1 && rescore != CA_RESCORE_WINDOW) {
-        // top-two rule: the best shift is re-scored before n1 is needed, and
-        // the same pass sums |z1|^2
-        double re = 0.0, im = 0.0, s1 = 0.0;
+    if (OWN_NORMS && rescore != CA_RESCORE_WINDOW) {
+        // top-two rule: the best shift is re-scored before the norms are
+        // needed, and the same pass sums |z1|^2 and |z2|^2
+        double re = 0.0, im = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             const cf zz = zat(bi, q);
             const double ax = a0[q].x, ay = a0[q].y, bx = zz.x, by = zz.y;
             s1 = fma(ax, ax, fma(ay, ay, s1));
+            s2 = fma(bx, bx, fma(by, by, s2));
             re = fma(ax, bx, fma(ay, by, re));
             im = fma(ay, bx, fma(-ax, by, im));
         }
         re = team_sum<T>(re);
         im = team_sum<T>(im);
         n1 = team_sum<T>(s1) / N;
+        n2 = team_sum<T>(s2) / N;
         if (special_case(res, n1, n2, (double)bv)) return res;
         const double d1 = (double)__builtin_amdgcn_sqrtf(bv), d2 = (double)__builtin_amdgcn_sqrtf(fmaxf(cv, 0.0f));
         const double epsD = (double)((float)(kErrScale * err_u * (double)ilog2_ceil(N) * N * N) *
@@ -192,14 +195,17 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
         finish(res, pk, N, n1, n2, d1, d2, epsD, false, theta_of(pk), theta64);
         return res;
     }
-    if (OWN_N1) {
-        double s1 = 0.0;
+    if (OWN_NORMS) {
+        double s1 = 0.0, s2 = 0.0;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            const double ax = a0[q].x, ay = a0[q].y;
+            const cf zz = zat(0, q);
+            const double ax = a0[q].x, ay = a0[q].y, bx = zz.x, by = zz.y;
             s1 = fma(ax, ax, fma(ay, ay, s1));
+            s2 = fma(bx, bx, fma(by, by, s2));
         }
         n1 = team_sum<T>(s1) / N;
+        n2 = team_sum<T>(s2) / N;
     }
     if (special_case(res, n1, n2, (double)bv)) return res;
     // |D| of the best and runner-up and the error bound only steer the choice
