@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256, 3) void k_align_bf16(const cf* __restrict__ z1
         cf d[kBR];
 #pragma unroll
         for (int q = 0; q < kBR; ++q) d[q] = s_d[wv][p][t + kBT * q];
-        const ca_result_t res = team_epilogue<kBN, kBT, kZTwice, true>(d, a0, zt, s_cand[wv][p], t, n1, n2,
+        const ca_result_t res = team_epilogue<kBN, kBT, kZTwice, true, false, true>(d, a0, zt, s_cand[wv][p], t, n1, n2,
                                                                        CA_RESCORE_WINDOW, theta64, kBf16U);
         if (t == 0 && mine) out[p0 + p] = res;
         wave_lds_sync();

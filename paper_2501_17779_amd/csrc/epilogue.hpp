@@ -102,7 +102,7 @@ enum { kZPad = 0, kZTwice = 1 };
 // nodes they share (n2 then sums curve 2's nodes in the shifted order that
 // pass reads them).
 // Returns the finished result (every lane).
-template <int N, int T, int ZL = kZPad, bool FUSE2 = false, bool OWN_NORMS = false>
+template <int N, int T, int ZL = kZPad, bool FUSE2 = false, bool OWN_NORMS = false, bool PRUNE = false>
 __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const cf (&a0)[N / T],
                                                      const cf* zb, int* cand, int t, double n1, double n2,
                                                      int rescore, int theta64,
@@ -218,7 +218,8 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
 
     // candidate list (team-uniform order: by register, then by lane)
     int cnt = 0;
-    bool capped = false;
+    bool capped = false, pruned = false;
+    Pick pk;
     if (rescore == CA_RESCORE_WINDOW) {
         const double thr = d1 - 2.0 * epsD;
         float thr2 = thr > 0.0 ? (float)(thr * thr) : 0.0f;
@@ -240,6 +241,43 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
             }
             thr2 = hi;
         }
+        int skip0 = -1, skip1 = -1, skip2 = -1;
+        if constexpr (PRUNE) {
+            // The argmax and its two neighbours in one FP64 pass, then only
+            // the window shifts whose bound |D| + epsD can still reach the
+            // best n |C| found (less the near-tie gap) are re-scored: a shift
+            // left out is strictly below the final best and cannot be within
+            // the near-tie gap of it, so the choice is the full window's.
+            const int cm = (bi + N - 1) & (N - 1), cp = (bi + 1) & (N - 1);
+            double r0 = 0.0, j0 = 0.0, r1 = 0.0, j1 = 0.0, r2 = 0.0, j2 = 0.0;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const cf u = zat(cm, q), w = zat(bi, q), x = zat(cp, q);
+                const double ax = a0[q].x, ay = a0[q].y;
+                const double ux = u.x, uy = u.y, wx = w.x, wy = w.y, xx = x.x, xy = x.y;
+                r0 = fma(ax, ux, fma(ay, uy, r0));
+                j0 = fma(ay, ux, fma(-ax, uy, j0));
+                r1 = fma(ax, wx, fma(ay, wy, r1));
+                j1 = fma(ay, wx, fma(-ax, wy, j1));
+                r2 = fma(ax, xx, fma(ay, xy, r2));
+                j2 = fma(ay, xx, fma(-ax, xy, j2));
+            }
+            r0 = team_sum<T>(r0);
+            j0 = team_sum<T>(j0);
+            r1 = team_sum<T>(r1);
+            j1 = team_sum<T>(j1);
+            r2 = team_sum<T>(r2);
+            j2 = team_sum<T>(j2);
+            pk.offer(cm, r0, j0);
+            pk.offer(bi, r1, j1);
+            pk.offer(cp, r2, j2);
+            const double tD = (double)N * sqrt(pk.best) * (1.0 - 2.0 * kNearTie) - epsD;
+            if (tD > 0.0) thr2 = fmaxf(thr2, (float)(tD * tD));
+            skip0 = cm;
+            skip1 = bi;
+            skip2 = cp;
+            pruned = true;
+        }
         {
             const int lane = threadIdx.x & 63;
             const int base = lane - t;
@@ -247,15 +285,15 @@ __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const
             const uint64_t below = (1ull << lane) - 1ull;
 #pragma unroll
             for (int q = 0; q < R; ++q) {
-                const bool hit = m2[q] >= thr2;
+                const int sq = t + T * q;
+                const bool hit = m2[q] >= thr2 && sq != skip0 && sq != skip1 && sq != skip2;
                 const uint64_t msk = __ballot(hit) & tmask;
-                if (hit) cand[cnt + __popcll(msk & below)] = t + T * q;
+                if (hit) cand[cnt + __popcll(msk & below)] = sq;
                 cnt += __popcll(msk);
             }
         }
     }
-    Pick pk;
-    if (rescore != CA_RESCORE_WINDOW || cnt == 0) {
+    if ((rescore != CA_RESCORE_WINDOW || cnt == 0) && !pruned) {
         // top two: the best shift, and the runner-up when the two are within
         // the bound; both are team-uniform, so no candidate list is needed
         double re, im;
