@@ -99,11 +99,16 @@ def test_bf16_1024_exact_copies_protocol_and_flags(ca):
     assert np.isnan(res["e0"][4])
 
 
+@pytest.mark.parametrize("n", [128, 1024])
 @pytest.mark.parametrize("shape", ["circle", "three_fold", "four_fold"])
-def test_bf16_1024_symmetric_curves(ca, shape):
+def test_bf16_symmetric_curves(ca, shape, n):
+    """Symmetric shapes: at n = 128 the pruned window keeps far peaks of
+    nearly equal height (three- and four-fold) and handles a window wider
+    than the candidate cap (the circle); at n = 1024 the separate-peak and
+    segment searches."""
     import test_gpu_ties as ties
-    z1, z2 = ties.pairs(shape, 1024, np.complex64)
-    note(f"split_bf16 ties {shape} n=1024")
+    z1, z2 = ties.pairs(shape, n, np.complex64)
+    note(f"split_bf16 ties {shape} n={n}")
     res = ca.to_numpy(ca.align_batch(torch.from_numpy(z1).cuda(), torch.from_numpy(z2).cuda(),
                                      precision="split_bf16"))
     for b in range(len(res)):
