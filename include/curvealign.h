@@ -65,11 +65,11 @@ enum {
 typedef struct {
     int32_t shift;    /* optimal correlation shift s* in [0, n)                      */
     uint32_t flags;   /* CA_FLAG_* bits                                              */
-    double theta;     /* arg C(s*), radians in (-pi, pi]: unless theta_fp64 is set,
-                         an FP32 arc tangent of the FP64 re-scored C(s*) (uniform
-                         FP32 batches and all pairs with n = 64, 128, ..., 1024;
-                         split-BF16 n = 128) or of the path's own C (every other
-                         FP32 or FP64 call, split-BF16 n = 1024)                       */
+    double theta;     /* arg C(s*), radians in (-pi, pi]: the arc tangent of the
+                         FP64 re-scored C(s*), taken in FP32 on the FP32 and
+                         split-BF16 n = 128 paths and in FP64 on the FP64 path or
+                         when theta_fp64 is set; split-BF16 n = 1024 takes it in
+                         FP32 from its own C unless theta_fp64 is set                 */
     double e0;        /* n1 + n2 - 2|C(s*)|/n with |C(s*)| and n_i in FP64           */
     float err_est;    /* relative half-width of the path's |C| error bound at s*     */
     float gap;        /* (|C|best - |C|runner-up) / |C|best, FP64 values when more

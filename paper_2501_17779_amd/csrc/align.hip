@@ -525,10 +525,6 @@ __global__ __launch_bounds__(NT, (blk_waves<T, NT, MMAX>())) void k_align_blk(co
         }
         __syncthreads();
         blk_fft<NT, MMAX>(A, p, tw);
-        double s1 = q1, s2 = q2;
-        block_sum2<NT>(s1, s2, red);
-        const double n1 = s1 / n, n2 = s2 / n;
-
         // largest |D|^2 and runner-up in one scan: per thread the two
         // largest (smallest shift first on equal values), then one reduction
         T b1 = T(-1), b2 = T(-1);
@@ -545,6 +541,40 @@ __global__ __launch_bounds__(NT, (blk_waves<T, NT, MMAX>())) void k_align_blk(co
         int bi, ci;
         block_top2<NT>(b1, i1, b2, i2, bv, bi, cv, ci, red);
 
+        // this thread's part of the FP64 C at shift c (times n): kRsU node
+        // pairs in flight per thread before their products (indices past n
+        // read node 0 and add zero); the terms are summed in the order
+        // k = t, t + NT, ...
+        auto dot_part = [&](int c, double& re, double& im) {
+            re = 0.0;
+            im = 0.0;
+            for (int k0 = 0; k0 < n; k0 += kRsU * NT) {
+                cpx<T> av[kRsU], bw[kRsU];
+#pragma unroll
+                for (int i = 0; i < kRsU; ++i) {
+                    const int k = k0 + threadIdx.x + i * NT;
+                    int idx = k - c;
+                    if (idx < 0) idx += n;
+                    av[i] = pa[k < n ? k : 0];
+                    bw[i] = pb[k < n ? idx : 0];
+                }
+#pragma unroll
+                for (int i = 0; i < kRsU; ++i) {
+                    const bool in = k0 + threadIdx.x + i * NT < n;
+                    const double ax = in ? (double)av[i].x : 0.0, ay = in ? (double)av[i].y : 0.0;
+                    const double bx = bw[i].x, by = bw[i].y;
+                    re = fma(ax, bx, fma(ay, by, re));
+                    im = fma(ay, bx, fma(-ax, by, im));
+                }
+            }
+        };
+        // the argmax is re-scored first, its two sums reduced together with
+        // the norms' (one pair of barriers for the four)
+        double re0, im0, s1 = q1, s2 = q2;
+        dot_part(bi, re0, im0);
+        block_sum4<NT>(re0, im0, s1, s2, red);
+        const double n1 = s1 / n, n2 = s2 / n;
+
         ca_result_t res;
         if (!special_case(res, n1, n2, (double)bv)) {
             const double d1 = sqrt((double)bv), d2 = sqrt(fmax((double)cv, 0.0));
@@ -555,30 +585,10 @@ __global__ __launch_bounds__(NT, (blk_waves<T, NT, MMAX>())) void k_align_blk(co
             const double epsD = kErrScale * num<T>::u * lg * (double)M * (double)n * sqrt(n1 * n2) *
                                 (padded ? 1.4142135623730951 : 1.0);
             Pick pk;
+            pk.offer(bi, re0, im0);
             auto rescore_one = [&](int c) {
-                // kRsU node pairs in flight per thread before their products
-                // (indices past n read node 0 and add zero); the terms are
-                // summed in the order k = t, t + NT, ...
-                double re = 0.0, im = 0.0;
-                for (int k0 = 0; k0 < n; k0 += kRsU * NT) {
-                    cpx<T> av[kRsU], bw[kRsU];
-#pragma unroll
-                    for (int i = 0; i < kRsU; ++i) {
-                        const int k = k0 + threadIdx.x + i * NT;
-                        int idx = k - c;
-                        if (idx < 0) idx += n;
-                        av[i] = pa[k < n ? k : 0];
-                        bw[i] = pb[k < n ? idx : 0];
-                    }
-#pragma unroll
-                    for (int i = 0; i < kRsU; ++i) {
-                        const bool in = k0 + threadIdx.x + i * NT < n;
-                        const double ax = in ? (double)av[i].x : 0.0, ay = in ? (double)av[i].y : 0.0;
-                        const double bx = bw[i].x, by = bw[i].y;
-                        re = fma(ax, bx, fma(ay, by, re));
-                        im = fma(ay, bx, fma(-ax, by, im));
-                    }
-                }
+                double re, im;
+                dot_part(c, re, im);
                 block_sum2<NT>(re, im, red);
                 pk.offer(c, re, im);
             };
@@ -589,25 +599,25 @@ __global__ __launch_bounds__(NT, (blk_waves<T, NT, MMAX>())) void k_align_blk(co
                 if (threadIdx.x == 0) clist[0] = 0;
                 __syncthreads();
                 for (int k = threadIdx.x; k < n; k += NT) {
-                    if ((double)norm2(A[base + k]) >= thr2) {
+                    if (k != bi && (double)norm2(A[base + k]) >= thr2) {
                         const int pos = atomicAdd(&clist[0], 1);
                         if (pos < kCandCap) clist[1 + pos] = k;
                     }
                 }
                 __syncthreads();
                 const int cnt = clist[0];
-                if (thr > 0.0 && cnt <= kCandCap) {
+                if (thr > 0.0 && cnt < kCandCap) {
                     for (int c = 0; c < cnt; ++c) rescore_one(clist[1 + c]);
                 } else {
                     capped = true;
                 }
             }
-            if (rescore != CA_RESCORE_WINDOW || capped || pk.count == 0) {
-                rescore_one(bi);
-                if (d1 - d2 < 2.0 * epsD) rescore_one(ci);
-            }
-            const cpx<T> sel = A[base + pk.shift];
-            const double thp = wrap_pi(atan2_fp64(-(double)sel.y, (double)sel.x));
+            if ((rescore != CA_RESCORE_WINDOW || capped) && d1 - d2 < 2.0 * epsD) rescore_one(ci);
+            // theta from the FP64 re-scored C at the chosen shift: an FP32 arc
+            // tangent on the FP32 path, FP64 on the FP64 path
+            double thp;
+            if constexpr (sizeof(T) == 4) thp = (double)wrap_pi(atan2f((float)pk.im, (float)pk.re));
+            else thp = wrap_pi(atan2_fp64(pk.im, pk.re));
             finish(res, pk, n, n1, n2, d1, d2, epsD, capped, thp, theta64);
         }
         if (threadIdx.x == 0) out[pair] = res;

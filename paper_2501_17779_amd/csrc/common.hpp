@@ -174,6 +174,35 @@ template <int NT> __device__ __forceinline__ void block_sum2(double& a, double& 
     a = sa;
     b = sb;
 }
+// Four sums at once (one pair of barriers); scratch holds 4 * (blockDim / 64) doubles.
+template <int NT> __device__ __forceinline__ void block_sum4(double& a, double& b, double& c, double& d,
+                                                            double* scratch) {
+    a = team_sum<64>(a);
+    b = team_sum<64>(b);
+    c = team_sum<64>(c);
+    d = team_sum<64>(d);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        scratch[4 * w] = a;
+        scratch[4 * w + 1] = b;
+        scratch[4 * w + 2] = c;
+        scratch[4 * w + 3] = d;
+    }
+    __syncthreads();
+    double sa = 0.0, sb = 0.0, sc = 0.0, sd = 0.0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) {
+        sa += scratch[4 * k];
+        sb += scratch[4 * k + 1];
+        sc += scratch[4 * k + 2];
+        sd += scratch[4 * k + 3];
+    }
+    a = sa;
+    b = sb;
+    c = sc;
+    d = sd;
+}
 __device__ __forceinline__ int ilog2_ceil(int n) {
     int l = 0;
     while ((1 << l) < n) ++l;

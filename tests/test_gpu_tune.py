@@ -254,7 +254,9 @@ def test_thread_counts_agree(ca, ctx):
         recs[t] = ca.to_numpy(ca.align_batch(r1, r2, offsets=off, ctx=ctx))
     a, b = recs[256], recs[512]
     assert np.array_equal(a["shift"], b["shift"]) and np.array_equal(a["flags"], b["flags"])
-    assert np.array_equal(a["theta"], b["theta"])
+    # theta is an FP32 arc tangent of the FP64 C, whose partial sums the two
+    # thread counts add in different orders: equal to FP32 rounding
+    assert np.all(np.abs(np.angle(np.exp(1j * (a["theta"] - b["theta"])))) <= 1e-6)
     assert np.all(np.abs(a["e0"] - b["e0"]) <= 1e-12 * np.abs(a["e0"]) + 1e-15)
     for i in range(0, 40, 8):
         lo, hi = d["off"][i], d["off"][i + 1]
