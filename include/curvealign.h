@@ -67,9 +67,8 @@ typedef struct {
     uint32_t flags;   /* CA_FLAG_* bits                                              */
     double theta;     /* arg C(s*), radians in (-pi, pi]: the arc tangent of the
                          FP64 re-scored C(s*), taken in FP32 on the FP32 and
-                         split-BF16 n = 128 paths and in FP64 on the FP64 path or
-                         when theta_fp64 is set; split-BF16 n = 1024 takes it in
-                         FP32 from its own C unless theta_fp64 is set                 */
+                         split-BF16 paths and in FP64 on the FP64 path or when
+                         theta_fp64 is set                                             */
     double e0;        /* n1 + n2 - 2|C(s*)|/n with |C(s*)| and n_i in FP64           */
     float err_est;    /* relative half-width of the path's |C| error bound at s*     */
     float gap;        /* (|C|best - |C|runner-up) / |C|best, FP64 values when more

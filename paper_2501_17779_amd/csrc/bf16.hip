@@ -753,16 +753,8 @@ __global__ __launch_bounds__(256, 2) void k_align_bf16_1k(const cf* __restrict__
                 add_run(fs, kFarD + 1, kFarD + 1);
             }
         }
-        // theta from the split-BF16 D at the chosen shift
-        const int s1 = pk.shift & 31, s2 = pk.shift >> 5;
-        const int gsel = 4 * (s2 >> 3) + (s2 & 3), lsel = 32 * ((s2 >> 2) & 1) + s1;
-        float dr = acc[0][0], di = acc[1][0];
-#pragma unroll
-        for (int g = 1; g < 16; ++g)
-            if (g == gsel) { dr = acc[0][g]; di = acc[1][g]; }
-        dr = __shfl(dr, lsel, 64);
-        di = __shfl(di, lsel, 64);
-        const double theta_path = (double)wrap_pi(atan2f(-di, dr));
+        // theta: FP32 arc tangent of the FP64 C at the chosen shift
+        const double theta_path = (double)wrap_pi(atan2f((float)pk.im, (float)pk.re));
         // runner-up |D| for the reported gap when only one shift was evaluated
         finish(res, pk, kB1k, n1, n2, d1, d1, epsD, capped, theta_path, theta64);
         if (l == 0) out[pair] = res;
