@@ -100,7 +100,10 @@ enum { kZPad = 0, kZTwice = 1 };
 // and n2 = (1/n) sum |z2|^2 are formed here: under the top-two rule in the
 // pass that re-scores the best shift, whose FP64 conversions of both curves'
 // nodes they share (n2 then sums curve 2's nodes in the shifted order that
-// pass reads them).
+// pass reads them).  With FUSE2 the window's candidates are re-scored two per
+// pass; with PRUNE (window rule) the argmax and its two neighbours are
+// re-scored in one pass and only the window shifts whose bound can still reach
+// the best value after it.
 // Returns the finished result (every lane).
 template <int N, int T, int ZL = kZPad, bool FUSE2 = false, bool OWN_NORMS = false, bool PRUNE = false>
 __device__ __forceinline__ ca_result_t team_epilogue(const cf (&d)[N / T], const cf (&a0)[N / T],
