@@ -339,8 +339,9 @@ ca_status_t ca_graph_destroy(ca_graph_t graph);
  *                           4096, 8192)                     1..8, or 0 for one block per pair
  *                                                           (default 1)
  *   CA_TUNE_BLOCK_THREADS   size class 3 or 4            1: threads per block of the FP32
- *                                                           class kernel, 256 or 512 (defaults
- *                                                           256 for class 3, 512 for class 4;
+ *                                                           class kernel, 256 or 512, or for
+ *                                                           class 4 also 1024 (defaults 256
+ *                                                           for class 3, 1024 for class 4;
  *                                                           FP64 keeps 256)
  *
  * ca_tune_set and ca_tune_load change the tables the kernels read: they
@@ -358,10 +359,13 @@ enum {
 /*
  * ca_autotune -- measure every candidate of one (knob, key) on a synthetic
  * batch that the library generates on the device (smooth star-shaped curves
- * with rotated, shifted templates; about 2^25 nodes per side), install the
- * fastest and report its time per launch in *best_ms (optional).  Candidates:
+ * with rotated, shifted templates; up to 2^25 nodes per side; the size-class
+ * knobs block_grid and block_threads use a ragged batch of 2^24 nodes whose
+ * curve sizes are spread over every n whose transform falls in the class),
+ * install the fastest and report its time per launch in *best_ms (optional).
+ * Candidates:
  * grid knobs 1, 2, 4 and 0; all-pairs columns 2, 4, 8, 16, 32, 64; threads
- * 256 and 512; radix
+ * 256 and 512 (and 1024 for class 4); radix
  * schedules: the orderings of the power-of-two part as eights, fours,
  * mixed or (M > 2048) sixteens, each with the odd radices first or last.  The first candidate runs
  * for about 20 ms first so that the clock settles; then every candidate is

@@ -441,7 +441,7 @@ template <typename T, int NT, int MMAX> constexpr int blk_waves() {
     if (sizeof(T) == 8) return MMAX >= 4096 ? 1 : 2;
     if (MMAX <= 2048) return 4;
     if (MMAX == 4096) return NT == 512 ? 4 : 3;
-    return NT == 512 ? 2 : 1;
+    return NT == 1024 ? 4 : NT == 512 ? 2 : 1;
 }
 
 template <typename T, int NT, int MMAX>
@@ -649,9 +649,9 @@ static hipError_t launch_blk_class(const BlkArgs& a, int cls, hipStream_t s) {
 }
 
 // Size classes by transform size: (64 threads, M <= 512), (128, <= 1024),
-// (256, <= 2048), (256 or, FP32, 512, <= 4096) and, FP32 only, (512 or 256,
-// <= 8192); the FP32 thread counts of the two large classes are tuning
-// choices.  A uniform batch launches its one class; a ragged batch is
+// (256, <= 2048), (256 or, FP32, 512, <= 4096) and, FP32 only, (1024, 512
+// or 256, <= 8192); the FP32 thread counts of the two large classes are
+// tuning choices.  A uniform batch launches its one class; a ragged batch is
 // binned on the device first.
 template <typename T>
 static hipError_t launch_blk(const BlkArgs& a, hipStream_t s) {
@@ -671,7 +671,9 @@ static hipError_t launch_blk(const BlkArgs& a, hipStream_t s) {
         if (hi > 2048 && lo <= 4096 && e == hipSuccess)
             e = a.threads[3] == 512 ? launch_blk_class<T, 512, 4096>(a, 3, s) : launch_blk_class<T, 256, 4096>(a, 3, s);
         if (hi > 4096 && e == hipSuccess)
-            e = a.threads[4] == 256 ? launch_blk_class<T, 256, 8192>(a, 4, s) : launch_blk_class<T, 512, 8192>(a, 4, s);
+            e = a.threads[4] == 256   ? launch_blk_class<T, 256, 8192>(a, 4, s)
+                : a.threads[4] == 512 ? launch_blk_class<T, 512, 8192>(a, 4, s)
+                                      : launch_blk_class<T, 1024, 8192>(a, 4, s);
     } else {
         if (hi > 2048 && lo <= 4096 && e == hipSuccess) e = launch_blk_class<T, 256, 4096>(a, 3, s);
     }

@@ -28,7 +28,7 @@ struct Tuning {
     int team_grid[kTeamKeys] = {1, 1, 1, 1, 1};       // per log2(n) - 6: occupancy multiples, 0 = one block per group
     int allpairs_cols[kTeamKeys] = {64, 64, 64, 64, 64};
     int blk_grid[kBlkClasses] = {1, 1, 1, 1, 1};
-    int blk_threads[kBlkClasses] = {64, 128, 256, 256, 512};   // classes 3 and 4 (FP32) are tunable
+    int blk_threads[kBlkClasses] = {64, 128, 256, 256, 1024};   // classes 3 and 4 (FP32) are tunable
     std::map<int, std::vector<int>> blk_plan;           // transform size -> radices (absent: default)
     std::map<std::pair<int, int>, float> ms;            // (knob, key) -> measured time of the choice
 };

@@ -33,36 +33,53 @@ __device__ __forceinline__ uint32_t tune_hash(uint32_t a, uint32_t b) {
 __device__ __forceinline__ float tune_unit(uint32_t h) { return (float)(h >> 8) * (1.0f / 16777216.0f); }
 
 // Smooth star-shaped curves r(t) = 1 + sum of three low modes, and templates:
-// curve 1 rotated, cyclically shifted and perturbed by 1e-3 noise.  Pair p,
-// node k: one thread each.
+// curve 1 rotated, cyclically shifted and perturbed by 1e-3 noise.  Node k of
+// pair p (n nodes from index base) sits at index i.
+__device__ __forceinline__ void tune_node(cf* __restrict__ z1, cf* __restrict__ z2, int64_t i, uint32_t p, int k,
+                                          int n, uint32_t seed) {
+    const float two_pi = 6.2831853f;
+    const float ph1 = two_pi * tune_unit(tune_hash(p, seed + 1));
+    const float ph2 = two_pi * tune_unit(tune_hash(p, seed + 2));
+    const float ph3 = two_pi * tune_unit(tune_hash(p, seed + 3));
+    const float rot = two_pi * tune_unit(tune_hash(p, seed + 4));
+    const int shift = (int)(tune_hash(p, seed + 5) % (uint32_t)n);
+    auto node = [&](int j) {
+        const float t = two_pi * (float)j / (float)n;
+        const float r = 1.0f + 0.1f * cosf(3.0f * t + ph1) + 0.05f * cosf(5.0f * t + ph2) +
+                        0.03f * cosf(7.0f * t + ph3);
+        return cf{r * cosf(t), r * sinf(t)};
+    };
+    z1[i] = node(k);
+    if (z2) {
+        int j = k + shift;
+        if (j >= n) j -= n;
+        const cf a = node(j);
+        const float c = cosf(rot), s = sinf(rot);
+        const uint32_t h = tune_hash((uint32_t)i, seed + 6);
+        const float ex = 2e-3f * (tune_unit(h) - 0.5f), ey = 2e-3f * (tune_unit(h * 747796405u + 1u) - 0.5f);
+        z2[i] = cf{c * a.x - s * a.y + ex, s * a.x + c * a.y + ey};
+    }
+}
+
+// A uniform batch: one thread per node.
 __global__ void k_tune_curves(cf* __restrict__ z1, cf* __restrict__ z2, int n, int64_t pairs, uint32_t seed) {
     const int64_t total = pairs * n;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t p = (uint32_t)(i / n);
-        const int k = (int)(i - (int64_t)p * n);
-        const float two_pi = 6.2831853f;
-        const float ph1 = two_pi * tune_unit(tune_hash(p, seed + 1));
-        const float ph2 = two_pi * tune_unit(tune_hash(p, seed + 2));
-        const float ph3 = two_pi * tune_unit(tune_hash(p, seed + 3));
-        const float rot = two_pi * tune_unit(tune_hash(p, seed + 4));
-        const int shift = (int)(tune_hash(p, seed + 5) % (uint32_t)n);
-        auto node = [&](int j) {
-            const float t = two_pi * (float)j / (float)n;
-            const float r = 1.0f + 0.1f * cosf(3.0f * t + ph1) + 0.05f * cosf(5.0f * t + ph2) +
-                            0.03f * cosf(7.0f * t + ph3);
-            return cf{r * cosf(t), r * sinf(t)};
-        };
-        z1[i] = node(k);
-        if (z2) {
-            int j = k + shift;
-            if (j >= n) j -= n;
-            const cf a = node(j);
-            const float c = cosf(rot), s = sinf(rot);
-            const uint32_t h = tune_hash((uint32_t)i, seed + 6);
-            const float ex = 2e-3f * (tune_unit(h) - 0.5f), ey = 2e-3f * (tune_unit(h * 747796405u + 1u) - 0.5f);
-            z2[i] = cf{c * a.x - s * a.y + ex, s * a.x + c * a.y + ey};
-        }
+        tune_node(z1, z2, i, p, (int)(i - (int64_t)p * n), n, seed);
+    }
+}
+
+// A ragged batch (pair p holds nodes offsets[p] .. offsets[p+1]-1): one block
+// per pair, strided over the grid.
+__global__ __launch_bounds__(256) void k_tune_curves_ragged(cf* __restrict__ z1, cf* __restrict__ z2,
+                                                            const int64_t* __restrict__ offsets, int64_t pairs,
+                                                            uint32_t seed) {
+    for (int64_t p = blockIdx.x; p < pairs; p += gridDim.x) {
+        const int64_t base = offsets[p];
+        const int n = (int)(offsets[p + 1] - base);
+        for (int k = threadIdx.x; k < n; k += blockDim.x) tune_node(z1, z2, base + k, (uint32_t)p, k, n, seed);
     }
 }
 
@@ -72,7 +89,7 @@ namespace {
 
 constexpr int kKnobs = 5;
 const char* const kKnobNames[kKnobs] = {"team_grid", "allpairs_cols", "block_plan", "block_grid", "block_threads"};
-const int kDefaultThreads[ca::kBlkClasses] = {64, 128, 256, 256, 512};
+const int kDefaultThreads[ca::kBlkClasses] = {64, 128, 256, 256, 1024};
 const int kTeamSizes[kTeamKeys] = {64, 128, 256, 512, 1024};
 const int kClassMax[ca::kBlkClasses] = {512, 1024, 2048, 4096, 8192};
 
@@ -106,8 +123,8 @@ ca_status_t validate(int knob, int key, const std::vector<int>& v) {
             return CA_OK;
         case CA_TUNE_BLOCK_THREADS:
             if (key != 3 && key != 4) return fail(CA_ERR_INVALID_ARG, "block_threads key must be class 3 or 4");
-            if (v.size() != 1 || (v[0] != 256 && v[0] != 512))
-                return fail(CA_ERR_INVALID_ARG, "block_threads takes one value, 256 or 512");
+            if (v.size() != 1 || (v[0] != 256 && v[0] != 512 && (key != 4 || v[0] != 1024)))
+                return fail(CA_ERR_INVALID_ARG, "block_threads takes one value: 256 or 512, or 1024 for class 4");
             return CA_OK;
         default:
             return fail(CA_ERR_INVALID_ARG, "unknown tuning knob");
@@ -286,14 +303,17 @@ ca_status_t alloc(DevBuf& b, size_t bytes) {
 
 constexpr int64_t kTuneNodes = int64_t(1) << 25;   // nodes per side of a grid / radix sweep
 
-ca::BlkArgs blk_args(ca_context* c, const void* z1, const void* z2, int n, int64_t pairs, ca_result_t* out) {
+// A uniform batch of size n, or (offsets non-NULL) a ragged batch whose
+// transforms are at most m_cap, binned into the workspace `bins`.
+ca::BlkArgs blk_args(ca_context* c, const void* z1, const void* z2, int n, int64_t pairs, ca_result_t* out,
+                     const int64_t* offsets = nullptr, int m_cap = kMaxM, int* bins = nullptr) {
     ca::BlkArgs a;
     a.z1 = z1;
     a.z2 = z2;
-    a.offsets = nullptr;
-    a.n_uniform = n;
-    a.m_uniform = transform_size(n);
-    a.m_cap = kMaxM;
+    a.offsets = offsets;
+    a.n_uniform = offsets ? 0 : n;
+    a.m_uniform = offsets ? 0 : transform_size(n);
+    a.m_cap = m_cap;
     a.num_pairs = pairs;
     a.out = out;
     a.plans = c->d_plans;
@@ -305,8 +325,30 @@ ca::BlkArgs blk_args(ca_context* c, const void* z1, const void* z2, int n, int64
         a.grid_mult[k] = c->tune.blk_grid[k];
         a.threads[k] = c->tune.blk_threads[k];
     }
-    a.bins = nullptr;
+    a.bins = bins;
     return a;
+}
+
+// Pair sizes of a ragged batch for a size-class knob: every curve size whose
+// block-engine transform falls in the class, drawn by a hash of the pair
+// index, until each side holds about `nodes` nodes.
+std::vector<int64_t> class_offsets(int cls, int64_t nodes) {
+    std::vector<int> sizes;
+    const int lo = cls > 0 ? kClassMax[cls - 1] : 0;
+    for (int n = 2; n <= CA_MAX_N; ++n) {
+        const int m = transform_size(n);
+        if (m > lo && m <= kClassMax[cls]) sizes.push_back(n);
+    }
+    std::vector<int64_t> off(1, 0);
+    if (sizes.empty()) return off;
+    for (uint32_t p = 0; off.back() < nodes; ++p) {
+        uint32_t h = (p + 1u) * 0x9E3779B1u;
+        h ^= h >> 15;
+        h *= 0x2C1B3C6Du;
+        h ^= h >> 12;
+        off.push_back(off.back() + sizes[h % (uint32_t)sizes.size()]);
+    }
+    return off;
 }
 
 ca_status_t autotune(ca_context* c, int knob, int key, hipStream_t s, float& best_ms) {
@@ -327,7 +369,8 @@ ca_status_t autotune(ca_context* c, int knob, int key, hipStream_t s, float& bes
             cands = {{1}, {2}, {4}, {0}};
             break;
         case CA_TUNE_BLOCK_THREADS:
-            cands = {{256}, {512}};
+            if (key == 4) cands = {{256}, {512}, {1024}};
+            else cands = {{256}, {512}};
             break;
         case CA_TUNE_ALLPAIRS_COLS:
             cands = {{2}, {4}, {8}, {16}, {32}, {64}};
@@ -336,12 +379,14 @@ ca_status_t autotune(ca_context* c, int knob, int key, hipStream_t s, float& bes
             cands = plan_candidates(key);
             break;
     }
+    // a size-class knob is timed on a ragged batch spread over the class
+    const bool by_class = knob == CA_TUNE_BLOCK_GRID || knob == CA_TUNE_BLOCK_THREADS;
     if (knob == CA_TUNE_TEAM_GRID || knob == CA_TUNE_ALLPAIRS_COLS) n = key;
     else if (knob == CA_TUNE_BLOCK_PLAN) n = representative_n(key);
-    else n = representative_n(kClassMax[key]);      // block_grid, block_threads
+    else n = representative_n(kClassMax[key]);
     if (n == 0) return fail(CA_ERR_UNSUPPORTED_N, "no curve size in [2, 4096] uses this transform size");
 
-    DevBuf z1, z2, out, spec, norms;
+    DevBuf z1, z2, out, spec, norms, offs, bins;
     int64_t pairs = 0;
     int m = 0;
     if (knob == CA_TUNE_ALLPAIRS_COLS) {
@@ -354,6 +399,23 @@ ca_status_t autotune(ca_context* c, int knob, int key, hipStream_t s, float& bes
         if ((st = gen_curves(z1.p, nullptr, n, m, s)) != CA_OK) return st;
         e = ca::launch_spectra(z1.p, m, n, spec.p, (double*)norms.p, team_tw_for(c, n), s);
         if (e != hipSuccess) return hip_fail(e, "spectra kernel launch");
+    } else if (by_class) {
+        const std::vector<int64_t> h_off = class_offsets(key, kTuneNodes / 2);
+        pairs = (int64_t)h_off.size() - 1;
+        const size_t nodes = (size_t)h_off.back();
+        if ((st = alloc(z1, nodes * sizeof(ca::cf))) != CA_OK) return st;
+        if ((st = alloc(z2, nodes * sizeof(ca::cf))) != CA_OK) return st;
+        if ((st = alloc(out, (size_t)pairs * sizeof(ca_result_t))) != CA_OK) return st;
+        if ((st = alloc(offs, h_off.size() * sizeof(int64_t))) != CA_OK) return st;
+        if ((st = alloc(bins, (size_t)ca::blk_bin_ints(pairs) * sizeof(int))) != CA_OK) return st;
+        if ((e = hipMemcpyAsync(offs.p, h_off.data(), h_off.size() * sizeof(int64_t), hipMemcpyHostToDevice, s)) !=
+                hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return hip_fail(e, "autotune offsets upload");
+        const int64_t blocks = std::min<int64_t>(pairs, 65536);
+        hipLaunchKernelGGL(ca::k_tune_curves_ragged, dim3((unsigned)blocks), dim3(256), 0, s, (ca::cf*)z1.p,
+                           (ca::cf*)z2.p, (const int64_t*)offs.p, pairs, 17779u);
+        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "curve generator launch");
     } else {
         pairs = std::max<int64_t>(1, (knob == CA_TUNE_TEAM_GRID ? kTuneNodes : kTuneNodes / 2) / n);
         if ((st = alloc(z1, (size_t)pairs * n * sizeof(ca::cf))) != CA_OK) return st;
@@ -386,7 +448,9 @@ ca_status_t autotune(ca_context* c, int knob, int key, hipStream_t s, float& bes
             const ca_status_t us = upload_block_plans(c, {key});
             if (us != CA_OK) return us;
         }
-        ca::BlkArgs a = blk_args(c, z1.p, z2.p, n, pairs, (ca_result_t*)out.p);
+        ca::BlkArgs a = by_class ? blk_args(c, z1.p, z2.p, 0, pairs, (ca_result_t*)out.p, (const int64_t*)offs.p,
+                                            kClassMax[key], (int*)bins.p)
+                                 : blk_args(c, z1.p, z2.p, n, pairs, (ca_result_t*)out.p);
         if (knob == CA_TUNE_BLOCK_GRID) a.grid_mult[key] = v[0];
         if (knob == CA_TUNE_BLOCK_THREADS) a.threads[key] = v[0];
         auto launch = [&]() { return ca::launch_align_blk_f32(a, s); };

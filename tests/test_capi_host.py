@@ -340,7 +340,7 @@ def test_tuning_file_rejections_on_host(L, tmp_path):
         "plan_r16_small": head % '[{"knob": "block_plan", "key": 1024, "values": [16, 16, 4]}]',
         "plan_key": head % '[{"knob": "block_plan", "key": 4099, "values": [4099]}]',
         "class": head % '[{"knob": "block_grid", "key": 5, "values": [1]}]',
-        "threads": head % '[{"knob": "block_threads", "key": 4, "values": [1024]}]',
+        "threads": head % '[{"knob": "block_threads", "key": 3, "values": [1024]}]',
         "values_type": head % '[{"knob": "block_grid", "key": 1, "values": ["2"]}]',
         "one_bad_of_two": head % ('[{"knob": "block_grid", "key": 1, "values": [2]}, '
                                   '{"knob": "block_grid", "key": 2, "values": [-2]}]'),

@@ -65,7 +65,7 @@ def transform_size(n):
     ("block_grid", 1, {(1,), (2,), (4,), (0,)}),
     ("block_grid", 4, {(1,), (2,), (4,), (0,)}),
     ("block_threads", 3, {(256,), (512,)}),
-    ("block_threads", 4, {(256,), (512,)}),
+    ("block_threads", 4, {(256,), (512,), (1024,)}),
 ])
 def test_autotune_installs_a_candidate(ca, ctx, knob, key, allowed):
     note(f"autotune {knob} key={key}")
@@ -234,8 +234,9 @@ def test_save_load_round_trip(ca, ctx, tmp_path):
 
 
 def test_thread_counts_agree(ca, ctx):
-    """The 256- and 512-thread kernels of classes 3 and 4 run the same
-    butterflies; only the order of the FP64 norm and re-scoring sums differs."""
+    """The 256-, 512- and (class 4) 1024-thread kernels of classes 3 and 4
+    run the same butterflies; only the order of the FP64 norm and re-scoring
+    sums differs."""
     sizes = [2053, 2500, 3001, 3072, 4093, 4096, 2187, 3500]   # padded (class 4) and 7-smooth (class 3)
     z1s, z2s = [], []
     for k, n in enumerate(sizes):
@@ -247,17 +248,19 @@ def test_thread_counts_agree(ca, ctx):
     d = {"z1": np.concatenate(z1s), "z2": np.concatenate(z2s), "off": offs}
     r1, r2, off = gpu(d["z1"]), gpu(d["z2"]), gpu(d["off"])
     recs = {}
-    for t in (256, 512):
-        ca.tune_set("block_threads", 3, t, ctx=ctx)
-        ca.tune_set("block_threads", 4, t, ctx=ctx)
-        note(f"block_threads={t}")
-        recs[t] = ca.to_numpy(ca.align_batch(r1, r2, offsets=off, ctx=ctx))
-    a, b = recs[256], recs[512]
-    assert np.array_equal(a["shift"], b["shift"]) and np.array_equal(a["flags"], b["flags"])
-    # theta is an FP32 arc tangent of the FP64 C, whose partial sums the two
-    # thread counts add in different orders: equal to FP32 rounding
-    assert np.all(np.abs(np.angle(np.exp(1j * (a["theta"] - b["theta"])))) <= 1e-6)
-    assert np.all(np.abs(a["e0"] - b["e0"]) <= 1e-12 * np.abs(a["e0"]) + 1e-15)
+    for t3, t4 in ((256, 256), (512, 512), (512, 1024)):
+        ca.tune_set("block_threads", 3, t3, ctx=ctx)
+        ca.tune_set("block_threads", 4, t4, ctx=ctx)
+        note(f"block_threads={t3},{t4}")
+        recs[t4] = ca.to_numpy(ca.align_batch(r1, r2, offsets=off, ctx=ctx))
+    a = recs[256]
+    for t in (512, 1024):
+        b = recs[t]
+        assert np.array_equal(a["shift"], b["shift"]) and np.array_equal(a["flags"], b["flags"])
+        # theta is an FP32 arc tangent of the FP64 C, whose partial sums the
+        # thread counts add in different orders: equal to FP32 rounding
+        assert np.all(np.abs(np.angle(np.exp(1j * (a["theta"] - b["theta"])))) <= 1e-6)
+        assert np.all(np.abs(a["e0"] - b["e0"]) <= 1e-12 * np.abs(a["e0"]) + 1e-15)
     for i in range(0, 40, 8):
         lo, hi = d["off"][i], d["off"][i + 1]
         acc.check_pair(b[i], d["z1"][lo:hi], d["z2"][lo:hi])
