@@ -402,6 +402,7 @@ ca_status_t autotune(ca_context* c, int knob, int key, hipStream_t s, float& bes
     } else if (by_class) {
         const std::vector<int64_t> h_off = class_offsets(key, kTuneNodes / 2);
         pairs = (int64_t)h_off.size() - 1;
+        if (pairs < 1) return fail(CA_ERR_UNSUPPORTED_N, "no curve size in [2, 4096] falls in this size class");
         const size_t nodes = (size_t)h_off.back();
         if ((st = alloc(z1, nodes * sizeof(ca::cf))) != CA_OK) return st;
         if ((st = alloc(z2, nodes * sizeof(ca::cf))) != CA_OK) return st;
