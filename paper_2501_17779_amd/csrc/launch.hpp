@@ -29,7 +29,7 @@ struct BlkArgs {
     // persistent blocks per CU of each size class, in multiples of the
     // kernel's occupancy limit; 0 = one block per pair
     int grid_mult[kBlkClasses];
-    // threads per block of the FP32 classes 3 and 4 (256 or 512; other
+    // threads per block of the FP32 classes 3 and 4 (256 or 512, or 1024 for class 4; other
     // classes and FP64 use their fixed sizes)
     int threads[kBlkClasses];
     // ragged batches: device workspace of kBlkClasses counters (kBinStride
