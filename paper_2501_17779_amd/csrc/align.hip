@@ -649,6 +649,7 @@ static hipError_t launch_blk_class(const BlkArgs& a, int cls, hipStream_t s) {
 }
 
 // Size classes by transform size: (64 threads, M <= 512), (128, <= 1024),
+// both 256 for batches of at most one pair per CU,
 // (256, <= 2048), (256 or, FP32, 512, <= 4096) and, FP32 only, (1024, 512
 // or 256, <= 8192); the FP32 thread counts of the two large classes are
 // tuning choices.  A uniform batch launches its one class; a ragged batch is
@@ -664,8 +665,14 @@ static hipError_t launch_blk(const BlkArgs& a, hipStream_t s) {
                            a.num_pairs, a.plans, a.m_cap, a.bins, a.out);
         e = hipGetLastError();
     }
-    if (lo <= 512 && e == hipSuccess) e = launch_blk_class<T, 64, 512>(a, 0, s);
-    if (hi > 512 && lo <= 1024 && e == hipSuccess) e = launch_blk_class<T, 128, 1024>(a, 1, s);
+    // a batch that cannot fill the chip runs the two small classes at 256
+    // threads per pair: each pair's butterflies spread over four SIMDs
+    // instead of one or two, which shortens the call (one pair: its latency)
+    const bool few = a.num_pairs <= a.num_cus;
+    if (lo <= 512 && e == hipSuccess)
+        e = few ? launch_blk_class<T, 256, 512>(a, 0, s) : launch_blk_class<T, 64, 512>(a, 0, s);
+    if (hi > 512 && lo <= 1024 && e == hipSuccess)
+        e = few ? launch_blk_class<T, 256, 1024>(a, 1, s) : launch_blk_class<T, 128, 1024>(a, 1, s);
     if (hi > 1024 && lo <= 2048 && e == hipSuccess) e = launch_blk_class<T, 256, 2048>(a, 2, s);
     if constexpr (sizeof(T) == 4) {
         if (hi > 2048 && lo <= 4096 && e == hipSuccess)

@@ -123,6 +123,41 @@ def test_fp64_batch_block_sizes(ca):
                         theta_tol=1e-10, e_rtol=1e-10)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("n", [300, 263, 1000])
+def test_small_batch_kernels_agree(ca, precision, n):
+    """A batch of at most one pair per CU runs size classes 0 and 1 with 256
+    threads per pair; a larger batch with 64 or 128.  The two run the same
+    butterflies; only the order of the FP64 norm and re-scoring sums
+    differs.  n = 300 (class 0), 263 (zero-padded to 540: class 1), 1000
+    (class 1)."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    big = cus + 37
+    z1, z2 = inputs.batch(960 + n, big, n)
+    if precision == "fp64":
+        z1, z2 = z1.astype(np.complex128), z2.astype(np.complex128)
+    note(f"small vs large batch {precision} n={n}: {cus} and {big} pairs")
+    small = ca.to_numpy(ca.align_batch(gpu(z1[:cus]), gpu(z2[:cus]), precision=precision))
+    large = ca.to_numpy(ca.align_batch(gpu(z1), gpu(z2), precision=precision))[:cus]
+    torch.cuda.synchronize()
+    assert np.array_equal(small["shift"], large["shift"])
+    assert np.array_equal(small["flags"], large["flags"])
+    th = 1e-6 if precision == "fp32" else 1e-12
+    assert np.all(np.abs(np.angle(np.exp(1j * (small["theta"] - large["theta"])))) <= th)
+    assert np.all(np.abs(small["e0"] - large["e0"]) <= 1e-12 * np.abs(large["e0"]) + 1e-15)
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    acc.check_batch(small[:16], z1[:16], z2[:16], theta_tol=tol, e_rtol=tol)
+    # ragged: the same pairs, alone and inside a larger ragged batch
+    off = np.arange(0, big + 1, dtype=np.int64) * n
+    rs = ca.to_numpy(ca.align_batch(gpu(z1[:cus].reshape(-1)), gpu(z2[:cus].reshape(-1)),
+                                    offsets=gpu(off[:cus + 1]), precision=precision))
+    rl = ca.to_numpy(ca.align_batch(gpu(z1.reshape(-1)), gpu(z2.reshape(-1)), offsets=gpu(off),
+                                    precision=precision))[:cus]
+    torch.cuda.synchronize()
+    assert np.array_equal(rs["shift"], rl["shift"]) and np.array_equal(rs["flags"], rl["flags"])
+    assert np.array_equal(rs["shift"], small["shift"])
+
+
 def test_ragged_batch(ca):
     d = inputs.ragged(31, 48)
     note(f"ragged align_batch B=48 n in [{d['n'].min()}, {d['n'].max()}]")
