@@ -456,8 +456,17 @@ __global__ __launch_bounds__(NT, (blk_waves<T, NT, MMAX>())) void k_align_blk(co
     constexpr bool kTwLds = MMAX * sizeof(cpx<T>) <= 16384 || blk_waves<T, NT, MMAX>() * 256 / NT <= 1;
     constexpr int HN = MMAX / NT;        // spectrum values of curve 2 held per thread
     constexpr int kRsU = HN < 4 ? HN : 4;  // node pairs per thread in flight in the re-scoring
+    // with at most four transform values per thread (the small-batch kernels
+    // of classes 0 and 1) both curves' nodes are staged in LDS with the
+    // twiddles: every input of a pair is requested at once, and the first
+    // passes and the re-scoring read LDS (a pair's latency sees one global
+    // round trip instead of four)
+    constexpr bool kStageIn = HN <= 4;
+    static_assert(!kStageIn || kTwLds, "staged inputs come with staged twiddles");
     __shared__ cpx<T> A[MMAX];
     __shared__ cpx<T> TWL[kTwLds ? MMAX : 1];
+    __shared__ cpx<T> ZA[kStageIn ? MMAX : 1];
+    __shared__ cpx<T> ZB[kStageIn ? MMAX : 1];
     __shared__ double red[4 * (NT / 64)];
     __shared__ int clist[kCandCap + 1];
     const int64_t todo = list ? (int64_t)*list_count : num_pairs;
@@ -475,7 +484,30 @@ __global__ __launch_bounds__(NT, (blk_waves<T, NT, MMAX>())) void k_align_blk(co
         const int M = plans[n].n;
         const Plan& p = plans[n];
         const cpx<T>* tw = arena + p.tw_off;
-        if constexpr (kTwLds) {
+        const cpx<T>* pa = z1 + off;
+        const cpx<T>* pb = z2 + off;
+        if constexpr (kStageIn) {
+            // HN NT = MMAX covers the M - 1 twiddles and the n <= M nodes
+            cpx<T> tv[HN], va[HN], vb[HN];
+#pragma unroll
+            for (int i = 0; i < HN; ++i) {
+                const int k = threadIdx.x + i * NT;
+                tv[i] = tw[k < M - 1 ? k : 0];
+                va[i] = pa[k < n ? k : 0];
+                vb[i] = pb[k < n ? k : 0];
+            }
+#pragma unroll
+            for (int i = 0; i < HN; ++i) {
+                const int k = threadIdx.x + i * NT;
+                if (k < M - 1) TWL[k] = tv[i];
+                if (k < n) {
+                    ZA[k] = va[i];
+                    ZB[k] = vb[i];
+                }
+            }
+            tw = TWL;
+            __syncthreads();                 // the first passes read ZA and ZB before their barriers
+        } else if constexpr (kTwLds) {
             // four loads in flight per thread, then their stores
             for (int k0 = 0; k0 < M - 1; k0 += 4 * NT) {
                 cpx<T> tv[4];
@@ -492,8 +524,9 @@ __global__ __launch_bounds__(NT, (blk_waves<T, NT, MMAX>())) void k_align_blk(co
             }
             tw = TWL;                        // first read after the barrier of the first pass
         }
-        const cpx<T>* pa = z1 + off;
-        const cpx<T>* pb = z2 + off;
+        // where the first passes and the re-scoring read the nodes
+        const cpx<T>* sa = kStageIn ? ZA : pa;
+        const cpx<T>* sb = kStageIn ? ZB : pb;
         const bool padded = M != n;
         const int base = M - n;              // D index of shift 0
         const int nb = padded ? 2 * n : n;   // extent of b
@@ -503,9 +536,9 @@ __global__ __launch_bounds__(NT, (blk_waves<T, NT, MMAX>())) void k_align_blk(co
         // registers (thread t keeps entries t + NT i), then the spectrum of a
         // takes the buffer and is multiplied in place by conj(.) b, then that
         // product is transformed.  Both first passes read the nodes from
-        // global memory.
+        // global memory (or their LDS copies).
         const double q2 = blk_fft_load<NT, MMAX>(A, p, tw, n, [&](int k) {
-            const cpx<T> x = pb[k < nb ? (k < n ? k : k - n) : 0];
+            const cpx<T> x = sb[k < nb ? (k < n ? k : k - n) : 0];
             return k < nb ? x : zero;
         });
         cpx<T> h[HN];
@@ -515,7 +548,7 @@ __global__ __launch_bounds__(NT, (blk_waves<T, NT, MMAX>())) void k_align_blk(co
             h[i] = k < M ? A[k] : zero;
         }
         const double q1 = blk_fft_load<NT, MMAX>(A, p, tw, n, [&](int k) {
-            const cpx<T> x = pa[k < n ? k : 0];
+            const cpx<T> x = sa[k < n ? k : 0];
             return k < n ? x : zero;
         });
 #pragma unroll
@@ -555,8 +588,8 @@ __global__ __launch_bounds__(NT, (blk_waves<T, NT, MMAX>())) void k_align_blk(co
                     const int k = k0 + threadIdx.x + i * NT;
                     int idx = k - c;
                     if (idx < 0) idx += n;
-                    av[i] = pa[k < n ? k : 0];
-                    bw[i] = pb[k < n ? idx : 0];
+                    av[i] = sa[k < n ? k : 0];
+                    bw[i] = sb[k < n ? idx : 0];
                 }
 #pragma unroll
                 for (int i = 0; i < kRsU; ++i) {
